@@ -1,0 +1,152 @@
+"""Pins of the oracle's density gradients and optimiser."""
+import numpy as np
+
+from oracle import attributes as at
+from oracle import density as den
+from oracle import density_grad as dg
+from oracle import optimizer as opt
+from oracle import poisson
+from oracle.geometry import geometry_of
+from paper_2403_09070_amd import synth
+
+
+def _case(seed=5, **kw):
+    return synth.make_case(config=synth.small_config(**kw), seed=seed)
+
+
+def _energy(c, xyz, geo):
+    rho = den.density_map(c.size, c.kind, xyz, geo)
+    return poisson.energy(rho, poisson.solve(rho, geo, want=("phi",))["phi"], geo)
+
+
+def test_density_adjoint_identity():
+    """<J u, w> = <u, J^T w> with J = d rho / d v taken by central differences."""
+    c = _case(9)
+    geo = geometry_of(c)
+    rng = np.random.default_rng(0)
+    v = c.xyz0.astype(np.float64)
+    u = rng.normal(size=v.shape)
+    u[:, (c.kind & 2) != 0] = 0.0
+    u[2, np.abs(v[2] - geo.dz / 2) < 1e-3] = 0.0      # keep cells off the size switch
+    w = rng.normal(size=(geo.nz, geo.ny, geo.nx))
+    h = 1e-6
+    ju = (den.density_map(c.size, c.kind, v + h * u, geo)
+          - den.density_map(c.size, c.kind, v - h * u, geo)) / (2 * h)
+    lhs = float(np.sum(ju * w))
+    rhs = float(np.sum(u * dg.density_vjp(c.size, c.kind, v, w, geo)))
+    assert abs(lhs - rhs) < 1e-6 * max(1.0, abs(lhs))
+
+
+def test_adjoint_gradient_of_energy_matches_central_differences():
+    c = _case(11)
+    geo = geometry_of(c)
+    v = c.xyz0.astype(np.float64)
+    rho = den.density_map(c.size, c.kind, v, geo)
+    phi = poisson.solve(rho, geo, want=("phi",))["phi"]
+    g = dg.density_vjp(c.size, c.kind, v, phi * geo.vol_bin, geo)
+    rng = np.random.default_rng(3)
+    h = 1e-4 * geo.wb
+    ok = total = 0
+    idx = list(rng.choice(c.meta["n_cells"], size=25, replace=False)) + list(range(c.meta["n_cells"], c.n_inst))
+    for i in idx:
+        for a in range(3):
+            if a == 2 and abs(v[2, i] - geo.dz / 2) < 2 * h:
+                continue
+            up, dn = v.copy(), v.copy()
+            up[a, i] += h
+            dn[a, i] -= h
+            eu, e0, ed = _energy(c, up, geo), _energy(c, v, geo), _energy(c, dn, geo)
+            fd = (eu - ed) / (2 * h)
+            one_sided_gap = abs((eu - e0) / h - (e0 - ed) / h)
+            total += 1
+            if one_sided_gap > 1e-3 * max(1.0, abs(fd)):   # a kink inside the stencil
+                continue
+            assert abs(g[a, i] - fd) < 1e-5 * max(1.0, abs(fd)), (i, a, g[a, i], fd)
+            ok += 1
+    assert ok >= 0.9 * total
+
+
+def test_field_gather_agrees_with_adjoint_and_converges_under_refinement():
+    """The paper's field gather approaches the exact adjoint gradient as bins shrink."""
+    errs = []
+    for n in (16, 32, 64):
+        cfg = synth.small_config(n_cells=200, n_nets=10, die=100.0, nx=n, ny=n, nz=2,
+                                 macros=("uniform", 2, 0.02, 0.04))
+        c = synth.make_case(config=cfg, seed=1)
+        geo = geometry_of(c)
+        v = c.xyz0.astype(np.float64)
+        rho = den.density_map(c.size, c.kind, v, geo)
+        sol = poisson.solve(rho, geo)
+        g_f = dg.field_gather(c.size, c.kind, v, sol["ex"], sol["ey"], sol["ez"], geo)
+        g_a = dg.density_vjp(c.size, c.kind, v, sol["phi"] * geo.vol_bin, geo)
+        assert float(np.sum(g_f[:2] * g_a[:2])) > 0.0
+        errs.append(np.linalg.norm(g_f[:2] - g_a[:2]) / np.linalg.norm(g_a[:2]))
+    assert errs[2] < errs[0]
+
+
+def test_field_gather_mirror_symmetry():
+    """Mirroring the placement in x mirrors the x-gradient and keeps y and z."""
+    c = _case(13)
+    geo = geometry_of(c)
+    v = c.xyz0.astype(np.float64)
+    m = v.copy()
+    m[0] = geo.die_x - v[0]
+    out = []
+    for p in (v, m):
+        rho = den.density_map(c.size, c.kind, p, geo)
+        sol = poisson.solve(rho, geo)
+        out.append(dg.field_gather(c.size, c.kind, p, sol["ex"], sol["ey"], sol["ez"], geo))
+    np.testing.assert_allclose(out[1][0], -out[0][0], atol=1e-9 * np.abs(out[0]).max())
+    np.testing.assert_allclose(out[1][1:], out[0][1:], atol=1e-9 * np.abs(out[0]).max())
+
+
+def test_preconditioner_follows_mixed_size_rule():
+    c = _case(2)
+    pb = opt.problem_of(c)
+    v = c.xyz0.astype(np.float64)
+    w, h = at.instance_size(c.size, c.kind, v[2], pb.geo.dz)
+    q = at.charge(w, h, pb.geo.dz)
+    for lam in (1e-6, 1e-2, 10.0):
+        H = opt.preconditioner(pb, v, lam)
+        mac = (c.kind & 1) != 0
+        np.testing.assert_allclose(H[mac], np.maximum(1.0, pb.npins[mac] + lam * q[mac]))
+        np.testing.assert_allclose(H[~mac], np.maximum(1.0, lam * q[~mac]))
+
+
+def test_nesterov_converges_on_a_convex_quadratic():
+    """With the objective replaced by 1/2 |v - v*|^2 the iterates converge to v*."""
+    rng = np.random.default_rng(0)
+    target = rng.uniform(10, 90, size=(3, 50))
+    v0 = rng.uniform(10, 90, size=(3, 50))
+    movable = np.ones(50, dtype=bool)
+    grad = lambda v: v - target  # noqa: E731
+    st = opt.GPState(u=v0.copy(), v=v0.copy(), v_prev=v0 - 0.01 * grad(v0), g_prev=None, a=1.0, lam=0.0)
+    st.g_prev = grad(st.v_prev)
+    err0 = np.abs(v0 - target).max()
+    for _ in range(60):
+        g = grad(st.v)
+        u, v, a, _ = opt.nesterov_update(st, g, lambda p: p, movable)
+        st.v_prev, st.g_prev, st.u, st.v, st.a = st.v, g, u, v, a
+    assert np.abs(st.u - target).max() < 1e-8 * err0
+
+
+def test_clamp_keeps_instances_inside_region():
+    c = _case(3)
+    pb = opt.problem_of(c)
+    rng = np.random.default_rng(0)
+    v = c.xyz0.astype(np.float64) + rng.normal(scale=60.0, size=c.xyz0.shape)
+    out = opt.clamp(pb, v)
+    w, h = at.instance_size(c.size, c.kind, out[2], pb.geo.dz)
+    mov = pb.movable
+    assert np.all(out[2, mov] >= pb.geo.dz / 4) and np.all(out[2, mov] <= 3 * pb.geo.dz / 4)
+    assert np.all(out[0, mov] - w[mov] / 2 >= -1e-12) and np.all(out[0, mov] + w[mov] / 2 <= pb.geo.die_x + 1e-12)
+    assert np.all(out[1, mov] - h[mov] / 2 >= -1e-12) and np.all(out[1, mov] + h[mov] / 2 <= pb.geo.die_y + 1e-12)
+
+
+def test_gp_reduces_overflow_and_keeps_wirelength_finite():
+    c = synth.make_case("c1")
+    pb = opt.problem_of(c)
+    st = opt.gp_init(pb, c.xyz0)
+    ms = [opt.gp_step(pb, st) for _ in range(8)]
+    assert ms[-1]["ovfl_bot"] < ms[0]["ovfl_bot"] and ms[-1]["ovfl_top"] < ms[0]["ovfl_top"]
+    assert all(np.isfinite(m["hpwl_d2d"]) for m in ms)
