@@ -1,0 +1,215 @@
+/*
+ * place3d.h -- C ABI of the MI355X (gfx950) global-placement hot path of analytical
+ * heterogeneous die-to-die 3D placement (arXiv 2403.09070).
+ *
+ * The library evaluates, for instances placed in the cuboid [0,d_x] x [0,d_y] x [0,d_z] of a
+ * two-die stack, the pieces of the unconstrained objective  sum_e W^_e(v) + lambda U^(v)
+ * (Eq. analytical-placement, Sec. II-A) and takes one preconditioned Nesterov step on it:
+ *
+ *   place3d_density     bin density map                       (Sec. IV-A, Eq. density-map-accum)
+ *   place3d_field       potential and field of the map        (Sec. III-A, Eqs. 3d-poisson-equation
+ *                                                              to possion-sol-force)
+ *   place3d_field_force density-penalty gradient by field gather (Sec. III-A, Sec. IV-A backward)
+ *   place3d_density_vjp exact adjoint of the density map      (differentiation form)
+ *   place3d_wl_grad     bistratal WA wirelength, its gradient and the FDA z-gradient
+ *                                                             (Eqs. wa-model-approx, wl-obj,
+ *                                                              wl-model, fda-grad, fda-normalize;
+ *                                                              Sec. IV-B)
+ *   place3d_step        one GP iteration: all of the above, the mixed-size preconditioner
+ *                       (Eq. improved-precond) and a Nesterov move
+ *
+ * Conventions (all calls):
+ *   - Device pointers unless stated.  Coordinates are instance centres in length units,
+ *     structure-of-arrays float32 [3][n] (x row, y row, z row).  Maps are float32
+ *     [Nz][Ny][Nx], x fastest.  CSR arrays are int32, pins sorted by net,
+ *     net_start[n_nets] == n_pins.
+ *   - The die depth is derived, d_z = N_z (w_b + h_b)/2 with w_b = d_x/N_x, h_b = d_y/N_y
+ *     (Sec. V-A); an instance's centre z decides its die: top iff z > d_z/2.
+ *   - Gradients are d(objective)/d(coordinate), not forces.  Fixed instances get 0.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream) and
+ *     never synchronises, except place3d_create, which reads the netlist back to the host once.
+ *   - The caller owns all device memory (inputs, outputs and the workspace).  The library never
+ *     allocates device memory.  Arrays named in place3d_problem must outlive the context.
+ *   - Return value: PLACE3D_OK (0) or a negative place3d_status.  Argument checks are
+ *     synchronous and run on the host before anything is enqueued; on error nothing is
+ *     enqueued.  place3d_last_error() gives a message.  No C++ exception crosses the ABI.
+ *   - One context must not be used from two host threads at once.  Calls on one context that
+ *     overlap on different streams race on its workspace.
+ */
+#ifndef PLACE3D_H
+#define PLACE3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLACE3D_ABI_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PLACE3D_API __attribute__((visibility("default")))
+#else
+#define PLACE3D_API
+#endif
+
+typedef enum place3d_status {
+  PLACE3D_OK = 0,
+  PLACE3D_ERR_ARG = -1,         /* null or misaligned pointer, bad enum value                */
+  PLACE3D_ERR_SIZE = -2,        /* sizes out of range or inconsistent (grid, CSR, workspace) */
+  PLACE3D_ERR_HIP = -3,         /* a HIP runtime call failed; the HIP code is in last_error  */
+  PLACE3D_ERR_NONFINITE = -4,   /* reserved: a non-finite value seen by a host-visible check */
+  PLACE3D_ERR_UNSUPPORTED = -5, /* valid request this build does not implement               */
+  PLACE3D_ERR_NETLIST = -6      /* CSR not monotone, pin owner out of range, or an instance
+                                   with two pins on one net (the FDA flips whole instances)  */
+} place3d_status;
+
+/* Arithmetic of the spectral contractions (a4, a5). */
+enum { PLACE3D_FP32 = 0,        /* float32 operands on float32 MFMA                          */
+       PLACE3D_BF16X3 = 1 };    /* split hi/lo bfloat16 operands, three products, f32 accum  */
+
+/* Density-penalty gradient used by place3d_step. */
+enum { PLACE3D_DGRAD_FIELD = 0,   /* the paper's field gather: -omega sum_b vol(D∩b) E_b     */
+       PLACE3D_DGRAD_ADJOINT = 1  /* exact adjoint of the density map applied to phi vol(b)  */ };
+
+/* Preconditioner used by place3d_step (Eqs. general-precond and improved-precond). */
+enum { PLACE3D_PRECOND_MIXED = 0,     /* max{1,|E_i|+lambda q_i} macros, max{1,lambda q_i} else */
+       PLACE3D_PRECOND_EPLACE = 1,    /* |E_i| + lambda q_i                                   */
+       PLACE3D_PRECOND_EPLACE3D = 2 };/* lambda q_i                                           */
+
+/* Instance kind bits (uint8 per instance). */
+enum { PLACE3D_KIND_MACRO = 1, PLACE3D_KIND_FIXED = 2 };
+
+/* Layout of the float64 wirelength metrics written by place3d_wl_grad (device, 16 slots). */
+enum {
+  PLACE3D_M_WA_BI = 0,     /* sum_e of the smoothed bistratal wirelength (x + y)            */
+  PLACE3D_M_WA_Z = 1,      /* alpha * sum_e WA p_e(z)                                       */
+  PLACE3D_M_HPWL = 2,      /* sum_e exact bistratal = minimal D2D HPWL, HBT optimally placed */
+  PLACE3D_M_HPWL3D = 3,    /* sum_e p_e(x) + p_e(y) + alpha p_e(z)  (Def. 3d-hpwl)          */
+  PLACE3D_M_NCUT = 4,      /* number of nets with pins on both dies (= #HBT)                */
+  PLACE3D_M_NORM_X = 5,    /* |grad_x W^_Bi|_1 over movable instances                       */
+  PLACE3D_M_NORM_Y = 6,    /* |grad_y W^_Bi|_1                                              */
+  PLACE3D_M_NORM_FDA = 7,  /* |FDA z-gradient|_1 before normalisation                       */
+  PLACE3D_M_FDA_SCALE = 8, /* (NORM_X + NORM_Y) / (2 NORM_FDA), 0 if NORM_FDA == 0          */
+  PLACE3D_NMETRICS = 16
+};
+
+/* Layout of the float64 optimiser scalars in place3d_state.scalars (device, 32 slots). */
+enum {
+  PLACE3D_S_A = 0,         /* Nesterov a_k                                                  */
+  PLACE3D_S_LAMBDA = 1,    /* density weight lambda_k                                       */
+  PLACE3D_S_STEP = 2,      /* step size of the last iteration                               */
+  PLACE3D_S_ITER = 3,      /* iterations taken                                              */
+  PLACE3D_S_OVFL_BOT = 4,  /* per-die overflow at the last evaluation point                 */
+  PLACE3D_S_OVFL_TOP = 5,
+  PLACE3D_S_ENERGY = 6,    /* 1/2 sum_b rho_b phi_b vol(b) (adjoint form only, else 0)      */
+  PLACE3D_S_WL = 8,        /* slots 8..23: the PLACE3D_M_* metrics at the evaluation point  */
+  PLACE3D_NSCALARS = 32
+};
+
+typedef struct place3d_problem {
+  int32_t n_inst;          /* instances: movable cells and macros, fixed instances           */
+  int32_t n_pins;
+  int32_t n_nets;
+  int32_t nx, ny, nz;      /* bin grid; nx, ny in [2, 8192]; nz even, in [2, 16]             */
+  double die_x, die_y;     /* die extent d_x, d_y (> 0)                                      */
+  double gamma;            /* WA smoothing, length units (> 0)                               */
+  double alpha;            /* weight of the cut term alpha p_e(z) (>= 0)                     */
+  double target_density;   /* rho_t of the overflow metric                                    */
+  double lambda_ramp;      /* lambda_{k+1} = lambda_ramp * lambda_k in place3d_step          */
+  int32_t precision;       /* PLACE3D_FP32 or PLACE3D_BF16X3                                 */
+  int32_t dgrad;           /* PLACE3D_DGRAD_FIELD or PLACE3D_DGRAD_ADJOINT                   */
+  int32_t precond;         /* PLACE3D_PRECOND_*                                              */
+  int32_t reserved;
+  /* device arrays, caller-owned, read-only, must outlive the context */
+  const float* size;       /* float32 [4][n_inst]: w_bot, h_bot, w_top, h_top (Eq. std-size-tech) */
+  const uint8_t* kind;     /* uint8 [n_inst], PLACE3D_KIND_* bits                             */
+  const int32_t* net_start;/* int32 [n_nets+1]                                                */
+  const int32_t* pin2node; /* int32 [n_pins], owner instance of each pin                      */
+  const float* pin_off;    /* float32 [4][n_pins]: ox_bot, oy_bot, ox_top, oy_top offsets from
+                              the owner's centre on each die                                  */
+  const float* fixed_xyz;  /* float32 [3][n_inst]: positions used for the fixed instances'
+                              constant density map (built once in place3d_create); entries of
+                              movable instances are ignored                                   */
+} place3d_problem;
+
+typedef struct place3d_state {
+  float* u;        /* float32 [3][n_inst] Nesterov major sequence                            */
+  float* v;        /* float32 [3][n_inst] evaluation point (the placement)                   */
+  float* v_prev;   /* float32 [3][n_inst] previous evaluation point                          */
+  float* g_prev;   /* float32 [3][n_inst] preconditioned gradient at v_prev                  */
+  double* scalars; /* float64 [PLACE3D_NSCALARS], PLACE3D_S_* slots                          */
+} place3d_state;
+
+typedef struct place3d_ctx place3d_ctx;
+
+/* ABI version of the loaded library (PLACE3D_ABI_VERSION it was built with). */
+PLACE3D_API int32_t place3d_abi_version(void);
+
+/* Message of the last error on `ctx` (or of the last failed place3d_create when ctx is NULL).
+ * The string is owned by the library and valid until the next call on the same context. */
+PLACE3D_API const char* place3d_last_error(const place3d_ctx* ctx);
+
+/* Bytes of device workspace a context for `prob` needs (256-byte aligned base required).
+ * Holds the DCT bases, intermediate maps, the fixed-instance map, the static net schedule,
+ * the node->pin CSR, per-pin partial results and reduction slots. */
+PLACE3D_API int32_t place3d_workspace_size(const place3d_problem* prob, size_t* bytes);
+
+/* Validate `prob`, copy the netlist topology to the host once to build the static net
+ * schedule and node->pin CSR, fill the workspace (bases, schedule, fixed-instance density map)
+ * on `stream`, and return a context.  Synchronises `stream`.  `d_workspace` (device, at least
+ * place3d_workspace_size bytes, 256-byte aligned) is owned by the caller and must outlive
+ * the context. */
+PLACE3D_API int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t bytes, void* stream,
+                       place3d_ctx** out);
+
+/* Release the host-side context (device memory stays with the caller).  NULL is a no-op. */
+PLACE3D_API int32_t place3d_destroy(place3d_ctx* ctx);
+
+/* rho[Nz][Ny][Nx] = fixed-instance map + movable instances at `xyz` (Eq. density-map-accum with
+ * the local-smoothness stretch and weight of Sec. IV-A, per-die cell sizes of Eq. std-size-tech
+ * and the macro size transition of Eq. macro-size-tech).  `xyz` float32 [3][n_inst]. */
+PLACE3D_API int32_t place3d_density(place3d_ctx* ctx, const float* xyz, float* rho, void* stream);
+
+/* Potential and field of `rho` on the bin centres (Eqs. poisson-sol-potential and
+ * possion-sol-force, Neumann boundary, zero-mean potential).  Any of phi, ex, ey, ez may be
+ * NULL and its transforms are skipped.  `energy` (device float64, may be NULL) receives
+ * 1/2 sum_b rho_b phi_b vol(b) and needs phi != NULL.  The map operator rho -> phi is
+ * symmetric, so the adjoint of the phi output is the same call. */
+PLACE3D_API int32_t place3d_field(place3d_ctx* ctx, const float* rho, float* phi, float* ex, float* ey,
+                      float* ez, double* energy, void* stream);
+
+/* Density-penalty gradient by the field gather: grad[a][i] (+)= -lambda omega_i
+ * sum_b vol(D_i ∩ b) E_a[b], a = x, y, z.  `accumulate` != 0 adds to grad_xyz. */
+PLACE3D_API int32_t place3d_field_force(place3d_ctx* ctx, const float* xyz, const float* ex, const float* ey,
+                            const float* ez, float lambda, float* grad_xyz, int32_t accumulate,
+                            void* stream);
+
+/* Exact adjoint of place3d_density: grad[a][i] (+)= sum_b g_rho[b] d rho_b / d v_{a,i},
+ * including the z-dependence of the macro size transition. */
+PLACE3D_API int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho,
+                            float* grad_xyz, int32_t accumulate, void* stream);
+
+/* Wirelength model at `xyz`: grad[x], grad[y] (+)= gradient of the smoothed bistratal
+ * wirelength; grad[z] (+)= normalised FDA gradient (Eqs. fda-grad, fda-normalize) plus
+ * alpha d p^_e(z)/dz.  `metrics` (device float64 [PLACE3D_NMETRICS], may be NULL) receives
+ * the PLACE3D_M_* values. */
+PLACE3D_API int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, double* metrics,
+                        int32_t accumulate, void* stream);
+
+/* Start a GP run from `xyz0` (float32 [3][n_inst]): u = v = clamp(xyz0), lambda_0 =
+ * |grad W|_1 / |grad U|_1, the bootstrap point v_prev and its preconditioned gradient g_prev;
+ * a = 1, iteration 0. */
+PLACE3D_API int32_t place3d_gp_init(place3d_ctx* ctx, place3d_state* state, const float* xyz0, void* stream);
+
+/* One GP iteration at state->v: density, field, wirelength, preconditioned gradient, Lipschitz
+ * step, Nesterov move, clamp, lambda *= lambda_ramp; metrics of the evaluation point go to
+ * state->scalars. */
+PLACE3D_API int32_t place3d_step(place3d_ctx* ctx, place3d_state* state, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLACE3D_H */

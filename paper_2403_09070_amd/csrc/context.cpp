@@ -1,0 +1,326 @@
+// Context creation, workspace layout, argument checks and the public C entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using p3d::set_err;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Lane-group class of a net of degree d: groups of 2, 4, ..., 64 lanes; larger nets loop.
+int net_class(int d) {
+  int c = 0;
+  while ((2 << c) < d && c < p3d::kNumClasses - 1) ++c;
+  return c;
+}
+
+int check_problem(const place3d_problem* p, std::string& why) {
+  if (!p) { why = "problem is NULL"; return PLACE3D_ERR_ARG; }
+  if (p->n_inst < 1 || p->n_pins < 0 || p->n_nets < 0) { why = "n_inst < 1 or negative pin/net count"; return PLACE3D_ERR_SIZE; }
+  if (p->nx < 2 || p->ny < 2 || p->nx > 8192 || p->ny > 8192) { why = "nx, ny must lie in [2, 8192]"; return PLACE3D_ERR_SIZE; }
+  if (p->nz < 2 || p->nz > p3d::kMaxNz || (p->nz & 1)) { why = "nz must be even and in [2, 16]"; return PLACE3D_ERR_SIZE; }
+  if (!(p->die_x > 0) || !(p->die_y > 0) || !std::isfinite(p->die_x) || !std::isfinite(p->die_y)) { why = "die extent must be positive"; return PLACE3D_ERR_ARG; }
+  if (!(p->gamma > 0) || !std::isfinite(p->gamma)) { why = "gamma must be positive"; return PLACE3D_ERR_ARG; }
+  if (!(p->alpha >= 0) || !std::isfinite(p->alpha)) { why = "alpha must be >= 0"; return PLACE3D_ERR_ARG; }
+  if (!std::isfinite(p->target_density) || !std::isfinite(p->lambda_ramp)) { why = "non-finite target density or ramp"; return PLACE3D_ERR_ARG; }
+  if (p->precision != PLACE3D_FP32 && p->precision != PLACE3D_BF16X3) { why = "bad precision"; return PLACE3D_ERR_ARG; }
+  if (p->dgrad != PLACE3D_DGRAD_FIELD && p->dgrad != PLACE3D_DGRAD_ADJOINT) { why = "bad dgrad"; return PLACE3D_ERR_ARG; }
+  if (p->precond < PLACE3D_PRECOND_MIXED || p->precond > PLACE3D_PRECOND_EPLACE3D) { why = "bad precond"; return PLACE3D_ERR_ARG; }
+  if (!p->size || !p->kind || !p->net_start || !p->fixed_xyz) { why = "null device array in problem"; return PLACE3D_ERR_ARG; }
+  if (p->n_pins > 0 && (!p->pin2node || !p->pin_off)) { why = "null pin arrays"; return PLACE3D_ERR_ARG; }
+  if ((reinterpret_cast<uintptr_t>(p->size) | reinterpret_cast<uintptr_t>(p->pin_off) |
+       reinterpret_cast<uintptr_t>(p->fixed_xyz) | reinterpret_cast<uintptr_t>(p->net_start) |
+       reinterpret_cast<uintptr_t>(p->pin2node)) & 3) { why = "misaligned device array"; return PLACE3D_ERR_ARG; }
+  return PLACE3D_OK;
+}
+
+size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
+  Carver w{base};
+  const size_t nx = p.nx, ny = p.ny, nz = p.nz, n = p.n_inst, P = p.n_pins, m = p.n_nets;
+  const size_t map = nx * ny * nz;
+  auto& d = c->dct;
+  d.Fx = w.take<float>(nx * nx); d.Gx = w.take<float>(nx * nx); d.Hx = w.take<float>(nx * nx);
+  d.FyT = w.take<float>(ny * ny); d.Gy = w.take<float>(ny * ny); d.Hy = w.take<float>(ny * ny);
+  d.zmat = w.take<float>(4 * p3d::kMaxNz * p3d::kMaxNz);
+  d.inv_w2 = w.take<float>(map);
+  c->map_t = w.take<float>(map); c->map_a = w.take<float>(map);
+  c->map_vg = w.take<float>(map); c->map_vh = w.take<float>(map);
+  c->map_pc = w.take<float>(map); c->map_ps = w.take<float>(map); c->map_qc = w.take<float>(map);
+  c->rho = w.take<float>(map); c->phi = w.take<float>(map);
+  c->ex = w.take<float>(map); c->ey = w.take<float>(map); c->ez = w.take<float>(map);
+  c->fixed_map = w.take<float>(map);
+  c->movable_macros = w.take<int32_t>(n);
+  c->fixed_large = w.take<int32_t>(n);
+  c->npins = w.take<float>(n);
+  c->s_net_start = w.take<int32_t>(m + 1);
+  c->s_pin_node = w.take<int32_t>(P + 1);
+  c->s_off = w.take<float4>(P + 1);
+  c->pin_out = w.take<float4>(P + 1);
+  c->node_slot_start = w.take<int32_t>(n + 1);
+  c->node_slots = w.take<int32_t>(P + 1);
+  c->wl_gzwa = w.take<float>(n);
+  c->gw = w.take<float>(3 * n);
+  c->wl_fda = w.take<float>(n);
+  c->den_grad = w.take<float>(3 * n);
+  c->red = w.take<double>(p3d::R_COUNT);
+  c->red2 = w.take<double>(p3d::R_COUNT);
+  return (w.off + 255) & ~size_t(255);
+}
+
+void fill_geom(place3d_ctx* c) {
+  const place3d_problem& p = c->prob;
+  auto& g = c->g;
+  g.n = p.n_inst; g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+  const double wb = p.die_x / p.nx, hb = p.die_y / p.ny, db = 0.5 * (wb + hb);
+  const double dz = p.nz * db;
+  g.dx = (float)p.die_x; g.dy = (float)p.die_y; g.dz = (float)dz;
+  g.wb = (float)wb; g.hb = (float)hb; g.db = (float)db;
+  g.inv_wb = (float)(1.0 / wb); g.inv_hb = (float)(1.0 / hb); g.inv_db = (float)(1.0 / db);
+  g.half_dz = (float)(0.5 * dz);
+  g.vol_bin = (float)(wb * hb * db);
+}
+
+int build_schedule(place3d_ctx* c, hipStream_t s) {
+  const place3d_problem& p = c->prob;
+  const int n = p.n_inst, P = p.n_pins, m = p.n_nets;
+  std::vector<int32_t> ns(m + 1), p2n(P);
+  std::vector<float> off(4 * (size_t)P);
+  std::vector<uint8_t> kind(n);
+  P3D_HIP(c, hipMemcpyAsync(ns.data(), p.net_start, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, s));
+  if (P > 0) {
+    P3D_HIP(c, hipMemcpyAsync(p2n.data(), p.pin2node, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
+    P3D_HIP(c, hipMemcpyAsync(off.data(), p.pin_off, sizeof(float) * 4 * (size_t)P, hipMemcpyDeviceToHost, s));
+  }
+  P3D_HIP(c, hipMemcpyAsync(kind.data(), p.kind, n, hipMemcpyDeviceToHost, s));
+  P3D_HIP(c, hipStreamSynchronize(s));
+
+  if (ns[0] != 0 || ns[m] != P) return set_err(c, PLACE3D_ERR_NETLIST, "net_start[0] must be 0 and net_start[n_nets] == n_pins");
+  for (int e = 0; e < m; ++e)
+    if (ns[e + 1] < ns[e]) return set_err(c, PLACE3D_ERR_NETLIST, "net_start is not monotone at net " + std::to_string(e));
+  for (int q = 0; q < P; ++q)
+    if (p2n[q] < 0 || p2n[q] >= n) return set_err(c, PLACE3D_ERR_NETLIST, "pin2node out of range at pin " + std::to_string(q));
+  {
+    std::vector<int32_t> tmp;
+    for (int e = 0; e < m; ++e) {
+      tmp.assign(p2n.begin() + ns[e], p2n.begin() + ns[e + 1]);
+      std::sort(tmp.begin(), tmp.end());
+      if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end())
+        return set_err(c, PLACE3D_ERR_NETLIST, "instance with two pins on net " + std::to_string(e));
+    }
+  }
+
+  // nets ordered by lane-group class, stable in net index; empty nets are dropped
+  std::vector<int32_t> order;
+  order.reserve(m);
+  for (int cl = 0; cl < p3d::kNumClasses; ++cl) {
+    c->classes.net_begin[cl] = (int32_t)order.size();
+    for (int e = 0; e < m; ++e) {
+      const int d = ns[e + 1] - ns[e];
+      if (d > 0 && net_class(d) == cl) order.push_back(e);
+    }
+  }
+  c->classes.net_begin[p3d::kNumClasses] = (int32_t)order.size();
+  int nb = 0;
+  for (int cl = 0; cl < p3d::kNumClasses; ++cl) {
+    c->classes.block_begin[cl] = nb;
+    const int per_block = p3d::kWaBlock / (2 << cl);
+    const int cnt = c->classes.net_begin[cl + 1] - c->classes.net_begin[cl];
+    nb += (cnt + per_block - 1) / per_block;
+  }
+  c->classes.block_begin[p3d::kNumClasses] = nb;
+  c->n_wa_blocks = nb;
+
+  const int ms = (int)order.size();
+  std::vector<int32_t> sns(ms + 1), spn(P > 0 ? P : 1), slot_of_pin(P > 0 ? P : 1);
+  std::vector<float> soff(4 * (size_t)(P > 0 ? P : 1));
+  int slot = 0;
+  for (int k = 0; k < ms; ++k) {
+    const int e = order[k];
+    sns[k] = slot;
+    for (int q = ns[e]; q < ns[e + 1]; ++q, ++slot) {
+      spn[slot] = p2n[q];
+      slot_of_pin[q] = slot;
+      soff[4 * (size_t)slot + 0] = off[q];
+      soff[4 * (size_t)slot + 1] = off[(size_t)P + q];
+      soff[4 * (size_t)slot + 2] = off[2 * (size_t)P + q];
+      soff[4 * (size_t)slot + 3] = off[3 * (size_t)P + q];
+    }
+  }
+  sns[ms] = slot;
+
+  // node -> slot CSR, slots ascending per node (fixed summation order)
+  std::vector<int32_t> nss(n + 1, 0), nsl(P > 0 ? P : 1);
+  for (int q = 0; q < P; ++q) nss[p2n[q] + 1]++;
+  for (int i = 0; i < n; ++i) nss[i + 1] += nss[i];
+  {
+    std::vector<int32_t> fill(nss.begin(), nss.end() - 1);
+    for (int sl = 0; sl < slot; ++sl) nsl[fill[spn[sl]]++] = sl;
+  }
+  std::vector<float> npins(n);
+  for (int i = 0; i < n; ++i) npins[i] = (float)(nss[i + 1] - nss[i]);
+
+  std::vector<int32_t> macros, fixed;
+  for (int i = 0; i < n; ++i) {
+    if (kind[i] & PLACE3D_KIND_FIXED) fixed.push_back(i);
+    else if (kind[i] & PLACE3D_KIND_MACRO) macros.push_back(i);
+  }
+  c->n_movable_macros = (int32_t)macros.size();
+  c->n_fixed = (int32_t)fixed.size();
+
+  P3D_HIP(c, hipMemcpyAsync(c->s_net_start, sns.data(), sizeof(int32_t) * (ms + 1), hipMemcpyHostToDevice, s));
+  if (P > 0) {
+    P3D_HIP(c, hipMemcpyAsync(c->s_pin_node, spn.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+    P3D_HIP(c, hipMemcpyAsync(c->s_off, soff.data(), sizeof(float) * 4 * (size_t)P, hipMemcpyHostToDevice, s));
+    P3D_HIP(c, hipMemcpyAsync(c->node_slots, nsl.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+  }
+  P3D_HIP(c, hipMemcpyAsync(c->node_slot_start, nss.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+  P3D_HIP(c, hipMemcpyAsync(c->npins, npins.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+  if (!macros.empty())
+    P3D_HIP(c, hipMemcpyAsync(c->movable_macros, macros.data(), sizeof(int32_t) * macros.size(), hipMemcpyHostToDevice, s));
+  if (!fixed.empty())
+    P3D_HIP(c, hipMemcpyAsync(c->fixed_large, fixed.data(), sizeof(int32_t) * fixed.size(), hipMemcpyHostToDevice, s));
+  P3D_HIP(c, hipStreamSynchronize(s));   // host vectors die at return
+  return PLACE3D_OK;
+}
+
+}  // namespace
+
+namespace p3d {
+int hip_fail(place3d_ctx* c, hipError_t e, const char* where) {
+  std::string msg = std::string("HIP error ") + std::to_string((int)e) + " (" + hipGetErrorString(e) + ") in " + where;
+  if (c) c->err = msg; else g_create_err = msg;
+  return PLACE3D_ERR_HIP;
+}
+}  // namespace p3d
+
+extern "C" {
+
+int32_t place3d_abi_version(void) { return PLACE3D_ABI_VERSION; }
+
+const char* place3d_last_error(const place3d_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int32_t place3d_workspace_size(const place3d_problem* prob, size_t* bytes) {
+  std::string why;
+  int rc = check_problem(prob, why);
+  if (rc != PLACE3D_OK) { g_create_err = why; return rc; }
+  if (!bytes) { g_create_err = "bytes is NULL"; return PLACE3D_ERR_ARG; }
+  place3d_ctx tmp;
+  *bytes = layout(&tmp, *prob, nullptr);
+  return PLACE3D_OK;
+}
+
+int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t bytes, void* stream,
+                       place3d_ctx** out) {
+  std::string why;
+  int rc = check_problem(prob, why);
+  if (rc != PLACE3D_OK) { g_create_err = why; return rc; }
+  if (!out) { g_create_err = "out is NULL"; return PLACE3D_ERR_ARG; }
+  *out = nullptr;
+  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) { g_create_err = "workspace NULL or not 256-byte aligned"; return PLACE3D_ERR_ARG; }
+  place3d_ctx* c = new (std::nothrow) place3d_ctx();
+  if (!c) { g_create_err = "out of host memory"; return PLACE3D_ERR_ARG; }
+  c->prob = *prob;
+  size_t need = layout(c, *prob, reinterpret_cast<char*>(d_workspace));
+  if (bytes < need) {
+    g_create_err = "workspace too small: need " + std::to_string(need) + " bytes";
+    delete c;
+    return PLACE3D_ERR_SIZE;
+  }
+  c->ws = reinterpret_cast<char*>(d_workspace);
+  c->ws_bytes = bytes;
+  fill_geom(c);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  rc = build_schedule(c, s);
+  if (rc == PLACE3D_OK) rc = p3d::build_dct_bases(c, s);
+  if (rc == PLACE3D_OK) rc = p3d::build_fixed_map(c, s);
+  if (rc == PLACE3D_OK) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = p3d::hip_fail(c, e, "hipStreamSynchronize(create)");
+  }
+  if (rc != PLACE3D_OK) {
+    g_create_err = c->err;
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return PLACE3D_OK;
+}
+
+int32_t place3d_destroy(place3d_ctx* ctx) {
+  delete ctx;
+  return PLACE3D_OK;
+}
+
+static int check_ctx(place3d_ctx* ctx) {
+  if (!ctx) { g_create_err = "ctx is NULL"; return PLACE3D_ERR_ARG; }
+  return PLACE3D_OK;
+}
+
+static bool bad_ptr(const void* p) { return !p || (reinterpret_cast<uintptr_t>(p) & 3); }
+
+int32_t place3d_density(place3d_ctx* ctx, const float* xyz, float* rho, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz) || bad_ptr(rho)) return set_err(ctx, PLACE3D_ERR_ARG, "xyz/rho NULL or misaligned");
+  return p3d::density_forward(ctx, xyz, rho, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_field(place3d_ctx* ctx, const float* rho, float* phi, float* ex, float* ey, float* ez,
+                      double* energy, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(rho)) return set_err(ctx, PLACE3D_ERR_ARG, "rho NULL or misaligned");
+  if (energy && !phi) return set_err(ctx, PLACE3D_ERR_ARG, "energy needs phi");
+  for (const void* q : {(const void*)phi, (const void*)ex, (const void*)ey, (const void*)ez})
+    if (q && (reinterpret_cast<uintptr_t>(q) & 3)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned output map");
+  return p3d::spectral_field(ctx, rho, phi, ex, ey, ez, energy, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_field_force(place3d_ctx* ctx, const float* xyz, const float* ex, const float* ey,
+                            const float* ez, float lambda, float* grad_xyz, int32_t accumulate, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz) || bad_ptr(ex) || bad_ptr(ey) || bad_ptr(ez) || bad_ptr(grad_xyz))
+    return set_err(ctx, PLACE3D_ERR_ARG, "NULL or misaligned array");
+  if (!std::isfinite(lambda)) return set_err(ctx, PLACE3D_ERR_ARG, "lambda not finite");
+  return p3d::density_field_gather(ctx, xyz, ex, ey, ez, -lambda, grad_xyz, accumulate != 0,
+                                   reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho, float* grad_xyz,
+                            int32_t accumulate, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz) || bad_ptr(g_rho) || bad_ptr(grad_xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "NULL or misaligned array");
+  return p3d::density_adjoint(ctx, xyz, g_rho, 1.0f, grad_xyz, accumulate != 0, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, double* metrics,
+                        int32_t accumulate, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz) || bad_ptr(grad_xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "NULL or misaligned array");
+  if (metrics && (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned metrics");
+  return p3d::wirelength_eval(ctx, xyz, grad_xyz, accumulate != 0, ctx->red, metrics,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP sources of libplace3d (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/place3d.h"
+
+namespace p3d {
+
+constexpr int kWave = 64;
+constexpr int kMaxNz = 16;
+constexpr int kNumClasses = 6;          // net groups of 2, 4, 8, 16, 32, 64 lanes
+constexpr int kWaBlock = 256;           // threads per wirelength block
+
+// Reduction slots (float64, device) inside the workspace.
+enum RedSlot {
+  R_WA_BI = 0, R_WA_Z, R_HPWL, R_HPWL3D, R_NCUT, R_NORM_X, R_NORM_Y, R_NORM_FDA,
+  R_DV2, R_DG2, R_Q_BOT, R_Q_TOP, R_EXCESS_BOT, R_EXCESS_TOP, R_ENERGY,
+  R_L1_WL, R_L1_DEN, R_GMAX, R_NONFINITE,
+  R_COUNT = 32
+};
+
+struct ClassTab {       // net schedule: nets and workgroups of each lane-group class
+  int32_t net_begin[kNumClasses + 1];
+  int32_t block_begin[kNumClasses + 1];
+};
+
+struct Geom {
+  int n, nx, ny, nz;
+  float dx, dy, dz, wb, hb, db, inv_wb, inv_hb, inv_db, half_dz, vol_bin;
+};
+
+struct DctBases {
+  // float32 [N][N] row-major, see spectral.hip for the definition of each matrix
+  float *Fx, *Gx, *Hx;      // x: forward (sample, freq), inverse cos (freq, sample), inverse sin*omega
+  float *FyT, *Gy, *Hy;     // y: forward^T (freq, sample), inverse cos (sample, freq), inverse sin*omega
+  float* zmat;              // small z matrices, see spectral.hip
+  float* inv_w2;            // [Nz][Ny][Nx] 1/|omega|^2 with the (0,0,0) entry 0
+};
+
+}  // namespace p3d
+
+struct place3d_ctx {
+  place3d_problem prob;
+  p3d::Geom g;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  // spectral
+  p3d::DctBases dct;
+  float *map_t = nullptr, *map_a = nullptr, *map_vg = nullptr, *map_vh = nullptr;
+  float *map_pc = nullptr, *map_ps = nullptr, *map_qc = nullptr;
+  // step scratch maps (rho, phi, ex, ey, ez)
+  float *rho = nullptr, *phi = nullptr, *ex = nullptr, *ey = nullptr, *ez = nullptr;
+  float* fixed_map = nullptr;
+  // instances
+  int32_t* movable_macros = nullptr;   // indices of movable macros
+  int32_t n_movable_macros = 0;
+  int32_t* fixed_large = nullptr;      // fixed instances (their map is built once)
+  int32_t n_fixed = 0;
+  float* npins = nullptr;              // |E_i| as float [n]
+  // wirelength schedule (nets ordered by lane-group class)
+  int32_t* s_net_start = nullptr;      // [n_sched_nets + 1] slot ranges
+  int32_t* s_pin_node = nullptr;       // [n_pins] owner per slot
+  float4* s_off = nullptr;             // [n_pins] (ox_bot, oy_bot, ox_top, oy_top) per slot
+  float4* pin_out = nullptr;           // [n_pins] (gx, gy, gz_wa, fda) per slot
+  int32_t* node_slot_start = nullptr;  // [n+1]
+  int32_t* node_slots = nullptr;       // [n_pins]
+  p3d::ClassTab classes = {};
+  int32_t n_wa_blocks = 0;
+  // per-instance scratch
+  float* wl_gzwa = nullptr;            // [n] alpha d p^(z)/dz per instance
+  float* wl_fda = nullptr;             // [n] FDA z-gradient before normalisation
+  float* gw = nullptr;                 // [3][n] wirelength gradient inside the GP step
+  float* den_grad = nullptr;           // [3][n] density-penalty gradient inside the GP step
+  double* red = nullptr;               // [R_COUNT] reductions
+  double* red2 = nullptr;              // [R_COUNT] second set (init)
+};
+
+namespace p3d {
+
+inline int set_err(place3d_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+int hip_fail(place3d_ctx* c, hipError_t e, const char* where);
+
+#define P3D_HIP(ctx, call)                                                     \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) return p3d::hip_fail((ctx), e_, #call);              \
+  } while (0)
+
+#define P3D_LAUNCH(ctx, what)                                                  \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess) return p3d::hip_fail((ctx), e_, what);               \
+  } while (0)
+
+inline unsigned blocks_for(long long n, int threads) {
+  long long b = (n + threads - 1) / threads;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ---- launchers implemented in the .hip sources (all enqueue only) ----
+int launch_zero_f64(place3d_ctx* c, double* p, int n, hipStream_t s);
+int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t s);
+
+int build_dct_bases(place3d_ctx* c, hipStream_t s);
+int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
+                   double* energy, hipStream_t s);
+
+int build_fixed_map(place3d_ctx* c, hipStream_t s);
+int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s);
+int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey,
+                         const float* ez, float scale, float* grad, int accumulate, hipStream_t s);
+int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad,
+                    int accumulate, hipStream_t s);
+int overflow_reduce(place3d_ctx* c, const float* rho, double* red, hipStream_t s);
+
+int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
+                    double* metrics, hipStream_t s);
+
+}  // namespace p3d

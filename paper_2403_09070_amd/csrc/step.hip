@@ -1,0 +1,299 @@
+// One global-placement iteration: objective gradient, mixed-size preconditioner
+// (Eq. improved-precond; the ePlace and ePlace3D forms of Eq. general-precond as options), the
+// Lipschitz step estimate and the Nesterov move, with the clamp to the movable region.
+//
+// The paper inherits its optimiser from ePlace/DREAMPlace without describing it.  The method
+// implemented: a_0 = 1, a_{k+1} = (1 + sqrt(4 a_k^2 + 1)) / 2,
+//   step = |v_k - v_{k-1}|_2 / |g_k - g_{k-1}|_2   (float64, movable coordinates),
+//   u_{k+1} = clamp(v_k - step g_k),  v_{k+1} = clamp(u_{k+1} + (a_k - 1)/a_{k+1} (u_{k+1} - u_k)),
+// with g the preconditioned gradient, lambda_0 = |grad W|_1 / |grad U|_1 at the start and
+// lambda multiplied by a fixed ratio every step.  Clamp: z to [d_z/4, 3d_z/4], then x and y so
+// that the instance, at the size its clamped z gives, stays inside the die.
+#include <cmath>
+
+#include "internal.h"
+
+namespace p3d {
+namespace {
+
+__device__ __forceinline__ void inst_wh(const Geom& g, const float* __restrict__ size, uint8_t kind, int i, float z,
+                                        float& w, float& h) {
+  const int n = g.n;
+  const float wbot = size[i], hbot = size[n + i], wtop = size[2 * n + i], htop = size[3 * n + i];
+  if (kind & PLACE3D_KIND_MACRO) {
+    const float zc = fminf(fmaxf(z, 0.25f * g.dz), 0.75f * g.dz);
+    const float t = 2.f * zc / g.dz;
+    w = (t - 0.5f) * wtop + (1.5f - t) * wbot;
+    h = (t - 0.5f) * htop + (1.5f - t) * hbot;
+  } else {
+    const bool top = z > g.half_dz;
+    w = top ? wtop : wbot;
+    h = top ? htop : hbot;
+  }
+}
+
+__device__ __forceinline__ void clamp_point(const Geom& g, const float* __restrict__ size, uint8_t kind, int i,
+                                            float& x, float& y, float& z) {
+  z = fminf(fmaxf(z, 0.25f * g.dz), 0.75f * g.dz);
+  float w, h;
+  inst_wh(g, size, kind, i, z, w, h);
+  x = fminf(fmaxf(x, 0.5f * w), g.dx - 0.5f * w);
+  y = fminf(fmaxf(y, 0.5f * h), g.dy - 0.5f * h);
+}
+
+__device__ __forceinline__ float precond(const Geom& g, const float* __restrict__ size, const float* __restrict__ npins,
+                                         uint8_t kind, int i, float z, double lam, int mode) {
+  float w, h;
+  inst_wh(g, size, kind, i, z, w, h);
+  const double lq = lam * (double)w * (double)h * (double)(0.5f * g.dz);
+  double H;
+  if (mode == PLACE3D_PRECOND_MIXED)
+    H = (kind & PLACE3D_KIND_MACRO) ? fmax(1.0, (double)npins[i] + lq) : fmax(1.0, lq);
+  else if (mode == PLACE3D_PRECOND_EPLACE)
+    H = (double)npins[i] + lq;
+  else
+    H = lq;
+  return (float)H;
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_add(double (&v)[NQ], double* __restrict__ out) {
+  __shared__ double sh[NQ][256 / kWave];
+  for (int q = 0; q < NQ; ++q) {
+    double x = v[q];
+    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[q][threadIdx.x / kWave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double x = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) x += sh[threadIdx.x][w];
+    atomicAdd(out + threadIdx.x, x);
+  }
+}
+
+// u = v = clamp(xyz0)
+__global__ void k_clamp_copy(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                             const float* __restrict__ src, float* __restrict__ u, float* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int n = g.n;
+  float x = src[i], y = src[n + i], z = src[2 * n + i];
+  if (!(kind[i] & PLACE3D_KIND_FIXED)) clamp_point(g, size, kind[i], i, x, y, z);
+  u[i] = x; u[n + i] = y; u[2 * n + i] = z;
+  if (v) { v[i] = x; v[n + i] = y; v[2 * n + i] = z; }
+}
+
+// L1 norms of the wirelength and density gradients over movable instances -> lambda_0
+__global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float* __restrict__ gw,
+                           const float* __restrict__ gd, double* __restrict__ red) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  double v[2] = {0.0, 0.0};
+  if (i < n && !(kind[i] & PLACE3D_KIND_FIXED)) {
+    for (int a = 0; a < 3; ++a) {
+      v[0] += fabs((double)gw[a * n + i]);
+      v[1] += fabs((double)gd[a * n + i]);
+    }
+  }
+  block_add<2>(v, red + R_L1_WL);
+}
+
+// g = (gw + lambda gd) / H.  Mode 0 (init): write g to `gout` and track max|g|.  Mode 1 (step):
+// accumulate |v - v_prev|^2 and |g - g_prev|^2, store g over g_prev, and the movable charge
+// per die (overflow denominators).
+__global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                          const float* __restrict__ npins, const float* __restrict__ v,
+                          const float* __restrict__ v_prev, const float* __restrict__ gw,
+                          const float* __restrict__ gd, const double* __restrict__ lam_ptr, int lam_slot,
+                          int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ red) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  const double lam = lam_ptr[lam_slot];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n) {
+    const uint8_t k = kind[i];
+    float gv[3] = {0.f, 0.f, 0.f};
+    const float z = v[2 * n + i];
+    if (!(k & PLACE3D_KIND_FIXED)) {
+      const float H = precond(g, size, npins, k, i, z, lam, mode_pre);
+      for (int a = 0; a < 3; ++a)
+        gv[a] = (float)(((double)gw[a * n + i] + lam * (double)gd[a * n + i]) / (double)H);
+      if (mode == 1) {
+        for (int a = 0; a < 3; ++a) {
+          const double dv = (double)v[a * n + i] - (double)v_prev[a * n + i];
+          const double dg = (double)gv[a] - (double)gout[a * n + i];
+          acc[0] += dv * dv;
+          acc[1] += dg * dg;
+        }
+        float w, h;
+        inst_wh(g, size, k, i, z, w, h);
+        const double q = (double)w * (double)h * (double)(0.5f * g.dz);
+        if (z > g.half_dz) acc[3] += q; else acc[2] += q;
+      } else {
+        acc[0] = fmax(fmax(fabs((double)gv[0]), fabs((double)gv[1])), fabs((double)gv[2]));
+      }
+    }
+    for (int a = 0; a < 3; ++a) gout[a * n + i] = gv[a];
+  }
+  if (mode == 1) {
+    block_add<4>(acc, red + R_DV2);   // R_DV2, R_DG2, R_Q_BOT, R_Q_TOP
+  } else {
+    // max |g| via unsigned compare of non-negative float64 bit patterns
+    double m = acc[0];
+    for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & (kWave - 1)) == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(red + R_GMAX), (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// v_prev = clamp(v - 0.01 w_b g / max|g|)
+__global__ void k_bootstrap(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                            const float* __restrict__ v, const float* __restrict__ g0, const double* __restrict__ red,
+                            float* __restrict__ v_prev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int n = g.n;
+  const double gmax = red[R_GMAX];
+  const float f = gmax > 0.0 ? (float)(0.01 * (double)g.wb / gmax) : 0.f;
+  float x = v[i], y = v[n + i], z = v[2 * n + i];
+  if (!(kind[i] & PLACE3D_KIND_FIXED)) {
+    x -= f * g0[i]; y -= f * g0[n + i]; z -= f * g0[2 * n + i];
+    clamp_point(g, size, kind[i], i, x, y, z);
+  }
+  v_prev[i] = x; v_prev[n + i] = y; v_prev[2 * n + i] = z;
+}
+
+__global__ void k_init_scalars(double* __restrict__ sc, const double* __restrict__ red) {
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < PLACE3D_NSCALARS; ++q) sc[q] = 0.0;
+  sc[PLACE3D_S_A] = 1.0;
+  sc[PLACE3D_S_LAMBDA] = red[R_L1_DEN] > 0.0 ? red[R_L1_WL] / red[R_L1_DEN] : 0.0;
+}
+
+// the Nesterov move; g (the new preconditioned gradient) sits in g_prev
+__global__ void k_nesterov(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                           const double* __restrict__ sc, const double* __restrict__ red, float* __restrict__ u,
+                           float* __restrict__ v, float* __restrict__ v_prev, const float* __restrict__ gk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const int n = g.n;
+  const double dv2 = red[R_DV2], dg2 = red[R_DG2];
+  const double step = dg2 > 0.0 ? sqrt(dv2 / dg2) : 0.0;
+  const double a = sc[PLACE3D_S_A];
+  const double a1 = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
+  const float coef = (float)((a - 1.0) / a1);
+  const float st = (float)step;
+  const float vx = v[i], vy = v[n + i], vz = v[2 * n + i];
+  v_prev[i] = vx; v_prev[n + i] = vy; v_prev[2 * n + i] = vz;
+  if (kind[i] & PLACE3D_KIND_FIXED) return;
+  float ux = vx - st * gk[i], uy = vy - st * gk[n + i], uz = vz - st * gk[2 * n + i];
+  clamp_point(g, size, kind[i], i, ux, uy, uz);
+  float nx = ux + coef * (ux - u[i]), ny = uy + coef * (uy - u[n + i]), nz = uz + coef * (uz - u[2 * n + i]);
+  clamp_point(g, size, kind[i], i, nx, ny, nz);
+  u[i] = ux; u[n + i] = uy; u[2 * n + i] = uz;
+  v[i] = nx; v[n + i] = ny; v[2 * n + i] = nz;
+}
+
+__global__ void k_step_finish(double* __restrict__ sc, const double* __restrict__ red, double ramp) {
+  if (threadIdx.x != 0) return;
+  const double dv2 = red[R_DV2], dg2 = red[R_DG2];
+  const double a = sc[PLACE3D_S_A];
+  sc[PLACE3D_S_STEP] = dg2 > 0.0 ? sqrt(dv2 / dg2) : 0.0;
+  sc[PLACE3D_S_A] = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
+  sc[PLACE3D_S_LAMBDA] *= ramp;
+  sc[PLACE3D_S_ITER] += 1.0;
+  sc[PLACE3D_S_OVFL_BOT] = red[R_Q_BOT] > 0.0 ? red[R_EXCESS_BOT] / red[R_Q_BOT] : 0.0;
+  sc[PLACE3D_S_OVFL_TOP] = red[R_Q_TOP] > 0.0 ? red[R_EXCESS_TOP] / red[R_Q_TOP] : 0.0;
+  sc[PLACE3D_S_ENERGY] = red[R_ENERGY];
+  for (int q = 0; q <= PLACE3D_M_NORM_FDA; ++q) sc[PLACE3D_S_WL + q] = red[R_WA_BI + q];
+  const double nf = red[R_NORM_FDA];
+  sc[PLACE3D_S_WL + PLACE3D_M_FDA_SCALE] = nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
+}
+
+// wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red
+int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s) {
+  int rc;
+  if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, s))) return rc;
+  if ((rc = density_forward(c, xyz, c->rho, s))) return rc;
+  if ((rc = overflow_reduce(c, c->rho, red, s))) return rc;
+  if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
+    if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;
+    if ((rc = density_field_gather(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s))) return rc;
+  } else {
+    if ((rc = spectral_field(c, c->rho, c->phi, nullptr, nullptr, nullptr, red + R_ENERGY, s))) return rc;
+    if ((rc = density_adjoint(c, xyz, c->phi, c->g.vol_bin, gd, 0, s))) return rc;
+  }
+  return PLACE3D_OK;
+}
+
+int check_state(place3d_ctx* c, const place3d_state* st) {
+  if (!st || !st->u || !st->v || !st->v_prev || !st->g_prev || !st->scalars)
+    return set_err(c, PLACE3D_ERR_ARG, "state has a NULL array");
+  if ((reinterpret_cast<uintptr_t>(st->u) | reinterpret_cast<uintptr_t>(st->v) |
+       reinterpret_cast<uintptr_t>(st->v_prev) | reinterpret_cast<uintptr_t>(st->g_prev)) & 3 ||
+      (reinterpret_cast<uintptr_t>(st->scalars) & 7))
+    return set_err(c, PLACE3D_ERR_ARG, "misaligned state array");
+  return PLACE3D_OK;
+}
+
+}  // namespace
+}  // namespace p3d
+
+using namespace p3d;
+
+extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const float* xyz0, void* stream) {
+  if (!c) return PLACE3D_ERR_ARG;
+  if (int rc = check_state(c, st)) return rc;
+  if (!xyz0 || (reinterpret_cast<uintptr_t>(xyz0) & 3)) return set_err(c, PLACE3D_ERR_ARG, "xyz0 NULL or misaligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Geom& g = c->g;
+  const place3d_problem& p = c->prob;
+  const unsigned nb = blocks_for(g.n, 256);
+  int rc;
+  hipLaunchKernelGGL(k_clamp_copy, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, xyz0, st->u, st->v);
+  P3D_LAUNCH(c, "k_clamp_copy");
+  // gradients at v0, lambda_0
+  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
+  if ((rc = launch_zero_f64(c, c->red2, R_COUNT, s))) return rc;
+  hipLaunchKernelGGL(k_l1_parts, dim3(nb), dim3(256), 0, s, g, p.kind, c->gw, c->den_grad, c->red2);
+  P3D_LAUNCH(c, "k_l1_parts");
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, st->scalars, c->red2);
+  P3D_LAUNCH(c, "k_init_scalars");
+  // g0 (into g_prev as scratch) and max|g0|
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
+                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
+                     c->red2);
+  P3D_LAUNCH(c, "k_combine(init)");
+  hipLaunchKernelGGL(k_bootstrap, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->v, st->g_prev, c->red2,
+                     st->v_prev);
+  P3D_LAUNCH(c, "k_bootstrap");
+  // preconditioned gradient at v_prev
+  if ((rc = eval_parts(c, st->v_prev, c->gw, c->den_grad, c->red, s))) return rc;
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v_prev, st->v_prev,
+                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
+                     c->red2);
+  P3D_LAUNCH(c, "k_combine(init2)");
+  return PLACE3D_OK;
+}
+
+extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream) {
+  if (!c) return PLACE3D_ERR_ARG;
+  if (int rc = check_state(c, st)) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Geom& g = c->g;
+  const place3d_problem& p = c->prob;
+  const unsigned nb = blocks_for(g.n, 256);
+  int rc;
+  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
+                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 1, st->g_prev,
+                     c->red);
+  P3D_LAUNCH(c, "k_combine");
+  hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, st->u, st->v,
+                     st->v_prev, st->g_prev);
+  P3D_LAUNCH(c, "k_nesterov");
+  hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, s, st->scalars, c->red, p.lambda_ramp);
+  P3D_LAUNCH(c, "k_step_finish");
+  return PLACE3D_OK;
+}

@@ -1,0 +1,78 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry point, and rejects
+bad arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "place3d.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2403_09070_amd import place3d
+    if not os.path.exists(place3d.LIB_PATH):
+        from paper_2403_09070_amd import build
+        build.build()
+    return place3d.lib()
+
+
+def declared():
+    return re.findall(r"PLACE3D_API\s+[\w\s\*]+?\b(place3d_\w+)\s*\(", open(HEADER).read())
+
+
+def test_header_declares_the_hot_path_calls():
+    names = set(declared())
+    for n in ("place3d_density", "place3d_field", "place3d_wl_grad", "place3d_step", "place3d_create",
+              "place3d_workspace_size", "place3d_density_vjp", "place3d_field_force", "place3d_gp_init"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for n in declared():
+        assert hasattr(L, n), n
+    assert L.place3d_abi_version() == 1
+
+
+def _problem(**kw):
+    from paper_2403_09070_amd.place3d import Problem_
+    p = Problem_(100, 10, 5, 16, 16, 2, 10.0, 10.0, 1.0, 0.5, 1.0, 1.05, 0, 0, 0, 0, 16, 32, 48, 64, 80, 96)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nx", 1, -2), ("ny", 9000, -2), ("nz", 3, -2), ("nz", 18, -2), ("n_inst", 0, -2),
+    ("gamma", 0.0, -1), ("die_x", -1.0, -1), ("precision", 7, -1), ("dgrad", 5, -1), ("precond", 9, -1),
+    ("alpha", -1.0, -1), ("size", 0, -1), ("pin_off", 18, -1),
+])
+def test_workspace_size_rejects_bad_problems(L, field, value, code):
+    n = ctypes.c_size_t()
+    p = _problem(**{field: value})
+    assert L.place3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == code
+    assert L.place3d_last_error(None)
+
+
+def test_workspace_size_accepts_a_valid_problem_and_grows_with_the_grid(L):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.place3d_workspace_size(ctypes.byref(_problem()), ctypes.byref(a)) == 0
+    assert L.place3d_workspace_size(ctypes.byref(_problem(nx=64, ny=64)), ctypes.byref(b)) == 0
+    assert b.value > a.value > 0 and a.value % 256 == 0
+
+
+def test_create_rejects_null_or_misaligned_workspace_without_a_device_call(L):
+    out = ctypes.c_void_p()
+    p = _problem()
+    assert L.place3d_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(out)) == -1
+    assert L.place3d_create(ctypes.byref(p), ctypes.c_void_p(4096 + 8), 1 << 20, None, ctypes.byref(out)) == -1
+    assert L.place3d_create(ctypes.byref(p), ctypes.c_void_p(4096), 16, None, ctypes.byref(out)) == -2
+    assert out.value is None
+
+
+def test_calls_reject_a_null_context(L):
+    assert L.place3d_density(None, None, None, None) == -1
+    assert L.place3d_step(None, None, None) == -1
+    assert L.place3d_destroy(None) == 0

@@ -1,0 +1,127 @@
+"""GPU-vs-oracle parity of every hot-path call through the C ABI.
+
+Inputs are the seeded synthetic cases; where a stage is compared in isolation, the oracle is fed
+the same float32 input the GPU stage received (e.g. the GPU density map for the field), so the
+comparison measures that stage's arithmetic only.  Tolerances:
+  density map        rel L2 <= 1e-6, total volume rel <= 1e-6   (float32 sums of <= 27 terms)
+  field phi, E       rel L2 <= 1e-4                            (float32 and split-bf16 MFMA)
+  wirelength totals  rel <= 1e-5
+  WA x/y gradient    rel L2 <= 1e-5
+  FDA z-gradient     per instance |diff| <= (4/d_z) * npins_i * 8 ulp(d_x)
+  density gradients  rel L2 <= 1e-5 given the same maps
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_problem, log, need_gpu, oracle_problem, ragged_case, rel_l2, tiny_case
+from oracle import density as oden
+from oracle import density_grad as odg
+from oracle import poisson as opois
+from oracle import wirelength as owl
+from oracle.geometry import geometry_of
+from paper_2403_09070_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "tiny": lambda: tiny_case(5),
+    "ragged": lambda: ragged_case(6),
+    "c1": lambda: synth.make_case("c1", 2403),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def setup(request):
+    need_gpu()
+    import torch
+    log(f"[parity] case {request.param}")
+    case = CASES[request.param]()
+    prob = gpu_problem(case)
+    torch.cuda.synchronize()
+    return request.param, case, prob
+
+
+def test_density_map(setup):
+    name, case, prob = setup
+    geo = geometry_of(case)
+    rho = prob.density(case.xyz0).cpu().numpy()
+    ref = oden.density_map(case.size, case.kind, case.xyz0, geo)
+    err = rel_l2(rho, ref)
+    log(f"[parity] {name} density rel_l2={err:.3e}")
+    assert err <= 1e-6
+    assert abs(rho.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_field(setup, precision):
+    name, case, prob = setup
+    from paper_2403_09070_amd import place3d
+    if precision == "bf16x3":
+        prob = gpu_problem(case, precision=place3d.BF16X3)
+    geo = geometry_of(case)
+    rho = prob.density(case.xyz0)
+    out = prob.field(rho, energy=True)
+    rho64 = rho.cpu().numpy().astype(np.float64)
+    ref = opois.solve(rho64, geo)
+    for k in ("phi", "ex", "ey", "ez"):
+        err = rel_l2(out[k].cpu().numpy(), ref[k])
+        log(f"[parity] {name} {precision} {k} rel_l2={err:.3e}")
+        assert err <= 1e-4, k
+    e_ref = opois.energy(rho64, ref["phi"], geo)
+    assert abs(float(out["energy"].cpu()[0]) - e_ref) <= 1e-4 * abs(e_ref)
+
+
+def test_wirelength(setup):
+    name, case, prob = setup
+    geo = geometry_of(case)
+    pb = oracle_problem(case)
+    g, met = prob.wl_grad(case.xyz0)
+    g = g.cpu().numpy()
+    met = met.cpu().numpy()
+    ref = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+    for key, slot in (("wa_bi", 0), ("wa_z", 1), ("hpwl_d2d", 2), ("hpwl_3d", 3)):
+        err = abs(met[slot] - ref[key]) / max(abs(ref[key]), 1e-30)
+        log(f"[parity] {name} {key} gpu={met[slot]:.9g} ref={ref[key]:.9g} rel={err:.2e}")
+        assert err <= 1e-5, key
+    assert int(round(met[4])) == ref["ncut"]
+    ex, ey = rel_l2(g[0], ref["grad_x"]), rel_l2(g[1], ref["grad_y"])
+    log(f"[parity] {name} wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
+    assert ex <= 1e-5 and ey <= 1e-5
+    # z: normalised FDA plus the WA cut term.  The FDA differences are exact up to the rounding
+    # of pin coordinates: a few ulp of the die size per net of the instance.
+    scale = met[8]
+    assert abs(scale - ref["fda_scale"]) <= 1e-5 * ref["fda_scale"]
+    ulp = float(np.spacing(np.float32(geo.die_x)))
+    npins = np.bincount(case.pin2node, minlength=case.n_inst)
+    want = scale * ref["fda"] + ref["grad_zwa"]
+    bound = scale * 4.0 / geo.dz * npins * 8 * ulp + 1e-5 * np.abs(ref["grad_zwa"]).max() + 1e-6 * np.abs(want)
+    diff = np.abs(g[2] - want)
+    log(f"[parity] {name} z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e} "
+        f"rel_l2={rel_l2(g[2], ref['grad'][2]):.3e}")
+    assert np.all(diff <= bound)
+
+
+def test_field_gather(setup):
+    name, case, prob = setup
+    geo = geometry_of(case)
+    rho = prob.density(case.xyz0)
+    f = prob.field(rho, want=("ex", "ey", "ez"))
+    g = prob.field_force(case.xyz0, f["ex"], f["ey"], f["ez"], lam=1.0).cpu().numpy()
+    ref = odg.field_gather(case.size, case.kind, case.xyz0, *(f[k].cpu().numpy().astype(np.float64)
+                                                               for k in ("ex", "ey", "ez")), geo)
+    err = rel_l2(g, ref)
+    log(f"[parity] {name} field-gather rel_l2={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_density_vjp(setup):
+    name, case, prob = setup
+    import torch
+    geo = geometry_of(case)
+    rng = np.random.default_rng(0)
+    gmap = rng.normal(size=(case.nz, case.ny, case.nx)).astype(np.float32)
+    g = prob.density_vjp(case.xyz0, torch.from_numpy(gmap).cuda()).cpu().numpy()
+    ref = odg.density_vjp(case.size, case.kind, case.xyz0, gmap.astype(np.float64), geo)
+    err = rel_l2(g, ref)
+    log(f"[parity] {name} density-vjp rel_l2={err:.3e}")
+    assert err <= 1e-5

@@ -1,0 +1,113 @@
+"""GP initialisation and Nesterov steps: GPU (C ABI) against the oracle's GP loop.
+
+* gp_init: lambda_0 and the bootstrap point agree with the oracle's.
+* One step from the same state (the oracle's state rounded to float32 on both sides): the
+  metrics at the evaluation point and the new iterate agree.  The step size divides by
+  |g_k - g_{k-1}|, which amplifies the float32 rounding of the gradient by |g| / |g_k - g_{k-1}|,
+  so the displacement is compared at 1e-3 relative (measured well below).
+* A short trajectory: the D2D HPWL of GPU and oracle stay within 1e-3 of each other.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import gpu_problem, log, need_gpu, oracle_problem, rel_l2, tiny_case
+from oracle import optimizer as opt
+from paper_2403_09070_amd import place3d, synth
+
+pytestmark = pytest.mark.gpu
+
+FORMS = {
+    "field-fp32": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.FP32),
+    "adjoint-bf16x3": dict(dgrad=place3d.DGRAD_ADJOINT, precision=place3d.BF16X3),
+}
+
+
+def _oracle_form(form):
+    return "field" if FORMS[form]["dgrad"] == place3d.DGRAD_FIELD else "adjoint"
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_gp_init(which, form):
+    need_gpu()
+    log(f"[step] init {which} {form}")
+    case = tiny_case(5) if which == "tiny" else synth.make_case("c1", 2403)
+    prob = gpu_problem(case, **FORMS[form])
+    pb = oracle_problem(case)
+    st = prob.gp_init(case.xyz0)
+    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form))
+    s = st.read()
+    log(f"[step] lambda0 gpu={s['lam']:.9g} ref={ref.lam:.9g}")
+    assert abs(s["lam"] - ref.lam) <= 1e-5 * ref.lam
+    assert rel_l2(st.v.cpu().numpy(), ref.v) <= 1e-7
+    assert rel_l2(st.v_prev.cpu().numpy(), ref.v_prev) <= 1e-6
+    err = rel_l2(st.g_prev.cpu().numpy(), ref.g_prev)
+    log(f"[step] g_prev rel_l2={err:.3e}")
+    assert err <= 1e-4
+
+
+def _load_state(prob, ref):
+    st = prob.new_state()
+    for name in ("u", "v", "v_prev", "g_prev"):
+        getattr(st, name).copy_(torch.from_numpy(np.asarray(getattr(ref, name), dtype=np.float32)))
+    sc = np.zeros(place3d.NSCALARS)
+    sc[place3d.S["a"]] = ref.a
+    sc[place3d.S["lam"]] = ref.lam
+    st.scalars.copy_(torch.from_numpy(sc))
+    return st
+
+
+def _round_state(ref):
+    for name in ("u", "v", "v_prev", "g_prev"):
+        setattr(ref, name, np.asarray(getattr(ref, name), dtype=np.float32).astype(np.float64))
+    return ref
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_one_step_from_the_same_state(form):
+    need_gpu()
+    log(f"[step] one step c1 {form}")
+    case = synth.make_case("c1", 2403)
+    prob = gpu_problem(case, **FORMS[form])
+    pb = oracle_problem(case)
+    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form))
+    for _ in range(3):                                   # move away from the bootstrap point
+        opt.gp_step(pb, ref, dgrad=_oracle_form(form))
+    ref = _round_state(ref)
+    st = _load_state(prob, ref)
+    v0 = ref.v.copy()
+    prob.step(st)
+    m = opt.gp_step(pb, ref, dgrad=_oracle_form(form))
+    s = st.read()
+    for key, rkey in (("hpwl", "hpwl_d2d"), ("wa_bi", "wa_bi"), ("wa_z", "wa_z")):
+        assert abs(s[key] - m[rkey]) <= 1e-5 * abs(m[rkey]), key
+    assert s["ncut"] == m["ncut"]
+    assert abs(s["ovfl_bot"] - m["ovfl_bot"]) <= 1e-6 and abs(s["ovfl_top"] - m["ovfl_top"]) <= 1e-6
+    assert abs(s["lam"] - ref.lam) <= 1e-12 * ref.lam
+    step_err = abs(s["step"] - m["step"]) / m["step"]
+    disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
+    log(f"[step] {form} step rel={step_err:.3e} displacement rel_l2={disp:.3e}")
+    assert step_err <= 1e-3 and disp <= 1e-3
+    if FORMS[form]["dgrad"] == place3d.DGRAD_ADJOINT:
+        assert abs(s["energy"] - m["energy"]) <= 1e-4 * abs(m["energy"])
+
+
+def test_short_trajectory_tracks_the_oracle():
+    need_gpu()
+    log("[step] 20-step trajectory c1")
+    case = synth.make_case("c1", 2403)
+    prob = gpu_problem(case)
+    pb = oracle_problem(case)
+    st = prob.gp_init(case.xyz0)
+    ref = opt.gp_init(pb, case.xyz0)
+    worst = 0.0
+    for k in range(20):
+        prob.step(st)
+        m = opt.gp_step(pb, ref)
+        s = st.read()
+        d = abs(s["hpwl"] - m["hpwl_d2d"]) / m["hpwl_d2d"]
+        worst = max(worst, d)
+        log(f"[step] it {k} hpwl gpu={s['hpwl']:.7g} ref={m['hpwl_d2d']:.7g} rel={d:.2e} "
+            f"ovfl gpu={s['ovfl_bot']:.4f}/{s['ovfl_top']:.4f} ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
+    assert worst <= 1e-3
