@@ -1,0 +1,211 @@
+"""Benchmark: global-placement iterations per second on one MI355X.
+
+Workload: the 1.2M-cell synthetic netlist (150 macros, 1.3M nets, ~4.5M pins, grid
+1024 x 1024 x 4, seed 2403).  Two forms run from the same seed:
+  plain  -- float32 DCT contractions, the paper's field-gather density gradient
+  mixed  -- split-bf16 (hi/lo, three products, float32 accumulation) DCT contractions, same
+            field-gather gradient (the precision form of this workload)
+  autograd (optional, --forms) -- split-bf16 contractions with the exact-adjoint density gradient
+A step is one full GP iteration (place3d_step): density map, spectral solve, density gradient,
+bistratal WA wirelength with the FDA z-gradient, preconditioned Nesterov move.  `value` is the
+mixed form's iterations/s over exactly --steps timed steps after --warmup untimed ones; the plain
+form's rate, both final D2D HPWLs and their relative difference are reported beside it.
+
+The roofline entry is for the kernel with the largest GPU time in the mixed step, from per-launch
+HIP events recorded on the launch stream during a profiled block of steps right after the timed
+block.  The CPU baseline is the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GP iterations/s at 1.2M cells: BF16-split vs FP32, HPWL within 0.1%"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+
+
+def gemm_flops_per_step(nx, ny, nz, dgrad_field, bf16x3):
+    """Executed MFMA flops of the DCT contractions in one step (3 products per contraction in the
+    split form).  x passes: M = nz ny, N = K = nx; y passes: nz batches of M = ny, N = nx, K = ny."""
+    x_pass = 2.0 * nz * ny * nx * nx
+    y_pass = 2.0 * nz * ny * nx * ny
+    if dgrad_field:          # forward x, y; inverse y (cos, sin); inverse x (Ex, Ey, Ez)
+        total = x_pass + y_pass + 2 * y_pass + 3 * x_pass
+    else:                    # forward x, y; inverse y (cos); inverse x (phi)
+        total = x_pass + y_pass + y_pass + x_pass
+    return total * (3.0 if bf16x3 else 1.0)
+
+
+def wl_bytes(n, P, m):
+    """Algorithmic bytes of the wirelength sweep: per pin the owner index and four offsets (20 B),
+    per instance the xyz read and the gradient write (24 B), per net its CSR entry (4 B)."""
+    return 20.0 * P + 24.0 * n + 4.0 * m
+
+
+def density_bytes(n, bins):
+    """Algorithmic bytes of the density map: per instance xyz and four sizes (28 B), per bin the
+    fixed-instance map read and the map write (8 B)."""
+    return 28.0 * n + 8.0 * bins
+
+
+def run_form(case, precision, dgrad, steps, warmup, profile_steps, log):
+    import torch
+    from paper_2403_09070_amd import place3d
+    prob = place3d.Problem.from_case(case, precision=precision, dgrad=dgrad)
+    st = prob.gp_init(case.xyz0)
+    for _ in range(warmup):
+        prob.step(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        prob.step(st)
+        if (k + 1) % 100 == 0:
+            log(f"  step {k + 1}/{steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = st.read()
+    prof = None
+    if profile_steps > 0:
+        prob.profile(True)
+        for _ in range(profile_steps):
+            prob.step(st)
+        torch.cuda.synchronize()
+        prof = prob.profile_read(reset=True)
+        prob.profile(False)
+    del prob
+    torch.cuda.empty_cache()
+    return dict(seconds=dt, ips=steps / dt, ms=1e3 * dt / steps, state=res, prof=prof)
+
+
+def cpu_baseline(case, frac=4):
+    """FP64 oracle, one GP iteration estimated from a bounded sample of the same workload: the
+    density map and field gather on every frac-th instance, the wirelength (with the vanilla FDA)
+    on the first 1/frac of the nets, each time scaled by frac, plus one full spectral solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import density as den
+    from oracle import density_grad as dg
+    from oracle import optimizer as opt
+    from oracle import poisson
+    from oracle import wirelength as wl
+    pb = opt.problem_of(case)
+    geo = pb.geo
+    idx = np.arange(0, case.n_inst, frac)
+    t = {}
+    t0 = time.perf_counter()
+    rho = den.density_map(case.size[:, idx], case.kind[idx], case.xyz0[:, idx], geo)
+    t["density"] = (time.perf_counter() - t0) * frac
+    t0 = time.perf_counter()
+    sol = poisson.solve(rho, geo, want=("ex", "ey", "ez"))
+    t["field"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dg.field_gather(case.size[:, idx], case.kind[idx], case.xyz0[:, idx], sol["ex"], sol["ey"], sol["ez"], geo)
+    t["gather"] = (time.perf_counter() - t0) * frac
+    m = case.n_nets // frac
+    P = int(case.net_start[m])
+    t0 = time.perf_counter()
+    wl.wirelength(case.size, case.kind, case.xyz0, case.net_start[:m + 1], case.pin2node[:P],
+                  case.pin_off[:, :P], geo, pb.gamma, pb.alpha)
+    t["wirelength"] = (time.perf_counter() - t0) * frac
+    per_iter = sum(t.values())
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": 1.0 / per_iter, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one FP64 oracle iteration of the same 1.2M-cell workload, estimated from every "
+                       f"{frac}th instance (density, field gather) and the first 1/{frac} of the nets "
+                       f"(WA + vanilla FDA), each scaled x{frac}, plus one full dense spectral solve; "
+                       f"per-stage seconds " + ", ".join(f"{k} {v:.2f}" for k, v in t.items())),
+            "seconds_per_iteration": per_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--seed", type=int, default=2403)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,mixed")
+    args = ap.parse_args()
+    log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (this path has no "
+              f"multi-GPU form).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2403_09070_amd import place3d, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    place3d.lib()
+    log(f"[bench] generating {args.config} seed {args.seed}")
+    case = synth.make_case(args.config, args.seed)
+    forms = {"plain": (place3d.FP32, place3d.DGRAD_FIELD), "mixed": (place3d.BF16X3, place3d.DGRAD_FIELD),
+             "autograd": (place3d.BF16X3, place3d.DGRAD_ADJOINT)}
+    res = {}
+    for name in args.forms.split(","):
+        log(f"[bench] form {name}: warmup {args.warmup}, timed {args.steps}")
+        res[name] = run_form(case, *forms[name], args.steps, args.warmup, args.profile_steps, log)
+        log(f"[bench] form {name}: {res[name]['ips']:.1f} it/s, hpwl {res[name]['state']['hpwl']:.6e}")
+    head = res.get("mixed") or res[list(res)[0]]
+    head_name = "mixed" if "mixed" in res else list(res)[0]
+    bf16x3 = head_name in ("mixed", "autograd")
+    n, P, m = case.n_inst, case.n_pins, case.n_nets
+    bins = case.nx * case.ny * case.nz
+
+    roof = None
+    if head["prof"]:
+        prof = head["prof"]
+        ps = args.profile_steps
+        field_form = head_name != "autograd"
+        cands = {
+            "gemm": ("mfma", gemm_flops_per_step(case.nx, case.ny, case.nz, field_form, bf16x3) / 1e12,
+                     PEAK_TFLOPS["bf16" if bf16x3 else "f32"], "TFLOP/s"),
+            "wl_nets": ("hbm", wl_bytes(n, P, m) / 1e9, HBM_PEAK_GBS, "GB/s"),
+            "density": ("hbm", density_bytes(n, bins) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        }
+        stage = max(prof, key=lambda k: prof[k][0])
+        per_step_ms = {k: v[0] / ps for k, v in prof.items()}
+        key = stage if stage in cands else "gemm"
+        bound, work, peak, unit = cands[key]
+        ms, launches = prof[key]
+        lps = launches / ps
+        avg_ms = ms / launches
+        achieved = (work / lps) / (avg_ms / 1e3)        # per launch / average launch duration
+        roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": key,
+                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": lps,
+                "stage_ms_per_step": {k: round(v, 4) for k, v in per_step_ms.items()}}
+
+    line = {
+        "metric": METRIC, "value": round(head["ips"], 2), "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3/f32" if bf16x3 else "f32", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {n - case.meta['n_macros']} cells + {case.meta['n_macros']} macros, "
+                               f"{m} nets, {P} pins, grid {case.nx}x{case.ny}x{case.nz}, seed {args.seed}",
+                   "form": head_name, "parallelism": "single GPU"},
+    }
+    if "plain" in res and "mixed" in res:
+        hp, hm = res["plain"]["state"]["hpwl"], res["mixed"]["state"]["hpwl"]
+        line["config"].update({"plain_iters_per_s": round(res["plain"]["ips"], 2),
+                               "mixed_over_plain": round(res["mixed"]["ips"] / res["plain"]["ips"], 3),
+                               "hpwl_plain": hp, "hpwl_mixed": hm, "hpwl_rel_diff": abs(hm - hp) / hp,
+                               "iterations": args.warmup + args.steps})
+    if roof:
+        line["roofline"] = roof
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,18 @@ enum {
   PLACE3D_NSCALARS = 32
 };
 
+/* Stages timed by the optional profiler (place3d_profile_enable / place3d_profile_read). */
+enum {
+  PLACE3D_STAGE_DENSITY = 0,   /* density map: fixed-map copy, cell and macro scatter            */
+  PLACE3D_STAGE_GEMM = 1,      /* every DCT contraction launch (k_gemm_f32 or k_gemm_bf16x3)     */
+  PLACE3D_STAGE_ZMIX = 2,      /* z mixing and spectral scaling between contractions             */
+  PLACE3D_STAGE_DGRAD = 3,     /* density gradient: field gather or exact adjoint                */
+  PLACE3D_STAGE_WL_NETS = 4,   /* per-net WA / bistratal / FDA kernel                            */
+  PLACE3D_STAGE_WL_NODES = 5,  /* per-instance gather of pin shares and z normalisation          */
+  PLACE3D_STAGE_UPDATE = 6,    /* preconditioning, Nesterov move, reductions                     */
+  PLACE3D_NSTAGES = 7
+};
+
 typedef struct place3d_problem {
   int32_t n_inst;          /* instances: movable cells and macros, fixed instances           */
   int32_t n_pins;
@@ -207,6 +219,15 @@ PLACE3D_API int32_t place3d_gp_init(place3d_ctx* ctx, place3d_state* state, cons
  * step, Nesterov move, clamp, lambda *= lambda_ramp; metrics of the evaluation point go to
  * state->scalars. */
 PLACE3D_API int32_t place3d_step(place3d_ctx* ctx, place3d_state* state, void* stream);
+
+/* Profiling.  With `on` != 0, every later kernel launch of `ctx` is bracketed by a pair of HIP
+ * events recorded on the launch stream; place3d_profile_read waits for the recorded events and
+ * returns, for `stage`, the summed GPU milliseconds and the number of launches since the last
+ * reset (`reset` != 0 clears all stages after reading).  Event objects are host-runtime objects;
+ * no device memory is allocated.  Profiling adds a small per-launch overhead. */
+PLACE3D_API int32_t place3d_profile_enable(place3d_ctx* ctx, int32_t on);
+PLACE3D_API int32_t place3d_profile_read(place3d_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
+                                         int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -55,8 +55,30 @@ int check_problem(const place3d_problem* p, std::string& why) {
   return PLACE3D_OK;
 }
 
+p3d::TileGeom tile_geom(const place3d_problem& p) {
+  p3d::TileGeom t;
+  int T = 32;
+  while (T > 4 && (3 * T * T * p.nz * 4 > 60 * 1024 || T > p.nx || T > p.ny)) T >>= 1;
+  t.T = T;
+  t.ntx = (p.nx + T - 1) / T;
+  t.nty = (p.ny + T - 1) / T;
+  t.ntiles = t.ntx * t.nty;
+  t.cpb = 2048;
+  t.nblk = (p.n_inst + t.cpb - 1) / t.cpb;
+  return t;
+}
+
+int parts_bound(const place3d_problem& p, const p3d::TileGeom& t) {
+  int b = std::max(p.n_nets / 4 + 16, p.n_inst / 256 + 2);
+  b = std::max(b, t.ntiles);
+  b = std::max(b, t.nblk);
+  return std::max(b, 1024);
+}
+
 size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   Carver w{base};
+  c->tg = tile_geom(p);
+  c->part_stride = parts_bound(p, c->tg);
   const size_t nx = p.nx, ny = p.ny, nz = p.nz, n = p.n_inst, P = p.n_pins, m = p.n_nets;
   const size_t map = nx * ny * nz;
   auto& d = c->dct;
@@ -70,8 +92,16 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->rho = w.take<float>(map); c->phi = w.take<float>(map);
   c->ex = w.take<float>(map); c->ey = w.take<float>(map); c->ez = w.take<float>(map);
   c->fixed_map = w.take<float>(map);
-  c->movable_macros = w.take<int32_t>(n);
-  c->fixed_large = w.take<int32_t>(n);
+  c->cls = w.take<uint8_t>(n);
+  c->large_list = w.take<int32_t>(n);
+  c->fixed_list = w.take<int32_t>(n);
+  c->bk_counts = w.take<int32_t>((size_t)c->tg.ntiles * c->tg.nblk);
+  c->bk_totals = w.take<int32_t>(c->tg.ntiles);
+  c->bk_tile_start = w.take<int32_t>(c->tg.ntiles + 1);
+  c->bk_entries = w.take<float4>(8 * n);
+  c->cell_entry = w.take<int32_t>(4 * n);
+  c->entry_out = w.take<float4>(4 * n);
+  c->part = w.take<double>((size_t)p3d::R_COUNT * c->part_stride);
   c->npins = w.take<float>(n);
   c->s_net_start = w.take<int32_t>(m + 1);
   c->s_pin_node = w.take<int32_t>(P + 1);
@@ -107,12 +137,14 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   std::vector<int32_t> ns(m + 1), p2n(P);
   std::vector<float> off(4 * (size_t)P);
   std::vector<uint8_t> kind(n);
+  std::vector<float> size(4 * (size_t)n);
   P3D_HIP(c, hipMemcpyAsync(ns.data(), p.net_start, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, s));
   if (P > 0) {
     P3D_HIP(c, hipMemcpyAsync(p2n.data(), p.pin2node, sizeof(int32_t) * P, hipMemcpyDeviceToHost, s));
     P3D_HIP(c, hipMemcpyAsync(off.data(), p.pin_off, sizeof(float) * 4 * (size_t)P, hipMemcpyDeviceToHost, s));
   }
   P3D_HIP(c, hipMemcpyAsync(kind.data(), p.kind, n, hipMemcpyDeviceToHost, s));
+  P3D_HIP(c, hipMemcpyAsync(size.data(), p.size, sizeof(float) * 4 * (size_t)n, hipMemcpyDeviceToHost, s));
   P3D_HIP(c, hipStreamSynchronize(s));
 
   if (ns[0] != 0 || ns[m] != P) return set_err(c, PLACE3D_ERR_NETLIST, "net_start[0] must be 0 and net_start[n_nets] == n_pins");
@@ -180,13 +212,23 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   std::vector<float> npins(n);
   for (int i = 0; i < n; ++i) npins[i] = (float)(nss[i + 1] - nss[i]);
 
-  std::vector<int32_t> macros, fixed;
-  for (int i = 0; i < n; ++i) {
-    if (kind[i] & PLACE3D_KIND_FIXED) fixed.push_back(i);
-    else if (kind[i] & PLACE3D_KIND_MACRO) macros.push_back(i);
+  // density classes: bucketed cells must span at most two tiles per axis on either die
+  std::vector<int32_t> large, fixed;
+  std::vector<uint8_t> cls(n);
+  {
+    const double wb = p.die_x / p.nx, hb = p.die_y / p.ny;
+    const double wlim = (c->tg.T - 1) * wb, hlim = (c->tg.T - 1) * hb;
+    for (int i = 0; i < n; ++i) {
+      if (kind[i] & PLACE3D_KIND_FIXED) { cls[i] = p3d::kClsFixed; fixed.push_back(i); continue; }
+      const double w = std::max(size[i], size[2 * (size_t)n + i]);
+      const double h = std::max(size[(size_t)n + i], size[3 * (size_t)n + i]);
+      if ((kind[i] & PLACE3D_KIND_MACRO) || w > wlim || h > hlim) { cls[i] = p3d::kClsLarge; large.push_back(i); }
+      else cls[i] = p3d::kClsCell;
+    }
   }
-  c->n_movable_macros = (int32_t)macros.size();
+  c->n_large = (int32_t)large.size();
   c->n_fixed = (int32_t)fixed.size();
+  P3D_HIP(c, hipMemcpyAsync(c->cls, cls.data(), n, hipMemcpyHostToDevice, s));
 
   P3D_HIP(c, hipMemcpyAsync(c->s_net_start, sns.data(), sizeof(int32_t) * (ms + 1), hipMemcpyHostToDevice, s));
   if (P > 0) {
@@ -196,17 +238,38 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   }
   P3D_HIP(c, hipMemcpyAsync(c->node_slot_start, nss.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
   P3D_HIP(c, hipMemcpyAsync(c->npins, npins.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
-  if (!macros.empty())
-    P3D_HIP(c, hipMemcpyAsync(c->movable_macros, macros.data(), sizeof(int32_t) * macros.size(), hipMemcpyHostToDevice, s));
+  if (!large.empty())
+    P3D_HIP(c, hipMemcpyAsync(c->large_list, large.data(), sizeof(int32_t) * large.size(), hipMemcpyHostToDevice, s));
   if (!fixed.empty())
-    P3D_HIP(c, hipMemcpyAsync(c->fixed_large, fixed.data(), sizeof(int32_t) * fixed.size(), hipMemcpyHostToDevice, s));
+    P3D_HIP(c, hipMemcpyAsync(c->fixed_list, fixed.data(), sizeof(int32_t) * fixed.size(), hipMemcpyHostToDevice, s));
   P3D_HIP(c, hipStreamSynchronize(s));   // host vectors die at return
   return PLACE3D_OK;
 }
 
 }  // namespace
 
+place3d_ctx::~place3d_ctx() {
+  for (auto& r : prof_pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+  for (auto& e : prof_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+}
+
 namespace p3d {
+int prof_begin(place3d_ctx* c, int stage, hipStream_t s) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!c->prof_free.empty()) {
+    ev = c->prof_free.back();
+    c->prof_free.pop_back();
+  } else {
+    if (hipEventCreate(&ev.first) != hipSuccess) return PLACE3D_ERR_HIP;
+    if (hipEventCreate(&ev.second) != hipSuccess) { hipEventDestroy(ev.first); return PLACE3D_ERR_HIP; }
+  }
+  c->prof_pending.push_back({stage, ev.first, ev.second});
+  return hipEventRecord(ev.first, s) == hipSuccess ? PLACE3D_OK : PLACE3D_ERR_HIP;
+}
+int prof_end(place3d_ctx* c, hipStream_t s) {
+  if (c->prof_pending.empty()) return PLACE3D_OK;
+  return hipEventRecord(c->prof_pending.back().b, s) == hipSuccess ? PLACE3D_OK : PLACE3D_ERR_HIP;
+}
 int hip_fail(place3d_ctx* c, hipError_t e, const char* where) {
   std::string msg = std::string("HIP error ") + std::to_string((int)e) + " (" + hipGetErrorString(e) + ") in " + where;
   if (c) c->err = msg; else g_create_err = msg;
@@ -271,6 +334,31 @@ int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t by
 
 int32_t place3d_destroy(place3d_ctx* ctx) {
   delete ctx;
+  return PLACE3D_OK;
+}
+
+int32_t place3d_profile_enable(place3d_ctx* ctx, int32_t on) {
+  if (!ctx) return PLACE3D_ERR_ARG;
+  ctx->prof_on = on != 0;
+  return PLACE3D_OK;
+}
+
+int32_t place3d_profile_read(place3d_ctx* ctx, int32_t stage, double* ms, int64_t* launches, int32_t reset) {
+  if (!ctx) return PLACE3D_ERR_ARG;
+  if (stage < 0 || stage >= PLACE3D_NSTAGES) return set_err(ctx, PLACE3D_ERR_ARG, "bad stage");
+  for (auto& r : ctx->prof_pending) {
+    P3D_HIP(ctx, hipEventSynchronize(r.b));
+    float t = 0.f;
+    P3D_HIP(ctx, hipEventElapsedTime(&t, r.a, r.b));
+    ctx->prof_ms[r.stage] += t;
+    ctx->prof_count[r.stage] += 1;
+    ctx->prof_free.push_back({r.a, r.b});
+  }
+  ctx->prof_pending.clear();
+  if (ms) *ms = ctx->prof_ms[stage];
+  if (launches) *launches = ctx->prof_count[stage];
+  if (reset)
+    for (int k = 0; k < PLACE3D_NSTAGES; ++k) { ctx->prof_ms[k] = 0.0; ctx->prof_count[k] = 0; }
   return PLACE3D_OK;
 }
 

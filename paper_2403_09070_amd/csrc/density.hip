@@ -5,13 +5,21 @@
 // weight; w, h follow the partition for cells (Eq. std-size-tech) and z linearly for macros
 // (Eq. macro-size-tech).  rho_b = sum_i omega_i vol(D_i ∩ b) / vol(b).
 //
-// Planar extents are handled in coordinates local to the bin column holding the centre, so
-// that the overlap lengths keep float32 precision relative to the bin size even where the
-// absolute coordinate is large.
+// Work split (the adaptive scheme of Sec. IV-A, re-planned for LDS):
+//   * the map is cut into T x T x Nz tiles, each owned by one workgroup that holds it in LDS;
+//   * cells are bucketed by the tiles their footprint overlaps (a counting sort each call:
+//     per-block tile histograms, a scan, a scatter of 32-byte entries), so a tile sweeps its
+//     cells contiguously and accumulates with LDS atomics;
+//   * large instances (movable macros, oversized cells) are swept bin-parallel by every tile
+//     they overlap;
+//   * each tile then writes its bins once (fixed-instance map + contributions), so the map is
+//     written without global atomics, and reduces the per-die overflow on the way out.
+// The field gather and the adjoint reuse the buckets: every (cell, tile) entry sums the bins of
+// the tile it overlaps from an LDS copy of the maps, and a per-cell pass adds its <= 4 entries.
+// Large instances take one workgroup each.  The constant map of fixed instances is built once.
 //
-// Work split: cells (small, many) take one thread per instance; macros (large, few) take one
-// workgroup per instance sweeping its bins (the bin-parallel side of the paper's adaptive
-// scheme).  Fixed instances form a constant map built once.
+// Planar extents are handled in coordinates local to the bin column holding the centre, so
+// overlap lengths keep float32 precision relative to the bin size at any absolute coordinate.
 #include "internal.h"
 
 namespace p3d {
@@ -23,11 +31,42 @@ struct Foot {
   float lx0, lx1, ly0, ly1;           // clipped planar edges, local to (cbx*wb, cby*hb)
   float rx0, rx1, ry0, ry1;           // unclipped planar edges, local
   float z0, z1, rz0, rz1;             // clipped / unclipped z edges (absolute)
-  float omega, w, h, wt, ht;
+  float omega, w, h;
   float dw, dh;                       // macro size slope dw/dz, dh/dz inside the transition range
+  float rx, ry, z, hw, hh;            // the local centre and stretched half extents it came from
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// footprint from the centre in local coordinates (rx = x - cbx w_b) and the stretched half extents
+__device__ __forceinline__ void foot_local(const Geom& g, Foot& f, int cbx, int cby, float rx, float ry, float z,
+                                           float hw, float hh) {
+  f.cbx = cbx;
+  f.cby = cby;
+  f.rx = rx; f.ry = ry; f.z = z; f.hw = hw; f.hh = hh;
+  const float ox = (float)cbx * g.wb, oy = (float)cby * g.hb;
+  f.rx0 = rx - hw;
+  f.rx1 = rx + hw;
+  f.ry0 = ry - hh;
+  f.ry1 = ry + hh;
+  f.lx0 = fmaxf(f.rx0, -ox);
+  f.lx1 = fminf(f.rx1, g.dx - ox);
+  f.ly0 = fmaxf(f.ry0, -oy);
+  f.ly1 = fminf(f.ry1, g.dy - oy);
+  f.rz0 = z - 0.25f * g.dz;
+  f.rz1 = z + 0.25f * g.dz;
+  f.z0 = fmaxf(f.rz0, 0.f);
+  f.z1 = fminf(f.rz1, g.dz);
+  f.bx0 = clampi(cbx + (int)floorf(f.lx0 * g.inv_wb), 0, g.nx - 1);
+  f.bx1 = clampi(cbx + (int)ceilf(f.lx1 * g.inv_wb) - 1, 0, g.nx - 1);
+  f.by0 = clampi(cby + (int)floorf(f.ly0 * g.inv_hb), 0, g.ny - 1);
+  f.by1 = clampi(cby + (int)ceilf(f.ly1 * g.inv_hb) - 1, 0, g.ny - 1);
+  f.bz0 = clampi((int)floorf(f.z0 * g.inv_db), 0, g.nz - 1);
+  f.bz1 = clampi((int)ceilf(f.z1 * g.inv_db) - 1, 0, g.nz - 1);
+  f.bx1 = max(f.bx1, f.bx0);
+  f.by1 = max(f.by1, f.by0);
+  f.bz1 = max(f.bz1, f.bz0);
+}
 
 __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict__ xyz,
                                           const float* __restrict__ size, uint8_t kind, int i) {
@@ -57,35 +96,22 @@ __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict
   const float wmin = r2 * g.wb, hmin = r2 * g.hb;
   f.w = w;
   f.h = h;
-  f.wt = fmaxf(w, wmin);
-  f.ht = fmaxf(h, hmin);
   f.omega = fminf(1.f, w / wmin) * fminf(1.f, h / hmin);
+  const int cbx = clampi((int)floorf(x * g.inv_wb), 0, g.nx - 1);
+  const int cby = clampi((int)floorf(y * g.inv_hb), 0, g.ny - 1);
+  foot_local(g, f, cbx, cby, x - (float)cbx * g.wb, y - (float)cby * g.hb, z, 0.5f * fmaxf(w, wmin),
+             0.5f * fmaxf(h, hmin));
+  return f;
+}
 
-  f.cbx = clampi((int)floorf(x * g.inv_wb), 0, g.nx - 1);
-  f.cby = clampi((int)floorf(y * g.inv_hb), 0, g.ny - 1);
-  const float ox = (float)f.cbx * g.wb, oy = (float)f.cby * g.hb;
-  const float rx = x - ox, ry = y - oy;
-  f.rx0 = rx - 0.5f * f.wt;
-  f.rx1 = rx + 0.5f * f.wt;
-  f.ry0 = ry - 0.5f * f.ht;
-  f.ry1 = ry + 0.5f * f.ht;
-  f.lx0 = fmaxf(f.rx0, -ox);
-  f.lx1 = fminf(f.rx1, g.dx - ox);
-  f.ly0 = fmaxf(f.ry0, -oy);
-  f.ly1 = fminf(f.ry1, g.dy - oy);
-  f.rz0 = z - 0.25f * g.dz;
-  f.rz1 = z + 0.25f * g.dz;
-  f.z0 = fmaxf(f.rz0, 0.f);
-  f.z1 = fminf(f.rz1, g.dz);
-  f.bx0 = clampi(f.cbx + (int)floorf(f.lx0 * g.inv_wb), 0, g.nx - 1);
-  f.bx1 = clampi(f.cbx + (int)ceilf(f.lx1 * g.inv_wb) - 1, 0, g.nx - 1);
-  f.by0 = clampi(f.cby + (int)floorf(f.ly0 * g.inv_hb), 0, g.ny - 1);
-  f.by1 = clampi(f.cby + (int)ceilf(f.ly1 * g.inv_hb) - 1, 0, g.ny - 1);
-  f.bz0 = clampi((int)floorf(f.z0 * g.inv_db), 0, g.nz - 1);
-  f.bz1 = clampi((int)ceilf(f.z1 * g.inv_db) - 1, 0, g.nz - 1);
-  f.bx1 = max(f.bx1, f.bx0);
-  f.by1 = max(f.by1, f.by0);
-  f.bz1 = max(f.bz1, f.bz0);
+// bucket entry: (cbx | cby << 16, rx, ry, z), (hw, hh, omega, 0)
+__device__ __forceinline__ Foot foot_entry(const Geom& g, float4 a, float4 b) {
+  Foot f;
+  const unsigned packed = __float_as_uint(a.x);
+  foot_local(g, f, (int)(packed & 0xFFFFu), (int)(packed >> 16), a.y, a.z, a.w, b.x, b.y);
+  f.omega = b.z;
+  f.w = f.h = 0.f;
+  f.dw = f.dh = 0.f;
   return f;
 }
 
@@ -104,123 +130,44 @@ __device__ __forceinline__ float len_z(const Geom& g, const Foot& f, int b) {
 }
 
 // bin holding an unclipped edge (or -1 when the region clips that edge)
-__device__ __forceinline__ int edge_bin_x(const Geom& g, const Foot& f, float redge, int lo, int hi) {
+__device__ __forceinline__ int edge_bin_x(const Geom& g, const Foot& f, float redge) {
   const float ox = (float)f.cbx * g.wb;
   if (!(redge > -ox && redge < g.dx - ox)) return -1;
   const int b = f.cbx + (int)floorf(redge * g.inv_wb);
-  return (b >= lo && b <= hi) ? b : -1;
+  return (b >= f.bx0 && b <= f.bx1) ? b : -1;
 }
-__device__ __forceinline__ int edge_bin_y(const Geom& g, const Foot& f, float redge, int lo, int hi) {
+__device__ __forceinline__ int edge_bin_y(const Geom& g, const Foot& f, float redge) {
   const float oy = (float)f.cby * g.hb;
   if (!(redge > -oy && redge < g.dy - oy)) return -1;
   const int b = f.cby + (int)floorf(redge * g.inv_hb);
-  return (b >= lo && b <= hi) ? b : -1;
+  return (b >= f.by0 && b <= f.by1) ? b : -1;
 }
-__device__ __forceinline__ int edge_bin_z(const Geom& g, float zedge, int lo, int hi) {
+__device__ __forceinline__ int edge_bin_z(const Geom& g, const Foot& f, float zedge) {
   if (!(zedge > 0.f && zedge < g.dz)) return -1;
   const int b = (int)floorf(zedge * g.inv_db);
-  return (b >= lo && b <= hi) ? b : -1;
+  return (b >= f.bz0 && b <= f.bz1) ? b : -1;
 }
 
 __device__ __forceinline__ size_t bin_index(const Geom& g, int bz, int by, int bx) {
   return ((size_t)bz * g.ny + by) * g.nx + bx;
 }
 
-// ------------------------------------------------------------------ forward scatter
-
-__global__ void k_density_cells(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
-                                const uint8_t* __restrict__ kind, float* __restrict__ rho) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const uint8_t k = kind[i];
-  if (k & (PLACE3D_KIND_MACRO | PLACE3D_KIND_FIXED)) return;
-  const Foot f = footprint(g, xyz, size, k, i);
-  const float wgt = f.omega / g.vol_bin;
-  for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-    const float lz = len_z(g, f, bz) * wgt;
-    for (int by = f.by0; by <= f.by1; ++by) {
-      const float lyz = len_y(g, f, by) * lz;
-      for (int bx = f.bx0; bx <= f.bx1; ++bx) {
-        const float v = len_x(g, f, bx) * lyz;
-        if (v != 0.f) atomicAdd(rho + bin_index(g, bz, by, bx), v);
-      }
-    }
+template <int NQ>
+__device__ __forceinline__ void block_partials(float (&v)[NQ], double* __restrict__ part, int stride, int slot0,
+                                               int idx) {
+  __shared__ double sh[NQ][256 / kWave];
+  __syncthreads();
+  for (int q = 0; q < NQ; ++q) {
+    double x = v[q];
+    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[q][threadIdx.x / kWave] = x;
   }
-}
-
-// one workgroup per listed instance, sweeping the bins of its cuboid
-__global__ void k_density_large(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
-                                const uint8_t* __restrict__ kind, const int32_t* __restrict__ list,
-                                float* __restrict__ rho) {
-  const int i = list[blockIdx.x];
-  const Foot f = footprint(g, xyz, size, kind[i], i);
-  const int nbx = f.bx1 - f.bx0 + 1, nby = f.by1 - f.by0 + 1, nbz = f.bz1 - f.bz0 + 1;
-  const long long total = (long long)nbx * nby * nbz;
-  const float wgt = f.omega / g.vol_bin;
-  for (long long t = threadIdx.x; t < total; t += blockDim.x) {
-    const int bx = f.bx0 + (int)(t % nbx);
-    const long long r = t / nbx;
-    const int by = f.by0 + (int)(r % nby);
-    const int bz = f.bz0 + (int)(r / nby);
-    const float v = len_x(g, f, bx) * len_y(g, f, by) * len_z(g, f, bz) * wgt;
-    if (v != 0.f) atomicAdd(rho + bin_index(g, bz, by, bx), v);
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double x = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) x += sh[threadIdx.x][w];
+    part[(size_t)(slot0 + threadIdx.x) * stride + idx] = x;
   }
-}
-
-__global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n4) {
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n4; t += (long long)gridDim.x * blockDim.x)
-    dst[t] = src[t];
-}
-
-__global__ void k_fill(float* __restrict__ p, long long n, float v) {
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
-    p[t] = v;
-}
-
-__global__ void k_zero_f64(double* __restrict__ p, int n) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) p[t] = 0.0;
-}
-
-// ------------------------------------------------------------------ field gather
-
-// out_a[i] (+)= scale * omega * sum_b vol(D_i ∩ b) M_a[b] for the three maps
-__device__ __forceinline__ void gather3(const Geom& g, const Foot& f, const float* __restrict__ mx,
-                                        const float* __restrict__ my, const float* __restrict__ mz,
-                                        int bz, int by, int bx, float v, float& sx, float& sy, float& sz) {
-  const size_t b = bin_index(g, bz, by, bx);
-  sx += v * mx[b];
-  sy += v * my[b];
-  sz += v * mz[b];
-}
-
-__global__ void k_gather_cells(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
-                               const uint8_t* __restrict__ kind, const float* __restrict__ mx,
-                               const float* __restrict__ my, const float* __restrict__ mz, float scale,
-                               float* __restrict__ grad, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const uint8_t k = kind[i];
-  if ((k & PLACE3D_KIND_MACRO) && !(k & PLACE3D_KIND_FIXED)) return;   // movable macros: k_gather_large
-  float sx = 0.f, sy = 0.f, sz = 0.f;
-  if (!(k & PLACE3D_KIND_FIXED)) {
-    const Foot f = footprint(g, xyz, size, k, i);
-    for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-      const float lz = len_z(g, f, bz);
-      for (int by = f.by0; by <= f.by1; ++by) {
-        const float lyz = len_y(g, f, by) * lz;
-        for (int bx = f.bx0; bx <= f.bx1; ++bx) {
-          const float v = len_x(g, f, bx) * lyz;
-          if (v != 0.f) gather3(g, f, mx, my, mz, bz, by, bx, v, sx, sy, sz);
-        }
-      }
-    }
-    const float s = scale * f.omega;
-    sx *= s; sy *= s; sz *= s;
-  }
-  const int n = g.n;
-  if (accumulate) { grad[i] += sx; grad[n + i] += sy; grad[2 * n + i] += sz; }
-  else { grad[i] = sx; grad[n + i] = sy; grad[2 * n + i] = sz; }
 }
 
 template <int NT>
@@ -236,7 +183,305 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
   return r;   // valid in thread 0
 }
 
-// one workgroup per macro: gather with a block reduction (fixed macros get 0)
+// ------------------------------------------------------------------ bucketing
+
+// tiles overlapped by a bucketed cell (at most 2 x 2 for the cells this path takes)
+__device__ __forceinline__ void cell_tiles(const Foot& f, const TileGeom& t, int& tx0, int& tx1, int& ty0, int& ty1) {
+  tx0 = f.bx0 / t.T; tx1 = f.bx1 / t.T;
+  ty0 = f.by0 / t.T; ty1 = f.by1 / t.T;
+}
+
+// packed tile range of a bucketed cell: tx0 | ty0 << 12 | (tx1 - tx0) << 24 | (ty1 - ty0) << 25
+__device__ __forceinline__ int pack_tiles(int tx0, int tx1, int ty0, int ty1) {
+  return tx0 | (ty0 << 12) | ((tx1 - tx0) << 24) | ((ty1 - ty0) << 25);
+}
+
+// Counts entries per (tile, block) and records each cell's packed tile range in cell_entry[0][i],
+// so that the scatter pass places a cell in exactly the tiles it was counted in.
+__global__ __launch_bounds__(256) void k_bucket_count(Geom g, TileGeom t, const float* __restrict__ xyz,
+                                                      const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                                                      const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
+                                                      int32_t* __restrict__ tiles_of) {
+  extern __shared__ int hist[];
+  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * t.cpb;
+  for (int c = threadIdx.x; c < t.cpb; c += blockDim.x) {
+    const int i = base + c;
+    if (i >= g.n) continue;
+    if (cls[i] != kClsCell) { tiles_of[i] = -1; continue; }
+    const Foot f = footprint(g, xyz, size, kind[i], i);
+    int tx0, tx1, ty0, ty1;
+    cell_tiles(f, t, tx0, tx1, ty0, ty1);
+    tx1 = min(tx1, tx0 + 1);           // bucketed cells span at most two tiles per axis
+    ty1 = min(ty1, ty0 + 1);
+    tiles_of[i] = pack_tiles(tx0, tx1, ty0, ty1);
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * t.ntx + tx], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) counts[(size_t)k * t.nblk + blockIdx.x] = hist[k];
+}
+
+// exclusive scan of one tile's counts over the bucket blocks (in place); the tile total to totals
+__global__ __launch_bounds__(256) void k_bucket_scan_rows(int nblk, int32_t* __restrict__ counts,
+                                                          int32_t* __restrict__ totals) {
+  __shared__ int sh[256];
+  int32_t* row = counts + (size_t)blockIdx.x * nblk;
+  const int per = (nblk + 255) / 256;
+  const int b0 = threadIdx.x * per, b1 = min(b0 + per, nblk);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += row[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {           // inclusive Hillis-Steele scan
+    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;                // exclusive prefix of this thread's chunk
+  for (int b = b0; b < b1; ++b) { const int c = row[b]; row[b] = run; run += c; }
+  if (threadIdx.x == 255) totals[blockIdx.x] = sh[255];
+}
+
+// exclusive scan of the tile totals -> tile_start[0..ntiles]
+__global__ __launch_bounds__(1024) void k_bucket_scan_tiles(int ntiles, const int32_t* __restrict__ totals,
+                                                            int32_t* __restrict__ tile_start) {
+  __shared__ int sh[1024];
+  const int per = (ntiles + 1023) / 1024;
+  const int k0 = threadIdx.x * per, k1 = min(k0 + per, ntiles);
+  int s = 0;
+  for (int k = k0; k < k1; ++k) s += totals[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int k = k0; k < k1; ++k) { tile_start[k] = run; run += totals[k]; }
+  if (threadIdx.x == 1023) tile_start[ntiles] = sh[1023];
+}
+
+__global__ __launch_bounds__(256) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
+                                                        const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                                                        const uint8_t* __restrict__ cls, const int32_t* __restrict__ counts,
+                                                        const int32_t* __restrict__ tile_start,
+                                                        float4* __restrict__ entries, int32_t* __restrict__ cell_entry) {
+  extern __shared__ int cursor[];
+  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x)
+    cursor[k] = tile_start[k] + counts[(size_t)k * t.nblk + blockIdx.x];
+  __syncthreads();
+  const int n = g.n;
+  const int base = blockIdx.x * t.cpb;
+  for (int c = threadIdx.x; c < t.cpb; c += blockDim.x) {
+    const int i = base + c;
+    if (i >= n) continue;
+    int slots[4] = {-1, -1, -1, -1};
+    const int packed = cell_entry[i];   // tile range recorded by the count pass, -1 if none
+    if (packed >= 0) {
+      const Foot f = footprint(g, xyz, size, kind[i], i);
+      const int tx0 = packed & 0xFFF, ty0 = (packed >> 12) & 0xFFF;
+      const int tx1 = tx0 + ((packed >> 24) & 1), ty1 = ty0 + ((packed >> 25) & 1);
+      const float4 ea = make_float4(__uint_as_float((unsigned)f.cbx | ((unsigned)f.cby << 16)), f.rx, f.ry, f.z);
+      const float4 eb = make_float4(f.hw, f.hh, f.omega, 0.f);
+      int q = 0;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const int slot = atomicAdd(&cursor[ty * t.ntx + tx], 1);
+          entries[2 * (size_t)slot] = ea;
+          entries[2 * (size_t)slot + 1] = eb;
+          slots[q++] = slot;
+        }
+    }
+    for (int q = 0; q < 4; ++q) cell_entry[(size_t)q * n + i] = slots[q];
+  }
+}
+
+// ------------------------------------------------------------------ tiled density map
+
+struct TileBox { int x0, y0, wx, wy; };
+
+__device__ __forceinline__ TileBox tile_box(const Geom& g, const TileGeom& t, int tile) {
+  TileBox b;
+  const int tx = tile % t.ntx, ty = tile / t.ntx;
+  b.x0 = tx * t.T;
+  b.y0 = ty * t.T;
+  b.wx = min(t.T, g.nx - b.x0);
+  b.wy = min(t.T, g.ny - b.y0);
+  return b;
+}
+
+__device__ __forceinline__ int lds_index(const TileGeom& t, int bz, int ly, int lx) { return (bz * t.T + ly) * t.T + lx; }
+
+__global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+                                                       const int32_t* __restrict__ tile_start,
+                                                       const float* __restrict__ fixed_map, const float* __restrict__ xyz,
+                                                       const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                                                       const int32_t* __restrict__ large, int nlarge, float target,
+                                                       float* __restrict__ rho, double* __restrict__ part, int stride) {
+  extern __shared__ float S[];
+  const int tile = blockIdx.x;
+  const TileBox tb = tile_box(g, t, tile);
+  const int tsz = t.T * t.T * g.nz;
+  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    S[k] = (lx < tb.wx && ly < tb.wy) ? fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
+  }
+  __syncthreads();
+  // large instances: bin-parallel sweep of their part of this tile
+  const float inv_vol = 1.f / g.vol_bin;
+  for (int j = 0; j < nlarge; ++j) {
+    const int i = large[j];
+    const Foot f = footprint(g, xyz, size, kind[i], i);
+    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+    if (bx0 > bx1 || by0 > by1) continue;
+    const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = f.bz1 - f.bz0 + 1;
+    const int total = nbx * nby * nbz;
+    const float wgt = f.omega * inv_vol;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = f.bz0 + q / (nbx * nby);
+      const float v = len_x(g, f, bx) * len_y(g, f, by) * len_z(g, f, bz) * wgt;
+      S[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += v;   // one thread per bin within one instance
+    }
+    __syncthreads();
+  }
+  // bucketed cells
+  const int e1 = tile_start[tile + 1];
+  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
+    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+    const float wgt = f.omega * inv_vol;
+    for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+      const float lz = len_z(g, f, bz) * wgt;
+      for (int by = by0; by <= by1; ++by) {
+        const float lyz = len_y(g, f, by) * lz;
+        for (int bx = bx0; bx <= bx1; ++bx) {
+          const float v = len_x(g, f, bx) * lyz;
+          if (v != 0.f) atomicAdd(&S[lds_index(t, bz, by - tb.y0, bx - tb.x0)], v);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  float ex[2] = {0.f, 0.f};
+  const int half = g.nz / 2;
+  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    if (lx < tb.wx && ly < tb.wy) {
+      const float v = S[k];
+      rho[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] = v;
+      ex[bz < half ? 0 : 1] += fmaxf(v - target, 0.f) * g.vol_bin;
+    }
+  }
+  block_partials<2>(ex, part, stride, R_EXCESS_BOT, tile);
+}
+
+// fixed map: one workgroup per fixed instance, global atomics (built once)
+__global__ void k_density_large(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
+                                const uint8_t* __restrict__ kind, const int32_t* __restrict__ list,
+                                float* __restrict__ rho) {
+  const int i = list[blockIdx.x];
+  const Foot f = footprint(g, xyz, size, kind[i], i);
+  const int nbx = f.bx1 - f.bx0 + 1, nby = f.by1 - f.by0 + 1, nbz = f.bz1 - f.bz0 + 1;
+  const long long total = (long long)nbx * nby * nbz;
+  const float wgt = f.omega / g.vol_bin;
+  for (long long q = threadIdx.x; q < total; q += blockDim.x) {
+    const int bx = f.bx0 + (int)(q % nbx);
+    const long long r = q / nbx;
+    const int by = f.by0 + (int)(r % nby);
+    const int bz = f.bz0 + (int)(r / nby);
+    const float v = len_x(g, f, bx) * len_y(g, f, by) * len_z(g, f, bz) * wgt;
+    if (v != 0.f) atomicAdd(rho + bin_index(g, bz, by, bx), v);
+  }
+}
+
+__global__ void k_fill(float* __restrict__ p, long long n, float v) {
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+    p[q] = v;
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) p[q] = 0.0;
+}
+
+// out[q] = sum (or max) over b < nparts of part[(slot0 + q) * stride + b], in a fixed order
+__global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ part, int stride, int slot0, int nparts,
+                                                   int is_max, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int q = slot0 + blockIdx.x;
+  const double* row = part + (size_t)q * stride;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) s = is_max ? fmax(s, row[b]) : s + row[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      sh[threadIdx.x] = is_max ? fmax(sh[threadIdx.x], sh[threadIdx.x + o]) : sh[threadIdx.x] + sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+// ------------------------------------------------------------------ field gather
+
+// every (cell, tile) entry: sum over the tile's bins of overlap * map, for three maps
+__global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+                                                      const int32_t* __restrict__ tile_start,
+                                                      const float* __restrict__ mx, const float* __restrict__ my,
+                                                      const float* __restrict__ mz, float4* __restrict__ out) {
+  extern __shared__ float S[];
+  const int tile = blockIdx.x;
+  const TileBox tb = tile_box(g, t, tile);
+  const int tsz = t.T * t.T * g.nz;
+  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    const bool in = lx < tb.wx && ly < tb.wy;
+    const size_t b = in ? bin_index(g, bz, tb.y0 + ly, tb.x0 + lx) : 0;
+    S[k] = in ? mx[b] : 0.f;
+    S[tsz + k] = in ? my[b] : 0.f;
+    S[2 * tsz + k] = in ? mz[b] : 0.f;
+  }
+  __syncthreads();
+  const int e1 = tile_start[tile + 1];
+  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
+    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+      const float lz = len_z(g, f, bz);
+      for (int by = by0; by <= by1; ++by) {
+        const float lyz = len_y(g, f, by) * lz;
+        for (int bx = bx0; bx <= bx1; ++bx) {
+          const float v = len_x(g, f, bx) * lyz;
+          const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
+          sx += v * S[k];
+          sy += v * S[tsz + k];
+          sz += v * S[2 * tsz + k];
+        }
+      }
+    }
+    out[e] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
+  }
+}
+
+__device__ __forceinline__ void gather3(const Geom& g, const float* __restrict__ mx, const float* __restrict__ my,
+                                        const float* __restrict__ mz, int bz, int by, int bx, float v, float& sx,
+                                        float& sy, float& sz) {
+  const size_t b = bin_index(g, bz, by, bx);
+  sx += v * mx[b];
+  sy += v * my[b];
+  sz += v * mz[b];
+}
+
+// one workgroup per large instance: gather with a block reduction
 __global__ void k_gather_large(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
                                const uint8_t* __restrict__ kind, const int32_t* __restrict__ list,
                                const float* __restrict__ mx, const float* __restrict__ my,
@@ -248,13 +493,13 @@ __global__ void k_gather_large(Geom g, const float* __restrict__ xyz, const floa
   const int nbx = f.bx1 - f.bx0 + 1, nby = f.by1 - f.by0 + 1, nbz = f.bz1 - f.bz0 + 1;
   const long long total = (long long)nbx * nby * nbz;
   float sx = 0.f, sy = 0.f, sz = 0.f;
-  for (long long t = threadIdx.x; t < total; t += blockDim.x) {
-    const int bx = f.bx0 + (int)(t % nbx);
-    const long long r = t / nbx;
+  for (long long q = threadIdx.x; q < total; q += blockDim.x) {
+    const int bx = f.bx0 + (int)(q % nbx);
+    const long long r = q / nbx;
     const int by = f.by0 + (int)(r % nby);
     const int bz = f.bz0 + (int)(r / nby);
     const float v = len_x(g, f, bx) * len_y(g, f, by) * len_z(g, f, bz);
-    gather3(g, f, mx, my, mz, bz, by, bx, v, sx, sy, sz);
+    gather3(g, mx, my, mz, bz, by, bx, v, sx, sy, sz);
   }
   sx = block_sum<256>(sx, sh);
   sy = block_sum<256>(sy, sh);
@@ -269,71 +514,79 @@ __global__ void k_gather_large(Geom g, const float* __restrict__ xyz, const floa
 
 // ------------------------------------------------------------------ exact adjoint
 
-// Face sums of the map for one instance: the derivative of each overlap length with respect to
-// an edge is +-1 on the bin holding that edge.  Returns (sx_hi - sx_lo, ...) and, for macros,
-// the size-transition terms, all times omega / vol(b).
-struct AdjSums { float gx, gy, gz; };
+// Face sums of the map: the derivative of an overlap length with respect to an edge is +-1 on
+// the bin holding that edge.  (gx, gy, gz) = face differences; for large instances also the sums
+// the macro size-transition terms need.  Loops over the bins q = t0, t0 + tstep, ... of the box
+// [bx0..bx1] x [by0..by1] x [bz0..bz1] (a sub-box of the footprint).
+struct AdjSums { float gx, gy, gz, xs, ys, all; };
 
-__device__ __forceinline__ AdjSums adjoint_range(const Geom& g, const Foot& f, const float* __restrict__ m,
-                                                 long long t0, long long tstep, bool is_macro) {
-  // the flattened loop over (bz, by, bx) of the clipped box; each bin collects its own share
-  const int ebx_lo = edge_bin_x(g, f, f.rx0, f.bx0, f.bx1), ebx_hi = edge_bin_x(g, f, f.rx1, f.bx0, f.bx1);
-  const int eby_lo = edge_bin_y(g, f, f.ry0, f.by0, f.by1), eby_hi = edge_bin_y(g, f, f.ry1, f.by0, f.by1);
-  const int ebz_lo = edge_bin_z(g, f.rz0, f.bz0, f.bz1), ebz_hi = edge_bin_z(g, f.rz1, f.bz0, f.bz1);
-  const int nbx = f.bx1 - f.bx0 + 1, nby = f.by1 - f.by0 + 1, nbz = f.bz1 - f.bz0 + 1;
-  const long long total = (long long)nbx * nby * nbz;
-  float xd = 0.f, xs = 0.f, yd = 0.f, ys = 0.f, zd = 0.f, all = 0.f;
-  for (long long t = t0; t < total; t += tstep) {
-    const int bx = f.bx0 + (int)(t % nbx);
-    const long long r = t / nbx;
-    const int by = f.by0 + (int)(r % nby);
-    const int bz = f.bz0 + (int)(r / nby);
-    const float mv = m[bin_index(g, bz, by, bx)];
+template <class MapAt>
+__device__ __forceinline__ AdjSums adjoint_sums(const Geom& g, const Foot& f, MapAt map_at, int bx0, int bx1,
+                                                int by0, int by1, int t0, int tstep, bool with_size_terms) {
+  const int ebx_lo = edge_bin_x(g, f, f.rx0), ebx_hi = edge_bin_x(g, f, f.rx1);
+  const int eby_lo = edge_bin_y(g, f, f.ry0), eby_hi = edge_bin_y(g, f, f.ry1);
+  const int ebz_lo = edge_bin_z(g, f, f.rz0), ebz_hi = edge_bin_z(g, f, f.rz1);
+  const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = f.bz1 - f.bz0 + 1;
+  const int total = nbx * nby * nbz;
+  AdjSums a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int q = t0; q < total; q += tstep) {
+    const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = f.bz0 + q / (nbx * nby);
+    const float mv = map_at(bz, by, bx);
     const float lx = len_x(g, f, bx), ly = len_y(g, f, by), lz = len_z(g, f, bz);
     const float fxh = (bx == ebx_hi) ? 1.f : 0.f, fxl = (bx == ebx_lo) ? 1.f : 0.f;
     const float fyh = (by == eby_hi) ? 1.f : 0.f, fyl = (by == eby_lo) ? 1.f : 0.f;
     const float fzh = (bz == ebz_hi) ? 1.f : 0.f, fzl = (bz == ebz_lo) ? 1.f : 0.f;
-    xd += (fxh - fxl) * ly * lz * mv;
-    yd += lx * (fyh - fyl) * lz * mv;
-    zd += lx * ly * (fzh - fzl) * mv;
-    if (is_macro) {
-      xs += (fxh + fxl) * ly * lz * mv;
-      ys += lx * (fyh + fyl) * lz * mv;
-      all += lx * ly * lz * mv;
+    a.gx += (fxh - fxl) * ly * lz * mv;
+    a.gy += lx * (fyh - fyl) * lz * mv;
+    a.gz += lx * ly * (fzh - fzl) * mv;
+    if (with_size_terms) {
+      a.xs += (fxh + fxl) * ly * lz * mv;
+      a.ys += lx * (fyh + fyl) * lz * mv;
+      a.all += lx * ly * lz * mv;
     }
   }
-  AdjSums a;
-  a.gx = f.omega * xd;
-  a.gy = f.omega * yd;
-  a.gz = f.omega * zd;
-  if (is_macro && (f.dw != 0.f || f.dh != 0.f)) {
+  return a;
+}
+
+__device__ __forceinline__ float3 adjoint_finish(const Geom& g, const Foot& f, const AdjSums& a) {
+  float3 r = make_float3(f.omega * a.gx, f.omega * a.gy, f.omega * a.gz);
+  if (f.dw != 0.f || f.dh != 0.f) {
     const float r2 = 1.41421356237309515f;
     const float wmin = r2 * g.wb, hmin = r2 * g.hb;
     const bool sw = f.w < wmin, sh = f.h < hmin;
     const float fw = fminf(1.f, f.w / wmin), fh = fminf(1.f, f.h / hmin);
     const float domega = (sw ? f.dw / wmin : 0.f) * fh + fw * (sh ? f.dh / hmin : 0.f);
     const float dwt = sw ? 0.f : f.dw, dht = sh ? 0.f : f.dh;
-    a.gz += domega * all + f.omega * 0.5f * (dwt * xs + dht * ys);
+    r.z += domega * a.all + f.omega * 0.5f * (dwt * a.xs + dht * a.ys);
   }
-  return a;
+  return r;
 }
 
-__global__ void k_adjoint_cells(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
-                                const uint8_t* __restrict__ kind, const float* __restrict__ m, float scale,
-                                float* __restrict__ grad, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
-  const uint8_t k = kind[i];
-  if ((k & PLACE3D_KIND_MACRO) && !(k & PLACE3D_KIND_FIXED)) return;   // movable macros: k_adjoint_large
-  AdjSums a = {0.f, 0.f, 0.f};
-  if (!(k & PLACE3D_KIND_FIXED)) {
-    const Foot f = footprint(g, xyz, size, k, i);
-    a = adjoint_range(g, f, m, 0, 1, false);
+__global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+                                                       const int32_t* __restrict__ tile_start,
+                                                       const float* __restrict__ m, float4* __restrict__ out) {
+  extern __shared__ float S[];
+  const int tile = blockIdx.x;
+  const TileBox tb = tile_box(g, t, tile);
+  const int tsz = t.T * t.T * g.nz;
+  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
   }
-  const float s = scale / g.vol_bin;
-  const int n = g.n;
-  if (accumulate) { grad[i] += s * a.gx; grad[n + i] += s * a.gy; grad[2 * n + i] += s * a.gz; }
-  else { grad[i] = s * a.gx; grad[n + i] = s * a.gy; grad[2 * n + i] = s * a.gz; }
+  __syncthreads();
+  const int e1 = tile_start[tile + 1];
+  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
+    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+    float3 r = make_float3(0.f, 0.f, 0.f);
+    if (bx0 <= bx1 && by0 <= by1) {
+      auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
+      const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, 0, 1, false);
+      r = adjoint_finish(g, f, a);
+    }
+    out[e] = make_float4(r.x, r.y, r.z, 0.f);
+  }
 }
 
 __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
@@ -343,42 +596,51 @@ __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const flo
   __shared__ float sh[256 / kWave];
   const int i = list[blockIdx.x];
   const Foot f = footprint(g, xyz, size, kind[i], i);
-  AdjSums a = adjoint_range(g, f, m, threadIdx.x, blockDim.x, true);
+  auto at = [&](int bz, int by, int bx) { return m[bin_index(g, bz, by, bx)]; };
+  AdjSums a = adjoint_sums(g, f, at, f.bx0, f.bx1, f.by0, f.by1, threadIdx.x, blockDim.x, true);
   a.gx = block_sum<256>(a.gx, sh);
   a.gy = block_sum<256>(a.gy, sh);
   a.gz = block_sum<256>(a.gz, sh);
+  a.xs = block_sum<256>(a.xs, sh);
+  a.ys = block_sum<256>(a.ys, sh);
+  a.all = block_sum<256>(a.all, sh);
   if (threadIdx.x == 0) {
+    const float3 r = adjoint_finish(g, f, a);
     const float s = scale / g.vol_bin;
     const int n = g.n;
-    if (accumulate) { grad[i] += s * a.gx; grad[n + i] += s * a.gy; grad[2 * n + i] += s * a.gz; }
-    else { grad[i] = s * a.gx; grad[n + i] = s * a.gy; grad[2 * n + i] = s * a.gz; }
+    if (accumulate) { grad[i] += s * r.x; grad[n + i] += s * r.y; grad[2 * n + i] += s * r.z; }
+    else { grad[i] = s * r.x; grad[n + i] = s * r.y; grad[2 * n + i] = s * r.z; }
   }
 }
 
-// ------------------------------------------------------------------ overflow
-
-__global__ void k_overflow(Geom g, const float* __restrict__ rho, float target, double* __restrict__ red) {
-  __shared__ float sh[256 / kWave];
-  const long long plane = (long long)g.nx * g.ny;
-  const long long half = plane * (g.nz / 2), total = plane * g.nz;
-  float bot = 0.f, top = 0.f;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
-    const float e = fmaxf(rho[t] - target, 0.f);
-    if (t < half) bot += e; else top += e;
+// per instance: the sum of its (<= 4) entry results for bucketed cells, zero for fixed
+// instances; large instances are written by their own kernel
+__global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ cell_entry,
+                                const float4* __restrict__ res, float scale, float* __restrict__ grad, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t c = cls[i];
+  if (c == kClsLarge) return;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  if (c == kClsCell) {
+    for (int q = 0; q < 4; ++q) {
+      const int e = cell_entry[(size_t)q * n + i];
+      if (e >= 0) { const float4 v = res[e]; sx += v.x; sy += v.y; sz += v.z; }
+    }
+    sx *= scale; sy *= scale; sz *= scale;
   }
-  bot = block_sum<256>(bot, sh);
-  top = block_sum<256>(top, sh);
-  if (threadIdx.x == 0) {
-    atomicAdd(red + R_EXCESS_BOT, (double)bot * g.vol_bin);
-    atomicAdd(red + R_EXCESS_TOP, (double)top * g.vol_bin);
-  }
+  if (accumulate) { grad[i] += sx; grad[n + i] += sy; grad[2 * n + i] += sz; }
+  else { grad[i] = sx; grad[n + i] = sy; grad[2 * n + i] = sz; }
 }
+
+size_t tile_lds(const place3d_ctx* c, int maps) { return sizeof(float) * (size_t)maps * c->tg.T * c->tg.T * c->g.nz; }
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 
 int launch_zero_f64(place3d_ctx* c, double* p, int n, hipStream_t s) {
+  ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
   hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
   P3D_LAUNCH(c, "k_zero_f64");
   return PLACE3D_OK;
@@ -391,76 +653,114 @@ int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t 
   return PLACE3D_OK;
 }
 
+int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s) {
+  ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+  hipLaunchKernelGGL(k_red_final, dim3(nq), dim3(256), 0, s, c->part, c->part_stride, slot0, nparts, is_max ? 1 : 0,
+                     out);
+  P3D_LAUNCH(c, "k_red_final");
+  return PLACE3D_OK;
+}
+
 int build_fixed_map(place3d_ctx* c, hipStream_t s) {
   const Geom& g = c->g;
   const long long map = (long long)g.nx * g.ny * g.nz;
   if (int rc = launch_fill_f32(c, c->fixed_map, map, 0.f, s)) return rc;
   if (c->n_fixed > 0) {
     hipLaunchKernelGGL(k_density_large, dim3(c->n_fixed), dim3(256), 0, s, g, c->prob.fixed_xyz,
-                       c->prob.size, c->prob.kind, c->fixed_large, c->fixed_map);
+                       c->prob.size, c->prob.kind, c->fixed_list, c->fixed_map);
     P3D_LAUNCH(c, "k_density_large(fixed)");
   }
   return PLACE3D_OK;
 }
 
-int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s) {
+int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
   const Geom& g = c->g;
-  const long long map = (long long)g.nx * g.ny * g.nz;
-  if (map % 4 == 0 && (reinterpret_cast<uintptr_t>(rho) & 15) == 0) {
-    const unsigned nb = (unsigned)std::min<long long>(blocks_for(map / 4, 256), 8192);
-    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, reinterpret_cast<const float4*>(c->fixed_map),
-                       reinterpret_cast<float4*>(rho), map / 4);
-    P3D_LAUNCH(c, "k_copy");
-  } else {
-    P3D_HIP(c, hipMemcpyAsync(rho, c->fixed_map, sizeof(float) * map, hipMemcpyDeviceToDevice, s));
-  }
-  hipLaunchKernelGGL(k_density_cells, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, xyz, c->prob.size,
-                     c->prob.kind, rho);
-  P3D_LAUNCH(c, "k_density_cells");
-  if (c->n_movable_macros > 0) {
-    hipLaunchKernelGGL(k_density_large, dim3(c->n_movable_macros), dim3(256), 0, s, g, xyz, c->prob.size,
-                       c->prob.kind, c->movable_macros, rho);
-    P3D_LAUNCH(c, "k_density_large");
-  }
+  const TileGeom& t = c->tg;
+  const place3d_problem& p = c->prob;
+  ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
+  const size_t hist = sizeof(int) * t.ntiles;
+  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls, c->bk_counts,
+                     c->cell_entry);
+  P3D_LAUNCH(c, "k_bucket_count");
+  hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
+  P3D_LAUNCH(c, "k_bucket_scan_rows");
+  hipLaunchKernelGGL(k_bucket_scan_tiles, dim3(1), dim3(1024), 0, s, t.ntiles, c->bk_totals, c->bk_tile_start);
+  P3D_LAUNCH(c, "k_bucket_scan_tiles");
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls,
+                     c->bk_counts, c->bk_tile_start, c->bk_entries, c->cell_entry);
+  P3D_LAUNCH(c, "k_bucket_scatter");
   return PLACE3D_OK;
 }
 
-int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey,
-                         const float* ez, float scale, float* grad, int accumulate, hipStream_t s) {
+int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s) {
   const Geom& g = c->g;
-  hipLaunchKernelGGL(k_gather_cells, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, xyz, c->prob.size,
-                     c->prob.kind, ex, ey, ez, scale, grad, accumulate);
-  P3D_LAUNCH(c, "k_gather_cells");
-  // macros (movable and fixed) are handled per workgroup; fixed ones get zero
-  if (c->n_movable_macros > 0) {
-    hipLaunchKernelGGL(k_gather_large, dim3(c->n_movable_macros), dim3(256), 0, s, g, xyz, c->prob.size,
-                       c->prob.kind, c->movable_macros, ex, ey, ez, scale, grad, accumulate);
+  const TileGeom& t = c->tg;
+  const place3d_problem& p = c->prob;
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
+    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 1), s, g, t, c->bk_entries,
+                       c->bk_tile_start, c->fixed_map, xyz, p.size, p.kind, c->large_list, c->n_large,
+                       (float)p.target_density, rho, c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_density_tiles");
+  }
+  return reduce_final(c, R_EXCESS_BOT, 2, t.ntiles, false, red + R_EXCESS_BOT, s);
+}
+
+int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s) {
+  if (int rc = bucket_cells(c, xyz, s)) return rc;
+  return density_tiles(c, xyz, rho, c->red2, s);
+}
+
+int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
+                    float* grad, int accumulate, hipStream_t s) {
+  const Geom& g = c->g;
+  const TileGeom& t = c->tg;
+  const place3d_problem& p = c->prob;
+  ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
+  hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 3), s, g, t, c->bk_entries,
+                     c->bk_tile_start, ex, ey, ez, c->entry_out);
+  P3D_LAUNCH(c, "k_gather_tiles");
+  if (c->n_large > 0) {
+    hipLaunchKernelGGL(k_gather_large, dim3(c->n_large), dim3(256), 0, s, g, xyz, p.size, p.kind, c->large_list, ex,
+                       ey, ez, scale, grad, accumulate);
     P3D_LAUNCH(c, "k_gather_large");
   }
+  hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
+                     c->entry_out, scale, grad, accumulate);
+  P3D_LAUNCH(c, "k_cells_combine");
   return PLACE3D_OK;
 }
 
-int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad,
-                    int accumulate, hipStream_t s) {
+int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
+                     hipStream_t s) {
   const Geom& g = c->g;
-  hipLaunchKernelGGL(k_adjoint_cells, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g, xyz, c->prob.size,
-                     c->prob.kind, gmap, scale, grad, accumulate);
-  P3D_LAUNCH(c, "k_adjoint_cells");
-  if (c->n_movable_macros > 0) {
-    hipLaunchKernelGGL(k_adjoint_large, dim3(c->n_movable_macros), dim3(256), 0, s, g, xyz, c->prob.size,
-                       c->prob.kind, c->movable_macros, gmap, scale, grad, accumulate);
+  const TileGeom& t = c->tg;
+  const place3d_problem& p = c->prob;
+  ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
+  hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 1), s, g, t, c->bk_entries,
+                     c->bk_tile_start, gmap, c->entry_out);
+  P3D_LAUNCH(c, "k_adjoint_tiles");
+  if (c->n_large > 0) {
+    hipLaunchKernelGGL(k_adjoint_large, dim3(c->n_large), dim3(256), 0, s, g, xyz, p.size, p.kind, c->large_list, gmap,
+                       scale, grad, accumulate);
     P3D_LAUNCH(c, "k_adjoint_large");
   }
+  hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
+                     c->entry_out, scale / g.vol_bin, grad, accumulate);
+  P3D_LAUNCH(c, "k_cells_combine");
   return PLACE3D_OK;
 }
 
-int overflow_reduce(place3d_ctx* c, const float* rho, double* red, hipStream_t s) {
-  const Geom& g = c->g;
-  const long long map = (long long)g.nx * g.ny * g.nz;
-  const unsigned nb = (unsigned)std::min<long long>(blocks_for(map, 256), 2048);
-  hipLaunchKernelGGL(k_overflow, dim3(nb), dim3(256), 0, s, g, rho, (float)c->prob.target_density, red);
-  P3D_LAUNCH(c, "k_overflow");
-  return PLACE3D_OK;
+int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez,
+                         float scale, float* grad, int accumulate, hipStream_t s) {
+  if (int rc = bucket_cells(c, xyz, s)) return rc;
+  return gather_bucketed(c, xyz, ex, ey, ez, scale, grad, accumulate, s);
+}
+
+int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
+                    hipStream_t s) {
+  if (int rc = bucket_cells(c, xyz, s)) return rc;
+  return adjoint_bucketed(c, xyz, gmap, scale, grad, accumulate, s);
 }
 
 }  // namespace p3d

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/place3d.h"
 
@@ -29,6 +30,16 @@ struct ClassTab {       // net schedule: nets and workgroups of each lane-group 
   int32_t block_begin[kNumClasses + 1];
 };
 
+// instance classes for the density path
+constexpr uint8_t kClsCell = 0;    // movable cell bucketed by tile
+constexpr uint8_t kClsLarge = 1;   // movable macro or oversized cell: swept bin-parallel
+constexpr uint8_t kClsFixed = 2;   // fixed: part of the constant map
+
+struct TileGeom {       // map tiles owned by one workgroup each, and the bucketing partition
+  int T, ntx, nty, ntiles;
+  int cpb, nblk;        // cells per bucket block, bucket blocks
+};
+
 struct Geom {
   int n, nx, ny, nz;
   float dx, dy, dz, wb, hb, db, inv_wb, inv_hb, inv_db, half_dz, vol_bin;
@@ -44,8 +55,19 @@ struct DctBases {
 
 }  // namespace p3d
 
+namespace p3d {
+struct ProfRec { int stage; hipEvent_t a, b; };
+}
+
 struct place3d_ctx {
   place3d_problem prob;
+  // optional per-stage event profiler
+  bool prof_on = false;
+  std::vector<p3d::ProfRec> prof_pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
+  double prof_ms[PLACE3D_NSTAGES] = {0};
+  long long prof_count[PLACE3D_NSTAGES] = {0};
+  ~place3d_ctx();
   p3d::Geom g;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -58,10 +80,22 @@ struct place3d_ctx {
   float *rho = nullptr, *phi = nullptr, *ex = nullptr, *ey = nullptr, *ez = nullptr;
   float* fixed_map = nullptr;
   // instances
-  int32_t* movable_macros = nullptr;   // indices of movable macros
-  int32_t n_movable_macros = 0;
-  int32_t* fixed_large = nullptr;      // fixed instances (their map is built once)
+  uint8_t* cls = nullptr;              // [n] kClsCell / kClsLarge / kClsFixed
+  int32_t* large_list = nullptr;       // movable macros and oversized cells
+  int32_t n_large = 0;
+  int32_t* fixed_list = nullptr;       // fixed instances (their map is built once)
   int32_t n_fixed = 0;
+  // tiles and per-call buckets
+  p3d::TileGeom tg = {};
+  int32_t* bk_counts = nullptr;        // [ntiles][nblk] counts, then exclusive offsets
+  int32_t* bk_totals = nullptr;        // [ntiles]
+  int32_t* bk_tile_start = nullptr;    // [ntiles + 1]
+  float4* bk_entries = nullptr;        // [2 * 4n] (cell, tile) entries
+  int32_t* cell_entry = nullptr;       // [4][n] entries of each cell, -1 if none
+  float4* entry_out = nullptr;         // [4n] per-entry gather / adjoint results
+  // two-stage reductions: part[slot * part_stride + block]
+  double* part = nullptr;
+  int32_t part_stride = 0;
   float* npins = nullptr;              // |E_i| as float [n]
   // wirelength schedule (nets ordered by lane-group class)
   int32_t* s_net_start = nullptr;      // [n_sched_nets + 1] slot ranges
@@ -106,6 +140,20 @@ inline unsigned blocks_for(long long n, int threads) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// Profiler brackets (no-ops unless profiling is on).  prof_end records on the same stream.
+int prof_begin(place3d_ctx* c, int stage, hipStream_t s);
+int prof_end(place3d_ctx* c, hipStream_t s);
+
+struct ProfScope {
+  place3d_ctx* c;
+  hipStream_t s;
+  bool on;
+  ProfScope(place3d_ctx* c_, int stage, hipStream_t s_) : c(c_), s(s_), on(c_->prof_on) {
+    if (on) prof_begin(c, stage, s);
+  }
+  ~ProfScope() { if (on) prof_end(c, s); }
+};
+
 // ---- launchers implemented in the .hip sources (all enqueue only) ----
 int launch_zero_f64(place3d_ctx* c, double* p, int n, hipStream_t s);
 int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t s);
@@ -114,13 +162,21 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s);
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
                    double* energy, hipStream_t s);
 
+// out[0..nq) = sums (max if is_max) of partial slots slot0.. over nparts blocks, fixed order
+int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);
+
 int build_fixed_map(place3d_ctx* c, hipStream_t s);
+int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s);
+int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s);
+int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
+                    float* grad, int accumulate, hipStream_t s);
+int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
+                     hipStream_t s);
 int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s);
 int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey,
                          const float* ez, float scale, float* grad, int accumulate, hipStream_t s);
 int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad,
                     int accumulate, hipStream_t s);
-int overflow_reduce(place3d_ctx* c, const float* rho, double* red, hipStream_t s);
 
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
                     double* metrics, hipStream_t s);

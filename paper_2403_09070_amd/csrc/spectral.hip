@@ -377,9 +377,9 @@ __global__ void k_zmix_inv(int plane, int nz, const float* __restrict__ zmat, co
   }
 }
 
-// energy = 1/2 vol(b) sum rho phi
+// partials of 1/2 vol(b) sum rho phi, one per block
 __global__ void k_energy(long long total, const float* __restrict__ rho, const float* __restrict__ phi, float half_vol,
-                         double* __restrict__ out) {
+                         double* __restrict__ part) {
   __shared__ double sh[256 / kWave];
   double s = 0.0;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x)
@@ -391,7 +391,7 @@ __global__ void k_energy(long long total, const float* __restrict__ rho, const f
   if (threadIdx.x == 0) {
     double r = 0.0;
     for (int w = 0; w < 256 / kWave; ++w) r += sh[w];
-    atomicAdd(out, r * (double)half_vol);
+    part[blockIdx.x] = r * (double)half_vol;
   }
 }
 
@@ -401,6 +401,7 @@ int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, const GemmProb* probs,
   a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
   for (int i = 0; i < 4; ++i) a.p[i] = i < nprob ? probs[i] : probs[0];
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nbatch * nprob);
+  ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
   if (c->prob.precision == PLACE3D_BF16X3)
     hipLaunchKernelGGL(k_gemm_bf16x3, grid, dim3(256), 0, s, a);
   else
@@ -446,9 +447,12 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
     GemmProb p = {d.FyT, c->map_t, c->map_a, 0, plane, plane};
     if ((rc = gemm(c, ny, nx, ny, nz, &p, 1, s))) return rc;
   }
-  hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat, d.inv_w2,
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+    hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat, d.inv_w2,
                      c->map_a);
-  P3D_LAUNCH(c, "k_zmix_fwd");
+    P3D_LAUNCH(c, "k_zmix_fwd");
+  }
   // inverse y
   const bool need_g = phi || ex || ez, need_h = ey != nullptr;
   {
@@ -462,9 +466,12 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
   float* ps = ez ? c->map_ps : nullptr;
   float* qc = ey ? c->map_qc : nullptr;
   if (pc || ps || qc) {
-    hipLaunchKernelGGL(k_zmix_inv, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat,
+    {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      hipLaunchKernelGGL(k_zmix_inv, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat,
                        need_g ? c->map_vg : nullptr, need_h ? c->map_vh : nullptr, pc, ps, qc);
-    P3D_LAUNCH(c, "k_zmix_inv");
+      P3D_LAUNCH(c, "k_zmix_inv");
+    }
   }
   // inverse x
   {
@@ -477,11 +484,15 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
     if ((rc = gemm(c, nz * ny, nx, nx, 1, p, np, s))) return rc;
   }
   if (energy) {
-    if ((rc = launch_zero_f64(c, energy, 1, s))) return rc;
     const long long map = plane * nz;
     const unsigned nb = (unsigned)std::min<long long>(blocks_for(map, 256), 1024);
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, s, map, rho, phi, 0.5f * g.vol_bin, energy);
-    P3D_LAUNCH(c, "k_energy");
+    {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, s, map, rho, phi, 0.5f * g.vol_bin,
+                         c->part + (size_t)R_ENERGY * c->part_stride);
+      P3D_LAUNCH(c, "k_energy");
+    }
+    if ((rc = reduce_final(c, R_ENERGY, 1, (int)nb, false, energy, s))) return rc;
   }
   return PLACE3D_OK;
 }

@@ -56,8 +56,9 @@ __device__ __forceinline__ float precond(const Geom& g, const float* __restrict_
   return (float)H;
 }
 
+// per-block partial sums: part[(slot0 + q) * stride + blockIdx.x]
 template <int NQ>
-__device__ __forceinline__ void block_add(double (&v)[NQ], double* __restrict__ out) {
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double* __restrict__ part, int stride, int slot0) {
   __shared__ double sh[NQ][256 / kWave];
   for (int q = 0; q < NQ; ++q) {
     double x = v[q];
@@ -68,7 +69,7 @@ __device__ __forceinline__ void block_add(double (&v)[NQ], double* __restrict__ 
   if (threadIdx.x < NQ) {
     double x = 0.0;
     for (int w = 0; w < 256 / kWave; ++w) x += sh[threadIdx.x][w];
-    atomicAdd(out + threadIdx.x, x);
+    part[(size_t)(slot0 + threadIdx.x) * stride + blockIdx.x] = x;
   }
 }
 
@@ -86,7 +87,7 @@ __global__ void k_clamp_copy(Geom g, const float* __restrict__ size, const uint8
 
 // L1 norms of the wirelength and density gradients over movable instances -> lambda_0
 __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float* __restrict__ gw,
-                           const float* __restrict__ gd, double* __restrict__ red) {
+                           const float* __restrict__ gd, double* __restrict__ part, int stride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
   double v[2] = {0.0, 0.0};
@@ -96,7 +97,7 @@ __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float
       v[1] += fabs((double)gd[a * n + i]);
     }
   }
-  block_add<2>(v, red + R_L1_WL);
+  block_partials<2>(v, part, stride, R_L1_WL);
 }
 
 // g = (gw + lambda gd) / H.  Mode 0 (init): write g to `gout` and track max|g|.  Mode 1 (step):
@@ -106,7 +107,7 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
                           const float* __restrict__ npins, const float* __restrict__ v,
                           const float* __restrict__ v_prev, const float* __restrict__ gw,
                           const float* __restrict__ gd, const double* __restrict__ lam_ptr, int lam_slot,
-                          int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ red) {
+                          int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ part, int stride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
   const double lam = lam_ptr[lam_slot];
@@ -137,13 +138,18 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
     for (int a = 0; a < 3; ++a) gout[a * n + i] = gv[a];
   }
   if (mode == 1) {
-    block_add<4>(acc, red + R_DV2);   // R_DV2, R_DG2, R_Q_BOT, R_Q_TOP
+    block_partials<4>(acc, part, stride, R_DV2);   // R_DV2, R_DG2, R_Q_BOT, R_Q_TOP
   } else {
-    // max |g| via unsigned compare of non-negative float64 bit patterns
+    __shared__ double shm[256 / kWave];
     double m = acc[0];
     for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if ((threadIdx.x & (kWave - 1)) == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(red + R_GMAX), (unsigned long long)__double_as_longlong(m));
+    if ((threadIdx.x & (kWave - 1)) == 0) shm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = 0.0;
+      for (int w = 0; w < 256 / kWave; ++w) r = fmax(r, shm[w]);
+      part[(size_t)R_GMAX * stride + blockIdx.x] = r;
+    }
   }
 }
 
@@ -211,18 +217,20 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
   sc[PLACE3D_S_WL + PLACE3D_M_FDA_SCALE] = nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
 }
 
-// wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red
+// wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red.
+// The cells are bucketed once and the buckets serve the density map and its gradient.
 int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s) {
   int rc;
+  if ((rc = launch_zero_f64(c, red, R_COUNT, s))) return rc;
   if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, s))) return rc;
-  if ((rc = density_forward(c, xyz, c->rho, s))) return rc;
-  if ((rc = overflow_reduce(c, c->rho, red, s))) return rc;
+  if ((rc = bucket_cells(c, xyz, s))) return rc;
+  if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;
-    if ((rc = density_field_gather(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s))) return rc;
+    if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s))) return rc;
   } else {
     if ((rc = spectral_field(c, c->rho, c->phi, nullptr, nullptr, nullptr, red + R_ENERGY, s))) return rc;
-    if ((rc = density_adjoint(c, xyz, c->phi, c->g.vol_bin, gd, 0, s))) return rc;
+    if ((rc = adjoint_bucketed(c, xyz, c->phi, c->g.vol_bin, gd, 0, s))) return rc;
   }
   return PLACE3D_OK;
 }
@@ -251,29 +259,48 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
   const place3d_problem& p = c->prob;
   const unsigned nb = blocks_for(g.n, 256);
   int rc;
-  hipLaunchKernelGGL(k_clamp_copy, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, xyz0, st->u, st->v);
-  P3D_LAUNCH(c, "k_clamp_copy");
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_clamp_copy, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, xyz0, st->u, st->v);
+    P3D_LAUNCH(c, "k_clamp_copy");
+  }
   // gradients at v0, lambda_0
   if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
-  if ((rc = launch_zero_f64(c, c->red2, R_COUNT, s))) return rc;
-  hipLaunchKernelGGL(k_l1_parts, dim3(nb), dim3(256), 0, s, g, p.kind, c->gw, c->den_grad, c->red2);
-  P3D_LAUNCH(c, "k_l1_parts");
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, st->scalars, c->red2);
-  P3D_LAUNCH(c, "k_init_scalars");
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_l1_parts, dim3(nb), dim3(256), 0, s, g, p.kind, c->gw, c->den_grad, c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_l1_parts");
+  }
+  if ((rc = reduce_final(c, R_L1_WL, 2, (int)nb, false, c->red2 + R_L1_WL, s))) return rc;
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, st->scalars, c->red2);
+    P3D_LAUNCH(c, "k_init_scalars");
+  }
   // g0 (into g_prev as scratch) and max|g0|
-  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
                      c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
-                     c->red2);
-  P3D_LAUNCH(c, "k_combine(init)");
-  hipLaunchKernelGGL(k_bootstrap, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->v, st->g_prev, c->red2,
+                     c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_combine(init)");
+  }
+  if ((rc = reduce_final(c, R_GMAX, 1, (int)nb, true, c->red2 + R_GMAX, s))) return rc;
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_bootstrap, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->v, st->g_prev, c->red2,
                      st->v_prev);
-  P3D_LAUNCH(c, "k_bootstrap");
+    P3D_LAUNCH(c, "k_bootstrap");
+  }
   // preconditioned gradient at v_prev
   if ((rc = eval_parts(c, st->v_prev, c->gw, c->den_grad, c->red, s))) return rc;
-  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v_prev, st->v_prev,
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v_prev, st->v_prev,
                      c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
-                     c->red2);
-  P3D_LAUNCH(c, "k_combine(init2)");
+                     c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_combine(init2)");
+  }
   return PLACE3D_OK;
 }
 
@@ -286,14 +313,24 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
   const unsigned nb = blocks_for(g.n, 256);
   int rc;
   if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
-  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
                      c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 1, st->g_prev,
-                     c->red);
-  P3D_LAUNCH(c, "k_combine");
-  hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, st->u, st->v,
+                     c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_combine");
+  }
+  if ((rc = reduce_final(c, R_DV2, 4, (int)nb, false, c->red + R_DV2, s))) return rc;
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, st->u, st->v,
                      st->v_prev, st->g_prev);
-  P3D_LAUNCH(c, "k_nesterov");
-  hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, s, st->scalars, c->red, p.lambda_ramp);
-  P3D_LAUNCH(c, "k_step_finish");
+    P3D_LAUNCH(c, "k_nesterov");
+  }
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, s, st->scalars, c->red, p.lambda_ramp);
+    P3D_LAUNCH(c, "k_step_finish");
+  }
   return PLACE3D_OK;
 }

@@ -191,7 +191,7 @@ __device__ __forceinline__ float axis_grad(const AxisWA& a, DF u, bool top, floa
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     int n, float half_dz, float four_over_dz, float gamma, float alpha, const float* __restrict__ xyz,
     const int32_t* __restrict__ s_net_start, const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
-    float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ red) {
+    float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part, int stride) {
   __shared__ double shred[5][kWaBlock / kWave];
   __shared__ int cls_s;
   if (threadIdx.x == 0) {
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   if (threadIdx.x < 5) {
     double x = 0.0;
     for (int w = 0; w < kWaBlock / kWave; ++w) x += shred[threadIdx.x][w];
-    atomicAdd(red + R_WA_BI + threadIdx.x, x);
+    part[(size_t)(R_WA_BI + threadIdx.x) * stride + blockIdx.x] = x;
   }
 }
 
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
 __global__ void k_wl_gather(int n, const uint8_t* __restrict__ kind, const int32_t* __restrict__ node_slot_start,
                             const int32_t* __restrict__ node_slots, const float4* __restrict__ pin_out,
                             float* __restrict__ grad, int accumulate, float* __restrict__ gz_wa,
-                            float* __restrict__ fda, double* __restrict__ red) {
+                            float* __restrict__ fda, double* __restrict__ part, int stride) {
   __shared__ double sh[3][256 / kWave];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float gx = 0.f, gy = 0.f, gz = 0.f, gf = 0.f;
@@ -358,7 +358,7 @@ __global__ void k_wl_gather(int n, const uint8_t* __restrict__ kind, const int32
   if (threadIdx.x < 3) {
     double x = 0.0;
     for (int w = 0; w < 256 / kWave; ++w) x += sh[threadIdx.x][w];
-    atomicAdd(red + R_NORM_X + threadIdx.x, x);
+    part[(size_t)(R_NORM_X + threadIdx.x) * stride + blockIdx.x] = x;
   }
 }
 
@@ -392,19 +392,28 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
   const Geom& g = c->g;
   const place3d_problem& p = c->prob;
   int rc;
-  if ((rc = launch_zero_f64(c, red, R_COUNT, s))) return rc;
   if (c->n_wa_blocks > 0) {
+    ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
     hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.n, g.half_dz, 4.f / g.dz,
                        (float)p.gamma, (float)p.alpha, xyz, c->s_net_start, c->s_pin_node, c->s_off, c->pin_out,
-                       c->classes, red);
+                       c->classes, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
   }
-  hipLaunchKernelGGL(k_wl_gather, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, p.kind, c->node_slot_start,
-                     c->node_slots, c->pin_out, grad, accumulate, c->wl_gzwa, c->wl_fda, red);
-  P3D_LAUNCH(c, "k_wl_gather");
-  hipLaunchKernelGGL(k_wl_finish_z, dim3(blocks_for(std::max(g.n, (int)PLACE3D_NMETRICS), 256)), dim3(256), 0, s,
-                     g.n, c->wl_gzwa, c->wl_fda, red, grad, accumulate, metrics);
-  P3D_LAUNCH(c, "k_wl_finish_z");
+  if ((rc = reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, red + R_WA_BI, s))) return rc;
+  const unsigned nb = blocks_for(g.n, 256);
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
+    hipLaunchKernelGGL(k_wl_gather, dim3(nb), dim3(256), 0, s, g.n, p.kind, c->node_slot_start, c->node_slots,
+                       c->pin_out, grad, accumulate, c->wl_gzwa, c->wl_fda, c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_wl_gather");
+  }
+  if ((rc = reduce_final(c, R_NORM_X, 3, (int)nb, false, red + R_NORM_X, s))) return rc;
+  {
+    ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
+    hipLaunchKernelGGL(k_wl_finish_z, dim3(blocks_for(std::max(g.n, (int)PLACE3D_NMETRICS), 256)), dim3(256), 0, s,
+                       g.n, c->wl_gzwa, c->wl_fda, red, grad, accumulate, metrics);
+    P3D_LAUNCH(c, "k_wl_finish_z");
+  }
   return PLACE3D_OK;
 }
 

@@ -25,6 +25,7 @@ KIND_MACRO, KIND_FIXED = 1, 2
 NMETRICS, NSCALARS = 16, 32
 M = dict(wa_bi=0, wa_z=1, hpwl=2, hpwl3d=3, ncut=4, norm_x=5, norm_y=6, norm_fda=7, fda_scale=8)
 S = dict(a=0, lam=1, step=2, it=3, ovfl_bot=4, ovfl_top=5, energy=6, wl=8)
+STAGES = ("density", "gemm", "zmix", "dgrad", "wl_nets", "wl_nodes", "update")
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SIZE", -3: "ERR_HIP", -4: "ERR_NONFINITE",
           -5: "ERR_UNSUPPORTED", -6: "ERR_NETLIST"}
 
@@ -75,6 +76,9 @@ def lib():
             "place3d_wl_grad": (i32, [vp, vp, vp, vp, i32, vp]),
             "place3d_gp_init": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
             "place3d_step": (i32, [vp, ctypes.POINTER(State_), vp]),
+            "place3d_profile_enable": (i32, [vp, i32]),
+            "place3d_profile_read": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64), i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -247,6 +251,20 @@ class Problem:
         cs = st.cstruct()
         _check(lib().place3d_gp_init(self._ctx, ctypes.byref(cs), _ptr(xyz0), _stream()), self._ctx)
         return st
+
+    def profile(self, on=True):
+        _check(lib().place3d_profile_enable(self._ctx, int(on)), self._ctx)
+
+    def profile_read(self, reset=True):
+        """{stage: (gpu milliseconds, launches)} since the last reset (waits for the events)."""
+        out = {}
+        for k, name in enumerate(STAGES):
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            last = reset and k == len(STAGES) - 1
+            _check(lib().place3d_profile_read(self._ctx, k, ctypes.byref(ms), ctypes.byref(cnt), int(last)),
+                   self._ctx)
+            out[name] = (ms.value, cnt.value)
+        return out
 
     def step(self, state):
         cs = state.cstruct()

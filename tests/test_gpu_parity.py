@@ -27,6 +27,7 @@ CASES = {
     "tiny": lambda: tiny_case(5),
     "ragged": lambda: ragged_case(6),
     "c1": lambda: synth.make_case("c1", 2403),
+    "c2": lambda: synth.make_case("c2", 2403),
 }
 
 
