@@ -69,7 +69,7 @@ p3d::TileGeom tile_geom(const place3d_problem& p) {
 }
 
 int parts_bound(const place3d_problem& p, const p3d::TileGeom& t) {
-  int b = std::max(p.n_nets / 4 + 16, p.n_inst / 256 + 2);
+  int b = std::max(p.n_nets / 4 + 16, p.n_inst / 256 + p.n_pins / 128 + 8);
   b = std::max(b, t.ntiles);
   b = std::max(b, t.nblk);
   return std::max(b, 1024);
@@ -94,6 +94,9 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->fixed_map = w.take<float>(map);
   c->cls = w.take<uint8_t>(n);
   c->large_list = w.take<int32_t>(n);
+  c->large_rec = w.take<float4>(4 * n);
+  c->lpart_cap = std::min<long long>((long long)n * c->tg.ntiles, 1ll << 22);
+  c->lpart = w.take<float4>(2 * (size_t)c->lpart_cap);
   c->fixed_list = w.take<int32_t>(n);
   c->bk_counts = w.take<int32_t>((size_t)c->tg.ntiles * c->tg.nblk);
   c->bk_totals = w.take<int32_t>(c->tg.ntiles);
@@ -108,7 +111,8 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->s_off = w.take<float4>(P + 1);
   c->pin_out = w.take<float4>(P + 1);
   c->node_slot_start = w.take<int32_t>(n + 1);
-  c->node_slots = w.take<int32_t>(P + 1);
+  c->slot_pos = w.take<int32_t>(P + 1);
+  c->heavy_list = w.take<int32_t>(n);
   c->wl_gzwa = w.take<float>(n);
   c->gw = w.take<float>(3 * n);
   c->wl_fda = w.take<float>(n);
@@ -206,11 +210,20 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   for (int q = 0; q < P; ++q) nss[p2n[q] + 1]++;
   for (int i = 0; i < n; ++i) nss[i + 1] += nss[i];
   {
+    // position of every slot in node order (slots ascending per node): the net kernel writes a
+    // pin's results there, so each node's shares are contiguous for the node-side sum
     std::vector<int32_t> fill(nss.begin(), nss.end() - 1);
-    for (int sl = 0; sl < slot; ++sl) nsl[fill[spn[sl]]++] = sl;
+    for (int sl = 0; sl < slot; ++sl) nsl[sl] = fill[spn[sl]]++;
   }
   std::vector<float> npins(n);
-  for (int i = 0; i < n; ++i) npins[i] = (float)(nss[i + 1] - nss[i]);
+  std::vector<int32_t> heavy;
+  for (int i = 0; i < n; ++i) {
+    npins[i] = (float)(nss[i + 1] - nss[i]);
+    if (nss[i + 1] - nss[i] > 32) heavy.push_back(i);
+  }
+  c->n_heavy = (int32_t)heavy.size();
+  if (!heavy.empty())
+    P3D_HIP(c, hipMemcpyAsync(c->heavy_list, heavy.data(), sizeof(int32_t) * heavy.size(), hipMemcpyHostToDevice, s));
 
   // density classes: bucketed cells must span at most two tiles per axis on either die
   std::vector<int32_t> large, fixed;
@@ -234,7 +247,7 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   if (P > 0) {
     P3D_HIP(c, hipMemcpyAsync(c->s_pin_node, spn.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
     P3D_HIP(c, hipMemcpyAsync(c->s_off, soff.data(), sizeof(float) * 4 * (size_t)P, hipMemcpyHostToDevice, s));
-    P3D_HIP(c, hipMemcpyAsync(c->node_slots, nsl.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+    P3D_HIP(c, hipMemcpyAsync(c->slot_pos, nsl.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
   }
   P3D_HIP(c, hipMemcpyAsync(c->node_slot_start, nss.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
   P3D_HIP(c, hipMemcpyAsync(c->npins, npins.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));

@@ -115,6 +115,21 @@ __device__ __forceinline__ Foot foot_entry(const Geom& g, float4 a, float4 b) {
   return f;
 }
 
+// Large-instance record, computed once per call: [0] (cbx | cby << 16, rx, ry, z), [1] (hw, hh,
+// omega, w), [2] (h, dw, dh, -), [3] (bx0, bx1, by0, by1) as integers.
+__device__ __forceinline__ Foot foot_record(const Geom& g, const float4* __restrict__ rec, int j) {
+  const float4 a = rec[4 * (size_t)j], b = rec[4 * (size_t)j + 1], c = rec[4 * (size_t)j + 2];
+  Foot f;
+  const unsigned packed = __float_as_uint(a.x);
+  foot_local(g, f, (int)(packed & 0xFFFFu), (int)(packed >> 16), a.y, a.z, a.w, b.x, b.y);
+  f.omega = b.z;
+  f.w = b.w;
+  f.h = c.x;
+  f.dw = c.y;
+  f.dh = c.z;
+  return f;
+}
+
 // overlap lengths of the clipped cuboid with bin b along each axis
 __device__ __forceinline__ float len_x(const Geom& g, const Foot& f, int b) {
   const float lo = (float)(b - f.cbx) * g.wb;
@@ -301,6 +316,43 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(Geom g, TileGeom t, cons
   }
 }
 
+__global__ void k_large_records(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
+                                const uint8_t* __restrict__ kind, const int32_t* __restrict__ large, int nlarge,
+                                float4* __restrict__ rec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nlarge) return;
+  const int i = large[j];
+  const Foot f = footprint(g, xyz, size, kind[i], i);
+  rec[4 * (size_t)j] = make_float4(__uint_as_float((unsigned)f.cbx | ((unsigned)f.cby << 16)), f.rx, f.ry, f.z);
+  rec[4 * (size_t)j + 1] = make_float4(f.hw, f.hh, f.omega, f.w);
+  rec[4 * (size_t)j + 2] = make_float4(f.h, f.dw, f.dh, 0.f);
+  rec[4 * (size_t)j + 3] = make_float4(__int_as_float(f.bx0), __int_as_float(f.bx1), __int_as_float(f.by0),
+                                       __int_as_float(f.by1));
+}
+
+// Compacts, in list order, the large instances whose records overlap the tile: chunks of the
+// block size are tested in parallel; `hits` receives record indices, returns the count of the
+// current chunk.  All threads must call it with the same chunk.
+__device__ __forceinline__ int large_hits(const float4* __restrict__ rec, int nlarge, int chunk, int x0, int x1, int y0,
+                                          int y1, int* hits, int* wave_cnt) {
+  const int j = chunk + threadIdx.x;
+  bool hit = false;
+  if (j < nlarge) {
+    const float4 b = rec[4 * (size_t)j + 3];
+    hit = !(__float_as_int(b.y) < x0 || __float_as_int(b.x) > x1 || __float_as_int(b.w) < y0 || __float_as_int(b.z) > y1);
+  }
+  const unsigned long long mask = __ballot(hit);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) wave_cnt[wid] = __popcll(mask);
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) { if (w < wid) base += wave_cnt[w]; total += wave_cnt[w]; }
+  if (hit) hits[base + __popcll(mask & ((1ull << lane) - 1ull))] = j;
+  __syncthreads();
+  return total;
+}
+
 // ------------------------------------------------------------------ tiled density map
 
 struct TileBox { int x0, y0, wx, wy; };
@@ -317,38 +369,48 @@ __device__ __forceinline__ TileBox tile_box(const Geom& g, const TileGeom& t, in
 
 __device__ __forceinline__ int lds_index(const TileGeom& t, int bz, int ly, int lx) { return (bz * t.T + ly) * t.T + lx; }
 
+// The tile accumulates in 64-bit fixed point (2^-32 units): integer LDS atomics run at full rate
+// where float LDS atomics serialise across lanes, and integer sums do not depend on the order in
+// which cells arrive, so the map is reproducible bit for bit.
+constexpr float kFix = 4294967296.f;          // 2^32
+constexpr double kUnfix = 1.0 / 4294967296.0;
+
+__device__ __forceinline__ unsigned long long to_fix(float v) { return __float2ull_rn(v * kFix); }
+
 __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
-                                                       const float* __restrict__ fixed_map, const float* __restrict__ xyz,
-                                                       const float* __restrict__ size, const uint8_t* __restrict__ kind,
-                                                       const int32_t* __restrict__ large, int nlarge, float target,
+                                                       const float* __restrict__ fixed_map,
+                                                       const float4* __restrict__ lrec, int nlarge, float target,
                                                        float* __restrict__ rho, double* __restrict__ part, int stride) {
-  extern __shared__ float S[];
+  extern __shared__ unsigned long long S64[];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
-    S[k] = (lx < tb.wx && ly < tb.wy) ? fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
+    S64[k] = (lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)]) : 0ull;
   }
   __syncthreads();
   // large instances: bin-parallel sweep of their part of this tile
+  __shared__ int hits[256];
+  __shared__ int wave_cnt[256 / kWave];
   const float inv_vol = 1.f / g.vol_bin;
-  for (int j = 0; j < nlarge; ++j) {
-    const int i = large[j];
-    const Foot f = footprint(g, xyz, size, kind[i], i);
-    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
-    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
-    if (bx0 > bx1 || by0 > by1) continue;
-    const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = f.bz1 - f.bz0 + 1;
-    const int total = nbx * nby * nbz;
-    const float wgt = f.omega * inv_vol;
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = f.bz0 + q / (nbx * nby);
-      const float v = len_x(g, f, bx) * len_y(g, f, by) * len_z(g, f, bz) * wgt;
-      S[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += v;   // one thread per bin within one instance
+  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
+    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+    for (int r = 0; r < nh; ++r) {
+      const Foot h = foot_record(g, lrec, hits[r]);
+      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+      const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
+      const int total_bins = nbx * nby * nbz;
+      const float wgt = h.omega * inv_vol;
+      for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
+        const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
+        const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz) * wgt;
+        S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix(v);   // one thread per bin within one instance
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // bucketed cells
   const int e1 = tile_start[tile + 1];
@@ -363,7 +425,7 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
         const float lyz = len_y(g, f, by) * lz;
         for (int bx = bx0; bx <= bx1; ++bx) {
           const float v = len_x(g, f, bx) * lyz;
-          if (v != 0.f) atomicAdd(&S[lds_index(t, bz, by - tb.y0, bx - tb.x0)], v);
+          if (v != 0.f) atomicAdd(&S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix(v));
         }
       }
     }
@@ -374,7 +436,7 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
     if (lx < tb.wx && ly < tb.wy) {
-      const float v = S[k];
+      const float v = (float)((double)S64[k] * kUnfix);
       rho[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] = v;
       ex[bz < half ? 0 : 1] += fmaxf(v - target, 0.f) * g.vol_bin;
     }
@@ -431,12 +493,18 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
 
 // ------------------------------------------------------------------ field gather
 
-// every (cell, tile) entry: sum over the tile's bins of overlap * map, for three maps
+// every (cell, tile) entry: sum over the tile's bins of overlap * map, for three maps; then, for
+// every large instance overlapping the tile, its partial sums over the tile (to lpart[j][tile])
 __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                       const int32_t* __restrict__ tile_start,
                                                       const float* __restrict__ mx, const float* __restrict__ my,
-                                                      const float* __restrict__ mz, float4* __restrict__ out) {
+                                                      const float* __restrict__ mz, float4* __restrict__ out,
+                                                      const float4* __restrict__ lrec, int nlarge,
+                                                      float4* __restrict__ lpart) {
   extern __shared__ float S[];
+  __shared__ int hits[256];
+  __shared__ int wave_cnt[256 / kWave];
+  __shared__ float rsh[3][256 / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
@@ -469,6 +537,64 @@ __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const 
       }
     }
     out[e] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
+  }
+  if (!lpart) return;
+  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
+    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+    for (int r = 0; r < nh; ++r) {
+      const int j = hits[r];
+      const Foot h = foot_record(g, lrec, j);
+      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+      const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
+      const int total_bins = nbx * nby * nbz;
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
+        const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
+        const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz);
+        const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
+        sx += v * S[k];
+        sy += v * S[tsz + k];
+        sz += v * S[2 * tsz + k];
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o); sy += __shfl_xor(sy, o); sz += __shfl_xor(sz, o);
+      }
+      if ((threadIdx.x & (kWave - 1)) == 0) {
+        rsh[0][threadIdx.x / kWave] = sx; rsh[1][threadIdx.x / kWave] = sy; rsh[2][threadIdx.x / kWave] = sz;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float a = 0.f, b = 0.f, c = 0.f;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) { a += rsh[0][w]; b += rsh[1][w]; c += rsh[2][w]; }
+        lpart[(size_t)j * t.ntiles + tile] = make_float4(h.omega * a, h.omega * b, h.omega * c, 0.f);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// per large instance (one wavefront each): sum the partials of the tiles its record overlaps
+__global__ void k_large_gather_finish(Geom g, TileGeom t, const int32_t* __restrict__ large, int nlarge,
+                                      const float4* __restrict__ lrec, const float4* __restrict__ lpart, float scale,
+                                      float* __restrict__ grad, int accumulate) {
+  const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (j >= nlarge) return;
+  const float4 b = lrec[4 * (size_t)j + 3];
+  const int tx0 = __float_as_int(b.x) / t.T, tx1 = __float_as_int(b.y) / t.T;
+  const int ty0 = __float_as_int(b.z) / t.T, ty1 = __float_as_int(b.w) / t.T;
+  const int ntx = tx1 - tx0 + 1, count = ntx * (ty1 - ty0 + 1);
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  for (int q = lane; q < count; q += kWave) {
+    const float4 v = lpart[(size_t)j * t.ntiles + (ty0 + q / ntx) * t.ntx + tx0 + q % ntx];
+    sx += v.x; sy += v.y; sz += v.z;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) { sx += __shfl_xor(sx, o); sy += __shfl_xor(sy, o); sz += __shfl_xor(sz, o); }
+  if (lane == 0) {
+    const int i = large[j], n = g.n;
+    if (accumulate) { grad[i] += scale * sx; grad[n + i] += scale * sy; grad[2 * n + i] += scale * sz; }
+    else { grad[i] = scale * sx; grad[n + i] = scale * sy; grad[2 * n + i] = scale * sz; }
   }
 }
 
@@ -564,8 +690,13 @@ __device__ __forceinline__ float3 adjoint_finish(const Geom& g, const Foot& f, c
 
 __global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
-                                                       const float* __restrict__ m, float4* __restrict__ out) {
+                                                       const float* __restrict__ m, float4* __restrict__ out,
+                                                       const float4* __restrict__ lrec, int nlarge,
+                                                       float4* __restrict__ lpart) {
   extern __shared__ float S[];
+  __shared__ int hits[256];
+  __shared__ int wave_cnt[256 / kWave];
+  __shared__ float rsh[6][256 / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
@@ -574,6 +705,7 @@ __global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const
     S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
   }
   __syncthreads();
+  auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
   const int e1 = tile_start[tile + 1];
   for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
     const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
@@ -581,11 +713,65 @@ __global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     float3 r = make_float3(0.f, 0.f, 0.f);
     if (bx0 <= bx1 && by0 <= by1) {
-      auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
       const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, 0, 1, false);
       r = adjoint_finish(g, f, a);
     }
     out[e] = make_float4(r.x, r.y, r.z, 0.f);
+  }
+  if (!lpart) return;
+  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
+    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+    for (int r = 0; r < nh; ++r) {
+      const int j = hits[r];
+      const Foot h = foot_record(g, lrec, j);
+      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+      AdjSums a = adjoint_sums(g, h, at, bx0, bx1, by0, by1, threadIdx.x, blockDim.x, true);
+      float v[6] = {a.gx, a.gy, a.gz, a.xs, a.ys, a.all};
+      for (int q = 0; q < 6; ++q) {
+        for (int o = kWave / 2; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        if ((threadIdx.x & (kWave - 1)) == 0) rsh[q][threadIdx.x / kWave] = v[q];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 6; ++q)
+          for (int u = 0; u < (int)(blockDim.x / kWave); ++u) w[q] += rsh[q][u];
+        lpart[2 * ((size_t)j * t.ntiles + tile)] = make_float4(w[0], w[1], w[2], 0.f);
+        lpart[2 * ((size_t)j * t.ntiles + tile) + 1] = make_float4(w[3], w[4], w[5], 0.f);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_large_adjoint_finish(Geom g, TileGeom t, const int32_t* __restrict__ large, int nlarge,
+                                       const float4* __restrict__ lrec, const float4* __restrict__ lpart, float scale,
+                                       float* __restrict__ grad, int accumulate) {
+  const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (j >= nlarge) return;
+  const float4 b = lrec[4 * (size_t)j + 3];
+  const int tx0 = __float_as_int(b.x) / t.T, tx1 = __float_as_int(b.y) / t.T;
+  const int ty0 = __float_as_int(b.z) / t.T, ty1 = __float_as_int(b.w) / t.T;
+  const int ntx = tx1 - tx0 + 1, count = ntx * (ty1 - ty0 + 1);
+  AdjSums a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int q = lane; q < count; q += kWave) {
+    const size_t k = 2 * ((size_t)j * t.ntiles + (ty0 + q / ntx) * t.ntx + tx0 + q % ntx);
+    const float4 u = lpart[k], w = lpart[k + 1];
+    a.gx += u.x; a.gy += u.y; a.gz += u.z; a.xs += w.x; a.ys += w.y; a.all += w.z;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    a.gx += __shfl_xor(a.gx, o); a.gy += __shfl_xor(a.gy, o); a.gz += __shfl_xor(a.gz, o);
+    a.xs += __shfl_xor(a.xs, o); a.ys += __shfl_xor(a.ys, o); a.all += __shfl_xor(a.all, o);
+  }
+  if (lane == 0) {
+    const Foot f = foot_record(g, lrec, j);
+    const float3 r = adjoint_finish(g, f, a);
+    const float s = scale / g.vol_bin;
+    const int i = large[j], n = g.n;
+    if (accumulate) { grad[i] += s * r.x; grad[n + i] += s * r.y; grad[2 * n + i] += s * r.z; }
+    else { grad[i] = s * r.x; grad[n + i] = s * r.y; grad[2 * n + i] = s * r.z; }
   }
 }
 
@@ -678,6 +864,11 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
   ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
+  if (c->n_large > 0) {
+    hipLaunchKernelGGL(k_large_records, dim3(blocks_for(c->n_large, 256)), dim3(256), 0, s, g, xyz, p.size, p.kind,
+                       c->large_list, c->n_large, c->large_rec);
+    P3D_LAUNCH(c, "k_large_records");
+  }
   const size_t hist = sizeof(int) * t.ntiles;
   hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls, c->bk_counts,
                      c->cell_entry);
@@ -698,9 +889,9 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
   const place3d_problem& p = c->prob;
   {
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
-    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 1), s, g, t, c->bk_entries,
-                       c->bk_tile_start, c->fixed_map, xyz, p.size, p.kind, c->large_list, c->n_large,
-                       (float)p.target_density, rho, c->part, c->part_stride);
+    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(256), 2 * tile_lds(c, 1), s, g, t, c->bk_entries,
+                       c->bk_tile_start, c->fixed_map, c->large_rec, c->n_large, (float)p.target_density, rho,
+                       c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
   }
   return reduce_final(c, R_EXCESS_BOT, 2, t.ntiles, false, red + R_EXCESS_BOT, s);
@@ -711,16 +902,27 @@ int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s)
   return density_tiles(c, xyz, rho, c->red2, s);
 }
 
+// large instances go through the tiles when their per-tile partials fit the workspace
+static bool large_in_tiles(const place3d_ctx* c) {
+  return (long long)c->n_large * c->tg.ntiles <= c->lpart_cap;
+}
+
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
                     float* grad, int accumulate, hipStream_t s) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
+  const bool tiled = large_in_tiles(c);
   ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
   hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 3), s, g, t, c->bk_entries,
-                     c->bk_tile_start, ex, ey, ez, c->entry_out);
+                     c->bk_tile_start, ex, ey, ez, c->entry_out, c->large_rec, c->n_large,
+                     tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_gather_tiles");
-  if (c->n_large > 0) {
+  if (c->n_large > 0 && tiled) {
+    hipLaunchKernelGGL(k_large_gather_finish, dim3(blocks_for(c->n_large, 256 / kWave)), dim3(256), 0, s, g, t,
+                       c->large_list, c->n_large, c->large_rec, c->lpart, scale, grad, accumulate);
+    P3D_LAUNCH(c, "k_large_gather_finish");
+  } else if (c->n_large > 0) {
     hipLaunchKernelGGL(k_gather_large, dim3(c->n_large), dim3(256), 0, s, g, xyz, p.size, p.kind, c->large_list, ex,
                        ey, ez, scale, grad, accumulate);
     P3D_LAUNCH(c, "k_gather_large");
@@ -736,11 +938,17 @@ int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float 
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
+  const bool tiled = large_in_tiles(c);
   ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
   hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 1), s, g, t, c->bk_entries,
-                     c->bk_tile_start, gmap, c->entry_out);
+                     c->bk_tile_start, gmap, c->entry_out, c->large_rec, c->n_large,
+                     tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_adjoint_tiles");
-  if (c->n_large > 0) {
+  if (c->n_large > 0 && tiled) {
+    hipLaunchKernelGGL(k_large_adjoint_finish, dim3(blocks_for(c->n_large, 256 / kWave)), dim3(256), 0, s, g, t,
+                       c->large_list, c->n_large, c->large_rec, c->lpart, scale, grad, accumulate);
+    P3D_LAUNCH(c, "k_large_adjoint_finish");
+  } else if (c->n_large > 0) {
     hipLaunchKernelGGL(k_adjoint_large, dim3(c->n_large), dim3(256), 0, s, g, xyz, p.size, p.kind, c->large_list, gmap,
                        scale, grad, accumulate);
     P3D_LAUNCH(c, "k_adjoint_large");

@@ -83,6 +83,9 @@ struct place3d_ctx {
   uint8_t* cls = nullptr;              // [n] kClsCell / kClsLarge / kClsFixed
   int32_t* large_list = nullptr;       // movable macros and oversized cells
   int32_t n_large = 0;
+  float4* large_rec = nullptr;         // [4 * n_large] per-call footprint records of large instances
+  float4* lpart = nullptr;             // [2 * lpart_cap] per (large instance, tile) partial sums
+  long long lpart_cap = 0;
   int32_t* fixed_list = nullptr;       // fixed instances (their map is built once)
   int32_t n_fixed = 0;
   // tiles and per-call buckets
@@ -101,9 +104,11 @@ struct place3d_ctx {
   int32_t* s_net_start = nullptr;      // [n_sched_nets + 1] slot ranges
   int32_t* s_pin_node = nullptr;       // [n_pins] owner per slot
   float4* s_off = nullptr;             // [n_pins] (ox_bot, oy_bot, ox_top, oy_top) per slot
-  float4* pin_out = nullptr;           // [n_pins] (gx, gy, gz_wa, fda) per slot
-  int32_t* node_slot_start = nullptr;  // [n+1]
-  int32_t* node_slots = nullptr;       // [n_pins]
+  float4* pin_out = nullptr;           // [n_pins] (gx, gy, gz_wa, fda) in node order
+  int32_t* node_slot_start = nullptr;  // [n+1] node -> range of pin_out
+  int32_t* slot_pos = nullptr;         // [n_pins] slot -> position in node order
+  int32_t* heavy_list = nullptr;       // instances with more than 32 pins (summed per wavefront)
+  int32_t n_heavy = 0;
   p3d::ClassTab classes = {};
   int32_t n_wa_blocks = 0;
   // per-instance scratch

@@ -134,6 +134,7 @@ struct AxisWA {        // smoothed WA pieces along one axis, for the gradient of
   float Mt, At_p, st_p, mt, At_m, st_m;   // top set: shift and (A - shift) terms
   float Mb, Ab_p, sb_p, mb, Ab_m, sb_m;   // bottom set
   float Me, Ae_p, se_p, me, Ae_m, se_m;   // whole net
+  float rt, rb, qt, qb;                   // e^{(M_S - M_e)/gamma}, e^{-(m_S - m_e)/gamma} per set
   bool split;
   float W;                                  // smoothed value
 };
@@ -149,6 +150,7 @@ __device__ __forceinline__ AxisWA axis_wa(const Ext& T, const SetSums& st, int c
   a.At_m = ct > 0 ? st.tm / st.sm : 0.f;
   a.Ab_p = cb > 0 ? sb.tp / sb.sp : 0.f;
   a.Ab_m = cb > 0 ? sb.tm / sb.sm : 0.f;
+  a.rt = a.rb = a.qt = a.qb = 1.f;
   const float pt = ct > 0 ? (a.Mt - a.mt) + (a.At_p - a.At_m) : 0.f;
   const float pb = cb > 0 ? (a.Mb - a.mb) + (a.Ab_p - a.Ab_m) : 0.f;
   // whole net: rescale the partial sums to the whole-net shifts
@@ -156,13 +158,15 @@ __device__ __forceinline__ AxisWA axis_wa(const Ext& T, const SetSums& st, int c
     a.Me = fmaxf(a.Mt, a.Mb);
     a.me = fminf(a.mt, a.mb);
     const float dt = a.Mt - a.Me, db = a.Mb - a.Me;                 // <= 0
-    const float rt = __expf(dt * inv_gamma), rb = __expf(db * inv_gamma);
-    a.se_p = st.sp * rt + sb.sp * rb;
-    const float te_p = rt * (st.tp + dt * st.sp) + rb * (sb.tp + db * sb.sp);
+    a.rt = __expf(dt * inv_gamma);
+    a.rb = __expf(db * inv_gamma);
+    a.se_p = st.sp * a.rt + sb.sp * a.rb;
+    const float te_p = a.rt * (st.tp + dt * st.sp) + a.rb * (sb.tp + db * sb.sp);
     const float dtm = a.mt - a.me, dbm = a.mb - a.me;              // >= 0
-    const float qt = __expf(-dtm * inv_gamma), qb = __expf(-dbm * inv_gamma);
-    a.se_m = st.sm * qt + sb.sm * qb;
-    const float te_m = qt * (st.tm + dtm * st.sm) + qb * (sb.tm + dbm * sb.sm);
+    a.qt = __expf(-dtm * inv_gamma);
+    a.qb = __expf(-dbm * inv_gamma);
+    a.se_m = st.sm * a.qt + sb.sm * a.qb;
+    const float te_m = a.qt * (st.tm + dtm * st.sm) + a.qb * (sb.tm + dbm * sb.sm);
     a.Ae_p = te_p / a.se_p;
     a.Ae_m = te_m / a.se_m;
   } else if (ct > 0) {
@@ -176,22 +180,64 @@ __device__ __forceinline__ AxisWA axis_wa(const Ext& T, const SetSums& st, int c
   return a;
 }
 
-// d W^ / d u for one pin of the chosen branch
-__device__ __forceinline__ float axis_grad(const AxisWA& a, DF u, bool top, float inv_gamma) {
-  float M, Ap, sp, m, Am, sm;
-  if (!a.split) { M = a.Me; Ap = a.Ae_p; sp = a.se_p; m = a.me; Am = a.Ae_m; sm = a.se_m; }
-  else if (top) { M = a.Mt; Ap = a.At_p; sp = a.st_p; m = a.mt; Am = a.At_m; sm = a.st_m; }
-  else { M = a.Mb; Ap = a.Ab_p; sp = a.sb_p; m = a.mb; Am = a.Ab_m; sm = a.sb_m; }
-  const float du = (u.h - M) + u.l;       // u - M  (<= 0)
-  const float dl = (u.h - m) + u.l;       // u - m  (>= 0)
-  const float ep = __expf(du * inv_gamma), em = __expf(-dl * inv_gamma);
-  return ep / sp * (1.f + (du - Ap) * inv_gamma) - em / sm * (1.f - (dl - Am) * inv_gamma);
+// a pin's offsets from its set's shifts and the shifted exponentials (phase B), kept for phase C
+struct PinExp { float dux, dlx, epx, emx, duy, dly, epy, emy, duz, dlz, epz, emz; };
+
+__device__ __forceinline__ PinExp pin_exps(const PinData& p, const Ext& tx, const Ext& bx, const Ext& ty,
+                                           const Ext& by, float zmax, float zmin, float inv_gamma) {
+  PinExp e;
+  const float Mx = p.top ? tx.mx.a1.h : bx.mx.a1.h, mx = p.top ? tx.mn.a1.h : bx.mn.a1.h;
+  const float My = p.top ? ty.mx.a1.h : by.mx.a1.h, my = p.top ? ty.mn.a1.h : by.mn.a1.h;
+  e.dux = (p.ux.h - Mx) + p.ux.l; e.dlx = (p.ux.h - mx) + p.ux.l;
+  e.duy = (p.uy.h - My) + p.uy.l; e.dly = (p.uy.h - my) + p.uy.l;
+  e.duz = p.z - zmax; e.dlz = p.z - zmin;
+  e.epx = __expf(e.dux * inv_gamma); e.emx = __expf(-e.dlx * inv_gamma);
+  e.epy = __expf(e.duy * inv_gamma); e.emy = __expf(-e.dly * inv_gamma);
+  e.epz = __expf(e.duz * inv_gamma); e.emz = __expf(-e.dlz * inv_gamma);
+  return e;
 }
+
+__device__ __forceinline__ void add_sums(const PinExp& e, bool top, SetSums& sxt, SetSums& sxb, SetSums& syt,
+                                         SetSums& syb, SetSums& sz) {
+  if (top) {
+    sxt.sp += e.epx; sxt.tp += e.dux * e.epx; sxt.sm += e.emx; sxt.tm += e.dlx * e.emx;
+    syt.sp += e.epy; syt.tp += e.duy * e.epy; syt.sm += e.emy; syt.tm += e.dly * e.emy;
+  } else {
+    sxb.sp += e.epx; sxb.tp += e.dux * e.epx; sxb.sm += e.emx; sxb.tm += e.dlx * e.emx;
+    syb.sp += e.epy; syb.tp += e.duy * e.epy; syb.sm += e.emy; syb.tm += e.dly * e.emy;
+  }
+  sz.sp += e.epz; sz.tp += e.duz * e.epz; sz.sm += e.emz; sz.tm += e.dlz * e.emz;
+}
+
+// d W^ / d u for one pin of the chosen branch, from its set-shifted offsets and exponentials.
+// Every field is passed by value so that the branch choice is a select between values.
+__device__ __forceinline__ float grad_branch(bool split, bool top, float du, float dl, float ep, float em,
+                                             float inv_gamma, float Mt, float Mb, float Me, float mt, float mb,
+                                             float me, float rt, float rb, float qt, float qb, float At_p, float Ab_p,
+                                             float Ae_p, float st_p, float sb_p, float se_p, float At_m, float Ab_m,
+                                             float Ae_m, float st_m, float sb_m, float se_m) {
+  const float Ap_s = top ? At_p : Ab_p, sp_s = top ? st_p : sb_p;
+  const float Am_s = top ? At_m : Ab_m, sm_s = top ? st_m : sb_m;
+  // whole-net branch: move from the set's shifts to the whole-net shifts
+  const float du_e = du + ((top ? Mt : Mb) - Me), dl_e = dl + ((top ? mt : mb) - me);
+  const float ep_e = ep * (top ? rt : rb), em_e = em * (top ? qt : qb);
+  const float Ap = split ? Ap_s : Ae_p, sp = split ? sp_s : se_p;
+  const float Am = split ? Am_s : Ae_m, sm = split ? sm_s : se_m;
+  const float u = split ? du : du_e, l = split ? dl : dl_e;
+  const float p = split ? ep : ep_e, q = split ? em : em_e;
+  return p / sp * (1.f + (u - Ap) * inv_gamma) - q / sm * (1.f - (l - Am) * inv_gamma);
+}
+
+#define P3D_AXIS_GRAD(a, top, du, dl, ep, em)                                                          \
+  grad_branch((a).split, top, du, dl, ep, em, inv_gamma, (a).Mt, (a).Mb, (a).Me, (a).mt, (a).mb, (a).me, \
+              (a).rt, (a).rb, (a).qt, (a).qb, (a).At_p, (a).Ab_p, (a).Ae_p, (a).st_p, (a).sb_p, (a).se_p, \
+              (a).At_m, (a).Ab_m, (a).Ae_m, (a).st_m, (a).sb_m, (a).se_m)
 
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     int n, float half_dz, float four_over_dz, float gamma, float alpha, const float* __restrict__ xyz,
     const int32_t* __restrict__ s_net_start, const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
-    float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part, int stride) {
+    const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part,
+    int stride) {
   __shared__ double shred[5][kWaBlock / kWave];
   __shared__ int cls_s;
   if (threadIdx.x == 0) {
@@ -210,24 +256,35 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
 
   int s = 0, d = 0;
   if (active) { s = s_net_start[net]; d = s_net_start[net + 1] - s; }
+  // the lane's first pin stays in registers through all phases; further pins (nets larger than
+  // the group, only in the 64-lane class) are reloaded per phase
+  const bool have0 = lane < d;
+  PinData p0;
+  if (have0) p0 = load_pin(xyz, n, pin_node, off, s + lane, half_dz);
 
   // ---- phase A: extremes per set and axis, z extremes, set sizes
   Ext tx = {top2_empty_max(), top2_empty_min()}, ty = tx, bx = tx, by = tx;
   float zmax = kNegInf, zmin = kPosInf;
   int ct = 0, cb = 0;
-  for (int k = lane; k < d; k += G) {
+#define P3D_PUT(p)                                                          \
+  do {                                                                      \
+    if ((p).top) {                                                          \
+      top2_put_max(tx.mx, (p).ux); top2_put_min(tx.mn, (p).ux);             \
+      top2_put_max(ty.mx, (p).uy); top2_put_min(ty.mn, (p).uy);             \
+      ++ct;                                                                 \
+    } else {                                                                \
+      top2_put_max(bx.mx, (p).ux); top2_put_min(bx.mn, (p).ux);             \
+      top2_put_max(by.mx, (p).uy); top2_put_min(by.mn, (p).uy);             \
+      ++cb;                                                                 \
+    }                                                                       \
+    zmax = fmaxf(zmax, (p).z); zmin = fminf(zmin, (p).z);                   \
+  } while (0)
+  if (have0) P3D_PUT(p0);
+  for (int k = lane + G; k < d; k += G) {
     const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    if (p.top) {
-      top2_put_max(tx.mx, p.ux); top2_put_min(tx.mn, p.ux);
-      top2_put_max(ty.mx, p.uy); top2_put_min(ty.mn, p.uy);
-      ++ct;
-    } else {
-      top2_put_max(bx.mx, p.ux); top2_put_min(bx.mn, p.ux);
-      top2_put_max(by.mx, p.uy); top2_put_min(by.mn, p.uy);
-      ++cb;
-    }
-    zmax = fmaxf(zmax, p.z); zmin = fminf(zmin, p.z);
+    P3D_PUT(p);
   }
+#undef P3D_PUT
   for (int m = G >> 1; m > 0; m >>= 1) {
     top2_merge_max(tx.mx, m); top2_merge_min(tx.mn, m);
     top2_merge_max(ty.mx, m); top2_merge_min(ty.mn, m);
@@ -241,27 +298,14 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
 
   // ---- phase B: shifted exponential sums per set and axis, and for z over the whole net
   SetSums sxt = {0, 0, 0, 0}, sxb = sxt, syt = sxt, syb = sxt, sz = sxt;
-  for (int k = lane; k < d; k += G) {
+  PinExp e0 = {};
+  if (have0) {
+    e0 = pin_exps(p0, tx, bx, ty, by, zmax, zmin, inv_gamma);
+    add_sums(e0, p0.top, sxt, sxb, syt, syb, sz);
+  }
+  for (int k = lane + G; k < d; k += G) {
     const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    // shifts of the pin's own set; sums go to that set
-    const float Mx = p.top ? tx.mx.a1.h : bx.mx.a1.h, mx = p.top ? tx.mn.a1.h : bx.mn.a1.h;
-    const float My = p.top ? ty.mx.a1.h : by.mx.a1.h, my = p.top ? ty.mn.a1.h : by.mn.a1.h;
-    const float dux = (p.ux.h - Mx) + p.ux.l, dlx = (p.ux.h - mx) + p.ux.l;
-    const float duy = (p.uy.h - My) + p.uy.l, dly = (p.uy.h - my) + p.uy.l;
-    const float epx = __expf(dux * inv_gamma), emx = __expf(-dlx * inv_gamma);
-    const float epy = __expf(duy * inv_gamma), emy = __expf(-dly * inv_gamma);
-    if (p.top) {
-      sxt.sp += epx; sxt.tp += dux * epx; sxt.sm += emx; sxt.tm += dlx * emx;
-      syt.sp += epy; syt.tp += duy * epy; syt.sm += emy; syt.tm += dly * emy;
-    } else {
-      sxb.sp += epx; sxb.tp += dux * epx; sxb.sm += emx; sxb.tm += dlx * emx;
-      syb.sp += epy; syb.tp += duy * epy; syb.sm += emy; syb.tm += dly * emy;
-    }
-    {
-      const float du = p.z - zmax, dl = p.z - zmin;
-      const float ep = __expf(du * inv_gamma), em = __expf(-dl * inv_gamma);
-      sz.sp += ep; sz.tp += du * ep; sz.sm += em; sz.tm += dl * em;
-    }
+    add_sums(pin_exps(p, tx, bx, ty, by, zmax, zmin, inv_gamma), p.top, sxt, sxb, syt, syb, sz);
   }
   for (int m = G >> 1; m > 0; m >>= 1) {
 #define P3D_RED4(S) S.sp += __shfl_xor(S.sp, m); S.tp += __shfl_xor(S.tp, m); \
@@ -278,26 +322,31 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const float Wy = bistratal_exact(ty.mx.a1, ty.mn.a1, ct, by.mx.a1, by.mn.a1, cb);
 
   // ---- phase C: per-pin gradient shares and FDA differences
-  for (int k = lane; k < d; k += G) {
+#define P3D_EMIT(p, e, slot)                                                                   \
+  do {                                                                                         \
+    const float gx_ = P3D_AXIS_GRAD(wx, (p).top, (e).dux, (e).dlx, (e).epx, (e).emx);          \
+    const float gy_ = P3D_AXIS_GRAD(wy, (p).top, (e).duy, (e).dly, (e).epy, (e).emy);          \
+    const float gz_ = alpha * ((e).epz / sz.sp * (1.f + ((e).duz - Azp) * inv_gamma) -         \
+                               (e).emz / sz.sm * (1.f - ((e).dlz - Azm) * inv_gamma));         \
+    float wfx_, wfy_;                                                                          \
+    if ((p).top) {                                                                             \
+      wfx_ = bistratal_flip(tx, ct, bx, cb, (p).ux, (p).fx);                                   \
+      wfy_ = bistratal_flip(ty, ct, by, cb, (p).uy, (p).fy);                                   \
+    } else {                                                                                   \
+      wfx_ = bistratal_flip(bx, cb, tx, ct, (p).ux, (p).fx);                                   \
+      wfy_ = bistratal_flip(by, cb, ty, ct, (p).uy, (p).fy);                                   \
+    }                                                                                          \
+    /* (4/d_z) (W with the owner on top - W with it on the bottom) */                          \
+    const float dw_ = (wfx_ - Wx) + (wfy_ - Wy);                                               \
+    pin_out[slot_pos[slot]] = make_float4(gx_, gy_, gz_, four_over_dz * ((p).top ? -dw_ : dw_)); \
+  } while (0)
+  if (have0) P3D_EMIT(p0, e0, s + lane);
+  for (int k = lane + G; k < d; k += G) {
     const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    const float gx = axis_grad(wx, p.ux, p.top, inv_gamma);
-    const float gy = axis_grad(wy, p.uy, p.top, inv_gamma);
-    const float du = p.z - zmax, dl = p.z - zmin;
-    const float ep = __expf(du * inv_gamma), em = __expf(-dl * inv_gamma);
-    const float gz = alpha * (ep / sz.sp * (1.f + (du - Azp) * inv_gamma) - em / sz.sm * (1.f - (dl - Azm) * inv_gamma));
-    float wfx, wfy;
-    if (p.top) {
-      wfx = bistratal_flip(tx, ct, bx, cb, p.ux, p.fx);
-      wfy = bistratal_flip(ty, ct, by, cb, p.uy, p.fy);
-    } else {
-      wfx = bistratal_flip(bx, cb, tx, ct, p.ux, p.fx);
-      wfy = bistratal_flip(by, cb, ty, ct, p.uy, p.fy);
-    }
-    // (4/d_z) (W with the owner on top - W with it on the bottom)
-    const float dw = (wfx - Wx) + (wfy - Wy);
-    const float fda = four_over_dz * (p.top ? -dw : dw);
-    pin_out[s + k] = make_float4(gx, gy, gz, fda);
+    const PinExp e = pin_exps(p, tx, bx, ty, by, zmax, zmin, inv_gamma);
+    P3D_EMIT(p, e, s + k);
   }
+#undef P3D_EMIT
 
   // ---- net totals: one contribution per group, block-reduced in float64
   double v[5] = {0, 0, 0, 0, 0};
@@ -328,25 +377,55 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   }
 }
 
-// per instance: sum the pin shares in slot order; L1 norms over movable instances
-__global__ void k_wl_gather(int n, const uint8_t* __restrict__ kind, const int32_t* __restrict__ node_slot_start,
-                            const int32_t* __restrict__ node_slots, const float4* __restrict__ pin_out,
-                            float* __restrict__ grad, int accumulate, float* __restrict__ gz_wa,
-                            float* __restrict__ fda, double* __restrict__ part, int stride) {
+// per instance: sum its pin shares (contiguous, ascending slot order); L1 norms over movable instances
+// per instance: sum its pin shares (contiguous, ascending slot order); L1 norms over movable
+// instances.  Blocks [0, nlight) take one instance per thread; instances with more than
+// kHeavyPins pins are left to the blocks after them, one wavefront per instance.
+constexpr int kHeavyPins = 32;
+
+__global__ void k_wl_gather(int n, int nlight, const int32_t* __restrict__ heavy, int nheavy,
+                            const uint8_t* __restrict__ kind, const int32_t* __restrict__ node_slot_start,
+                            const float4* __restrict__ pin_out, float* __restrict__ grad, int accumulate,
+                            float* __restrict__ gz_wa, float* __restrict__ fda, double* __restrict__ part, int stride) {
   __shared__ double sh[3][256 / kWave];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float gx = 0.f, gy = 0.f, gz = 0.f, gf = 0.f;
-  if (i < n && !(kind[i] & PLACE3D_KIND_FIXED)) {
-    for (int q = node_slot_start[i]; q < node_slot_start[i + 1]; ++q) {
-      const float4 v = pin_out[node_slots[q]];
-      gx += v.x; gy += v.y; gz += v.z; gf += v.w;
+  int i = -1;
+  bool writer = false;
+  if ((int)blockIdx.x < nlight) {
+    i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+      const int q0 = node_slot_start[i], q1 = node_slot_start[i + 1];
+      writer = q1 - q0 <= kHeavyPins;
+      if (writer && !(kind[i] & PLACE3D_KIND_FIXED))
+        for (int q = q0; q < q1; ++q) {
+          const float4 v = pin_out[q];
+          gx += v.x; gy += v.y; gz += v.z; gf += v.w;
+        }
+    }
+  } else {
+    const int w = ((int)blockIdx.x - nlight) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (w < nheavy) {
+      i = heavy[w];
+      if (!(kind[i] & PLACE3D_KIND_FIXED))
+        for (int q = node_slot_start[i] + lane; q < node_slot_start[i + 1]; q += kWave) {
+          const float4 v = pin_out[q];
+          gx += v.x; gy += v.y; gz += v.z; gf += v.w;
+        }
+      for (int m = kWave / 2; m > 0; m >>= 1) {   // butterfly: lane sums, fixed order
+        gx += __shfl_xor(gx, m); gy += __shfl_xor(gy, m);
+        gz += __shfl_xor(gz, m); gf += __shfl_xor(gf, m);
+      }
+      writer = lane == 0;
     }
   }
-  if (i < n) {
+  if (writer) {
     if (accumulate) { grad[i] += gx; grad[n + i] += gy; }
     else { grad[i] = gx; grad[n + i] = gy; }
     gz_wa[i] = gz;
     fda[i] = gf;
+  } else {
+    gx = gy = gz = gf = 0.f;
   }
   double a[3] = {fabs((double)gx), fabs((double)gy), fabs((double)gf)};
   for (int q = 0; q < 3; ++q) {
@@ -395,16 +474,18 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
   if (c->n_wa_blocks > 0) {
     ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
     hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.n, g.half_dz, 4.f / g.dz,
-                       (float)p.gamma, (float)p.alpha, xyz, c->s_net_start, c->s_pin_node, c->s_off, c->pin_out,
-                       c->classes, c->part, c->part_stride);
+                       (float)p.gamma, (float)p.alpha, xyz, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
+                       c->pin_out, c->classes, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
   }
   if ((rc = reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, red + R_WA_BI, s))) return rc;
-  const unsigned nb = blocks_for(g.n, 256);
+  const unsigned nlight = blocks_for(g.n, 256);
+  const unsigned nb = nlight + (unsigned)((c->n_heavy + 3) / 4);
   {
     ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
-    hipLaunchKernelGGL(k_wl_gather, dim3(nb), dim3(256), 0, s, g.n, p.kind, c->node_slot_start, c->node_slots,
-                       c->pin_out, grad, accumulate, c->wl_gzwa, c->wl_fda, c->part, c->part_stride);
+    hipLaunchKernelGGL(k_wl_gather, dim3(nb), dim3(256), 0, s, g.n, (int)nlight, c->heavy_list, c->n_heavy, p.kind,
+                       c->node_slot_start, c->pin_out, grad, accumulate, c->wl_gzwa, c->wl_fda, c->part,
+                       c->part_stride);
     P3D_LAUNCH(c, "k_wl_gather");
   }
   if ((rc = reduce_final(c, R_NORM_X, 3, (int)nb, false, red + R_NORM_X, s))) return rc;
