@@ -84,6 +84,8 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   auto& d = c->dct;
   d.Fx = w.take<float>(nx * nx); d.Gx = w.take<float>(nx * nx); d.Hx = w.take<float>(nx * nx);
   d.FyT = w.take<float>(ny * ny); d.Gy = w.take<float>(ny * ny); d.Hy = w.take<float>(ny * ny);
+  for (uint16_t** q : {&d.Fx_h, &d.Fx_l, &d.Gx_h, &d.Gx_l, &d.Hx_h, &d.Hx_l}) *q = w.take<uint16_t>(nx * nx);
+  for (uint16_t** q : {&d.FyT_h, &d.FyT_l, &d.Gy_h, &d.Gy_l, &d.Hy_h, &d.Hy_l}) *q = w.take<uint16_t>(ny * ny);
   d.zmat = w.take<float>(4 * p3d::kMaxNz * p3d::kMaxNz);
   d.inv_w2 = w.take<float>(map);
   c->map_t = w.take<float>(map); c->map_a = w.take<float>(map);

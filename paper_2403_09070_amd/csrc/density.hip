@@ -479,9 +479,16 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
   __shared__ double sh[256];
   const int q = slot0 + blockIdx.x;
   const double* row = part + (size_t)q * stride;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 256) s = is_max ? fmax(s, row[b]) : s + row[b];
-  sh[threadIdx.x] = s;
+  // four independent accumulators keep four loads in flight per thread
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 768 < nparts; b += 1024) {
+    const double v0 = row[b], v1 = row[b + 256], v2 = row[b + 512], v3 = row[b + 768];
+    if (is_max) { a0 = fmax(a0, v0); a1 = fmax(a1, v1); a2 = fmax(a2, v2); a3 = fmax(a3, v3); }
+    else { a0 += v0; a1 += v1; a2 += v2; a3 += v3; }
+  }
+  for (; b < nparts; b += 256) a0 = is_max ? fmax(a0, row[b]) : a0 + row[b];
+  sh[threadIdx.x] = is_max ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o)

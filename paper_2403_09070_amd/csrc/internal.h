@@ -49,6 +49,9 @@ struct DctBases {
   // float32 [N][N] row-major, see spectral.hip for the definition of each matrix
   float *Fx, *Gx, *Hx;      // x: forward (sample, freq), inverse cos (freq, sample), inverse sin*omega
   float *FyT, *Gy, *Hy;     // y: forward^T (freq, sample), inverse cos (sample, freq), inverse sin*omega
+  // bfloat16 hi/lo splits, k contiguous: x bases transposed to [N][K], y bases as stored
+  uint16_t *Fx_h, *Fx_l, *Gx_h, *Gx_l, *Hx_h, *Hx_l;
+  uint16_t *FyT_h, *FyT_l, *Gy_h, *Gy_l, *Hy_h, *Hy_l;
   float* zmat;              // small z matrices, see spectral.hip
   float* inv_w2;            // [Nz][Ny][Nx] 1/|omega|^2 with the (0,0,0) entry 0
 };

@@ -219,19 +219,39 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
 
 // Same contraction with each float32 operand split into bfloat16 hi + lo (round to nearest
 // even) and three products hi.hi + hi.lo + lo.hi accumulated in float32 (32x32x16 bf16 MFMA).
-__global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs args) {
-  constexpr int BK = 32, LDK = BK + 8;   // k contiguous in LDS for both operands
-  __shared__ unsigned short Ah[BM][LDK], Al[BM][LDK];
-  __shared__ unsigned short Bh[BN][LDK], Bl[BN][LDK];
+// One operand is a DCT basis, split once at context creation and stored with k contiguous
+// ([rows][K] for a left basis, transposed [N][K] for a right basis); the other is a map,
+// loaded as float32 and split on the way into LDS.  LDS holds both operands k-contiguous,
+// double-buffered, one barrier per 32-wide k step.
+struct GemmSplitProb {
+  const float* data;                 // map operand, float32 row-major
+  const uint16_t* bhi;               // basis hi, k contiguous
+  const uint16_t* blo;               // basis lo
+  float* C;
+  long long s_data, s_C;             // batch strides (elements)
+};
+
+struct GemmSplitArgs {
+  int M, N, K, nbatch;
+  GemmSplitProb p[4];
+};
+
+template <bool LEFT_BASIS>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
+  constexpr int BK = 32, LDK = BK + 8;
+  __shared__ unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
+  __shared__ unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
   const int M = args.M, N = args.N, K = args.K;
   const int prob = blockIdx.z / args.nbatch, bat = blockIdx.z % args.nbatch;
-  const GemmProb P = args.p[prob];
-  const float* __restrict__ A = P.A + bat * P.sA;
-  const float* __restrict__ B = P.B + bat * P.sB;
-  float* __restrict__ C = P.C + bat * P.sC;
+  const GemmSplitProb P = args.p[prob];
+  const float* __restrict__ D = P.data + bat * P.s_data;
+  const uint16_t* __restrict__ Bh_g = P.bhi;
+  const uint16_t* __restrict__ Bl_g = P.blo;
+  float* __restrict__ C = P.C + bat * P.s_C;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0) && (N % 4 == 0) && (K % 8 == 0);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -241,70 +261,115 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  float ra[16], rb[16];
-  auto load = [&](int k0) {
-    // A: 128 rows x 4 groups of 8 consecutive k; thread takes groups f = tid, tid + 256
+  // staging registers: 16 data floats, 2 x 2 basis groups of 8 bf16
+  float rd[16];
+  u16x8 rbh[2], rbl[2];
+
+  // basis tile: rows [r0, r0 + 128) of a k-contiguous [rows][K] array; thread takes row f >> 2,
+  // k group (f & 3) * 8 for f = tid, tid + 256
+  auto load_basis = [&](int k0, int r0, int rows) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
-      const int gm = m0 + r;
+      const int gr = r0 + r, gk = k0 + kg;
+      if (full) {
+        rbh[q] = *reinterpret_cast<const u16x8*>(Bh_g + (size_t)gr * K + gk);
+        rbl[q] = *reinterpret_cast<const u16x8*>(Bl_g + (size_t)gr * K + gk);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + kg + e;
-        ra[8 * q + e] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : 0.f;
-      }
-    }
-    // B: 128 columns x 4 groups of 8 consecutive k; consecutive threads take consecutive n
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int f = tid + 256 * q;
-      const int cn = f & 127, kg = (f >> 7) * 8;
-      const int gn = n0 + cn;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + kg + e;
-        rb[8 * q + e] = (gn < N && gk < K) ? B[(size_t)gk * N + gn] : 0.f;
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = gr < rows && gk + e < K;
+          rbh[q][e] = ok ? Bh_g[(size_t)gr * K + gk + e] : (unsigned short)0;
+          rbl[q][e] = ok ? Bl_g[(size_t)gr * K + gk + e] : (unsigned short)0;
+        }
       }
     }
   };
-  auto store = [&]() {
+  auto store_basis = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
-      u16x8 h, l;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const unsigned short hb = bf16_rne(ra[8 * q + e]);
-        h[e] = hb;
-        l[e] = bf16_rne(ra[8 * q + e] - bf16_to_f32(hb));
-      }
-      *reinterpret_cast<u16x8*>(&Ah[r][kg]) = h;
-      *reinterpret_cast<u16x8*>(&Al[r][kg]) = l;
+      *reinterpret_cast<u16x8*>(&H[r][kg]) = rbh[q];
+      *reinterpret_cast<u16x8*>(&L[r][kg]) = rbl[q];
     }
+  };
+  auto split_store = [&](unsigned short* h, unsigned short* l, const float* v) {
+    u16x8 hh, ll;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const unsigned short hb = bf16_rne(v[e]);
+      hh[e] = hb;
+      ll[e] = bf16_rne(v[e] - bf16_to_f32(hb));
+    }
+    *reinterpret_cast<u16x8*>(h) = hh;
+    *reinterpret_cast<u16x8*>(l) = ll;
+  };
+  // left data operand (map as A [M][K]): thread takes row f >> 2, k group (f & 3) * 8
+  auto load_left_data = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
-      const int cn = f & 127, kg = (f >> 7) * 8;
-      u16x8 h, l;
+      const int r = f >> 2, kg = (f & 3) * 8;
+      const int gm = m0 + r, gk = k0 + kg;
+      if (full) {
+        const float4 v0 = *reinterpret_cast<const float4*>(D + (size_t)gm * K + gk);
+        const float4 v1 = *reinterpret_cast<const float4*>(D + (size_t)gm * K + gk + 4);
+        rd[8 * q + 0] = v0.x; rd[8 * q + 1] = v0.y; rd[8 * q + 2] = v0.z; rd[8 * q + 3] = v0.w;
+        rd[8 * q + 4] = v1.x; rd[8 * q + 5] = v1.y; rd[8 * q + 6] = v1.z; rd[8 * q + 7] = v1.w;
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const unsigned short hb = bf16_rne(rb[8 * q + e]);
-        h[e] = hb;
-        l[e] = bf16_rne(rb[8 * q + e] - bf16_to_f32(hb));
+        for (int e = 0; e < 8; ++e) rd[8 * q + e] = (gm < M && gk + e < K) ? D[(size_t)gm * K + gk + e] : 0.f;
       }
-      *reinterpret_cast<u16x8*>(&Bh[cn][kg]) = h;
-      *reinterpret_cast<u16x8*>(&Bl[cn][kg]) = l;
     }
+  };
+  auto store_left_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int f = tid + 256 * q;
+      const int r = f >> 2, kg = (f & 3) * 8;
+      split_store(&H[r][kg], &L[r][kg], rd + 8 * q);
+    }
+  };
+  // right data operand (map as B [K][N]): thread takes columns 2 (tid & 63) + {0, 1} and k group
+  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers
+  auto load_right_data = [&](int k0) {
+    const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
+    const int gn = n0 + cn;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + kg + e;
+      if (full) {
+        const float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * N + gn);
+        rd[e] = v.x;
+        rd[8 + e] = v.y;
+      } else {
+        rd[e] = (gk < K && gn < N) ? D[(size_t)gk * N + gn] : 0.f;
+        rd[8 + e] = (gk < K && gn + 1 < N) ? D[(size_t)gk * N + gn + 1] : 0.f;
+      }
+    }
+  };
+  auto store_right_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
+    const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
+    split_store(&H[cn][kg], &L[cn][kg], rd);
+    split_store(&H[cn + 1][kg], &L[cn + 1][kg], rd + 8);
+  };
+  auto load = [&](int k0) {
+    if (LEFT_BASIS) { load_basis(k0, m0, M); load_right_data(k0); }
+    else { load_left_data(k0); load_basis(k0, n0, N); }
+  };
+  auto store = [&](int buf) {
+    if (LEFT_BASIS) { store_basis(Ah[buf], Al[buf]); store_right_data(Bh[buf], Bl[buf]); }
+    else { store_left_data(Ah[buf], Al[buf]); store_basis(Bh[buf], Bl[buf]); }
   };
 
   const int KT = (K + BK - 1) / BK;
   load(0);
+  store(0);
+  __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
-    __syncthreads();            // previous tile fully consumed
-    store();
-    __syncthreads();
+    const int cur = kt & 1;
     if (kt + 1 < KT) load((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
@@ -314,10 +379,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs args) {
       for (int t = 0; t < 2; ++t) {
         const int ar = wm * 64 + t * 32 + (lane & 31);
         const int bc = wn * 64 + t * 32 + (lane & 31);
-        ah[t] = *reinterpret_cast<const bf16x8*>(&Ah[ar][ko]);
-        al[t] = *reinterpret_cast<const bf16x8*>(&Al[ar][ko]);
-        bh[t] = *reinterpret_cast<const bf16x8*>(&Bh[bc][ko]);
-        bl[t] = *reinterpret_cast<const bf16x8*>(&Bl[bc][ko]);
+        ah[t] = *reinterpret_cast<const bf16x8*>(&Ah[cur][ar][ko]);
+        al[t] = *reinterpret_cast<const bf16x8*>(&Al[cur][ar][ko]);
+        bh[t] = *reinterpret_cast<const bf16x8*>(&Bh[cur][bc][ko]);
+        bl[t] = *reinterpret_cast<const bf16x8*>(&Bl[cur][bc][ko]);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -328,6 +393,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs args) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
         }
     }
+    if (kt + 1 < KT) store(cur ^ 1);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -340,6 +407,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs args) {
         if (row < M && col < N) C[(size_t)row * N + col] = acc[a][b][r];
       }
     }
+}
+
+// hi/lo bfloat16 split of a float32 matrix src[rows][cols]; with `transpose` the outputs are
+// [cols][rows] (so that a right-hand basis becomes k-contiguous)
+__global__ void k_split_bf16(const float* __restrict__ src, int rows, int cols, int transpose,
+                             uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)rows * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);
+  const float v = src[t];
+  const unsigned short h = bf16_rne(v);
+  const size_t o = transpose ? (size_t)c * rows + r : (size_t)t;
+  hi[o] = h;
+  lo[o] = bf16_rne(v - bf16_to_f32(h));
 }
 
 // ------------------------------------------------------------------ z mixing
@@ -395,17 +476,34 @@ __global__ void k_energy(long long total, const float* __restrict__ rho, const f
   }
 }
 
-int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, const GemmProb* probs, int nprob, hipStream_t s) {
+// A basis operand of a contraction: its float32 matrix and its k-contiguous bfloat16 split
+struct Basis { const float* f32; const uint16_t* hi; const uint16_t* lo; };
+
+// batched C = A . B where exactly one of A (left_basis) or B is a DCT basis shared by the batch
+int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, bool left_basis, const float* const* data,
+         long long s_data, const Basis* basis, float* const* out, long long s_out, int nprob, hipStream_t s) {
   if (nprob <= 0) return PLACE3D_OK;
-  GemmArgs a;
-  a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
-  for (int i = 0; i < 4; ++i) a.p[i] = i < nprob ? probs[i] : probs[0];
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nbatch * nprob);
   ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
-  if (c->prob.precision == PLACE3D_BF16X3)
-    hipLaunchKernelGGL(k_gemm_bf16x3, grid, dim3(256), 0, s, a);
-  else
+  if (c->prob.precision == PLACE3D_BF16X3) {
+    GemmSplitArgs a;
+    a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
+    for (int i = 0; i < 4; ++i) {
+      const int j = i < nprob ? i : 0;
+      a.p[i] = {data[j], basis[j].hi, basis[j].lo, out[j], s_data, s_out};
+    }
+    if (left_basis) hipLaunchKernelGGL(k_gemm_bf16x3<true>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_gemm_bf16x3<false>, grid, dim3(256), 0, s, a);
+  } else {
+    GemmArgs a;
+    a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
+    for (int i = 0; i < 4; ++i) {
+      const int j = i < nprob ? i : 0;
+      a.p[i] = left_basis ? GemmProb{basis[j].f32, data[j], out[j], 0, s_data, s_out}
+                          : GemmProb{data[j], basis[j].f32, out[j], s_data, 0, s_out};
+    }
     hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, a);
+  }
   P3D_LAUNCH(c, "k_gemm");
   return PLACE3D_OK;
 }
@@ -422,6 +520,17 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_basis_y, dim3(blocks_for((long long)g.ny * g.ny, 256)), dim3(256), 0, s, g.ny, p.die_y,
                      c->dct.FyT, c->dct.Gy, c->dct.Hy);
   P3D_LAUNCH(c, "k_basis_y");
+  {
+    const DctBases& d = c->dct;
+    const unsigned bx = blocks_for((long long)g.nx * g.nx, 256), by = blocks_for((long long)g.ny * g.ny, 256);
+    hipLaunchKernelGGL(k_split_bf16, dim3(bx), dim3(256), 0, s, d.Fx, g.nx, g.nx, 1, d.Fx_h, d.Fx_l);
+    hipLaunchKernelGGL(k_split_bf16, dim3(bx), dim3(256), 0, s, d.Gx, g.nx, g.nx, 1, d.Gx_h, d.Gx_l);
+    hipLaunchKernelGGL(k_split_bf16, dim3(bx), dim3(256), 0, s, d.Hx, g.nx, g.nx, 1, d.Hx_h, d.Hx_l);
+    hipLaunchKernelGGL(k_split_bf16, dim3(by), dim3(256), 0, s, d.FyT, g.ny, g.ny, 0, d.FyT_h, d.FyT_l);
+    hipLaunchKernelGGL(k_split_bf16, dim3(by), dim3(256), 0, s, d.Gy, g.ny, g.ny, 0, d.Gy_h, d.Gy_l);
+    hipLaunchKernelGGL(k_split_bf16, dim3(by), dim3(256), 0, s, d.Hy, g.ny, g.ny, 0, d.Hy_h, d.Hy_l);
+    P3D_LAUNCH(c, "k_split_bf16");
+  }
   hipLaunchKernelGGL(k_basis_z, dim3(1), dim3(kMaxNz * kMaxNz), 0, s, g.nz, dz, c->dct.zmat);
   P3D_LAUNCH(c, "k_basis_z");
   const long long map = (long long)g.nx * g.ny * g.nz;
@@ -438,29 +547,35 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long plane = (long long)nx * ny;
   int rc;
-  // forward x, forward y
+  const Basis Fx{d.Fx, d.Fx_h, d.Fx_l}, Gx{d.Gx, d.Gx_h, d.Gx_l}, Hx{d.Hx, d.Hx_h, d.Hx_l};
+  const Basis FyT{d.FyT, d.FyT_h, d.FyT_l}, Gy{d.Gy, d.Gy_h, d.Gy_l}, Hy{d.Hy, d.Hy_h, d.Hy_l};
+  // forward x: T = rho . Fx;  forward y: A[z] = FyT . T[z]
   {
-    GemmProb p = {rho, d.Fx, c->map_t, 0, 0, 0};
-    if ((rc = gemm(c, nz * ny, nx, nx, 1, &p, 1, s))) return rc;
+    const float* in[1] = {rho};
+    float* out[1] = {c->map_t};
+    if ((rc = gemm(c, nz * ny, nx, nx, 1, false, in, 0, &Fx, out, 0, 1, s))) return rc;
   }
   {
-    GemmProb p = {d.FyT, c->map_t, c->map_a, 0, plane, plane};
-    if ((rc = gemm(c, ny, nx, ny, nz, &p, 1, s))) return rc;
+    const float* in[1] = {c->map_t};
+    float* out[1] = {c->map_a};
+    if ((rc = gemm(c, ny, nx, ny, nz, true, in, plane, &FyT, out, plane, 1, s))) return rc;
   }
   {
     ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
     hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat, d.inv_w2,
-                     c->map_a);
+                       c->map_a);
     P3D_LAUNCH(c, "k_zmix_fwd");
   }
-  // inverse y
+  // inverse y: Vg = Gy . b[l], Vh = Hy . b[l]
   const bool need_g = phi || ex || ez, need_h = ey != nullptr;
   {
-    GemmProb p[2];
+    const float* in[2] = {c->map_a, c->map_a};
+    Basis bs[2];
+    float* out[2];
     int np = 0;
-    if (need_g) p[np++] = {d.Gy, c->map_a, c->map_vg, 0, plane, plane};
-    if (need_h) p[np++] = {d.Hy, c->map_a, c->map_vh, 0, plane, plane};
-    if ((rc = gemm(c, ny, nx, ny, nz, p, np, s))) return rc;
+    if (need_g) { bs[np] = Gy; out[np++] = c->map_vg; }
+    if (need_h) { bs[np] = Hy; out[np++] = c->map_vh; }
+    if ((rc = gemm(c, ny, nx, ny, nz, true, in, plane, bs, out, plane, np, s))) return rc;
   }
   float* pc = (phi || ex) ? c->map_pc : nullptr;
   float* ps = ez ? c->map_ps : nullptr;
@@ -473,15 +588,17 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
       P3D_LAUNCH(c, "k_zmix_inv");
     }
   }
-  // inverse x
+  // inverse x: Ex = Pc . Hx, Ey = Qc . Gx, Ez = Ps . Gx, phi = Pc . Gx
   {
-    GemmProb p[4];
+    const float* in[4];
+    Basis bs[4];
+    float* out[4];
     int np = 0;
-    if (ex) p[np++] = {c->map_pc, d.Hx, ex, 0, 0, 0};
-    if (ey) p[np++] = {c->map_qc, d.Gx, ey, 0, 0, 0};
-    if (ez) p[np++] = {c->map_ps, d.Gx, ez, 0, 0, 0};
-    if (phi) p[np++] = {c->map_pc, d.Gx, phi, 0, 0, 0};
-    if ((rc = gemm(c, nz * ny, nx, nx, 1, p, np, s))) return rc;
+    if (ex) { in[np] = c->map_pc; bs[np] = Hx; out[np++] = ex; }
+    if (ey) { in[np] = c->map_qc; bs[np] = Gx; out[np++] = ey; }
+    if (ez) { in[np] = c->map_ps; bs[np] = Gx; out[np++] = ez; }
+    if (phi) { in[np] = c->map_pc; bs[np] = Gx; out[np++] = phi; }
+    if ((rc = gemm(c, nz * ny, nx, nx, 1, false, in, 0, bs, out, 0, np, s))) return rc;
   }
   if (energy) {
     const long long map = plane * nz;
