@@ -28,13 +28,6 @@ struct Carver {
   }
 };
 
-// Lane-group class of a net of degree d: groups of 2, 4, ..., 64 lanes; larger nets loop.
-int net_class(int d) {
-  int c = 0;
-  while ((2 << c) < d && c < p3d::kNumClasses - 1) ++c;
-  return c;
-}
-
 int check_problem(const place3d_problem* p, std::string& why) {
   if (!p) { why = "problem is NULL"; return PLACE3D_ERR_ARG; }
   if (p->n_inst < 1 || p->n_pins < 0 || p->n_nets < 0) { why = "n_inst < 1 or negative pin/net count"; return PLACE3D_ERR_SIZE; }
@@ -168,26 +161,39 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     }
   }
 
-  // nets ordered by lane-group class, stable in net index; empty nets are dropped
+  // nets by lane-group class: a net of degree d takes G = 2^c lanes, the smallest with
+  // d <= kPinsPerLane * G (64 lanes for larger nets, which then loop).  Classes are laid out
+  // from the widest groups down, nets by degree (descending, stable in net index) within a class
+  // so that a wavefront holds nets of (near) equal degree; empty nets are dropped.
+  auto net_class = [](int d) {
+    int cl = 0;
+    while (p3d::kPinsPerLane * (1 << cl) < d && cl < p3d::kNumClasses - 1) ++cl;
+    return cl;
+  };
   std::vector<int32_t> order;
   order.reserve(m);
-  for (int cl = 0; cl < p3d::kNumClasses; ++cl) {
-    c->classes.net_begin[cl] = (int32_t)order.size();
-    for (int e = 0; e < m; ++e) {
-      const int d = ns[e + 1] - ns[e];
-      if (d > 0 && net_class(d) == cl) order.push_back(e);
+  for (int e = 0; e < m; ++e)
+    if (ns[e + 1] > ns[e]) order.push_back(e);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return ns[a + 1] - ns[a] > ns[b + 1] - ns[b];
+  });
+  {
+    int nb = 0;
+    size_t k = 0;
+    for (int i = 0; i < p3d::kNumClasses; ++i) {     // layout position i: G = 2^(kNumClasses-1-i)
+      const int cl = p3d::kNumClasses - 1 - i;
+      c->classes.net_begin[i] = (int32_t)k;
+      c->classes.block_begin[i] = nb;
+      size_t k1 = k;
+      while (k1 < order.size() && net_class(ns[order[k1] + 1] - ns[order[k1]]) == cl) ++k1;
+      const int per_block = p3d::kWaBlock >> cl;
+      nb += (int)((k1 - k + per_block - 1) / per_block);
+      k = k1;
     }
+    c->classes.net_begin[p3d::kNumClasses] = (int32_t)order.size();
+    c->classes.block_begin[p3d::kNumClasses] = nb;
+    c->n_wa_blocks = nb;
   }
-  c->classes.net_begin[p3d::kNumClasses] = (int32_t)order.size();
-  int nb = 0;
-  for (int cl = 0; cl < p3d::kNumClasses; ++cl) {
-    c->classes.block_begin[cl] = nb;
-    const int per_block = p3d::kWaBlock / (2 << cl);
-    const int cnt = c->classes.net_begin[cl + 1] - c->classes.net_begin[cl];
-    nb += (cnt + per_block - 1) / per_block;
-  }
-  c->classes.block_begin[p3d::kNumClasses] = nb;
-  c->n_wa_blocks = nb;
 
   const int ms = (int)order.size();
   std::vector<int32_t> sns(ms + 1), spn(P > 0 ? P : 1), slot_of_pin(P > 0 ? P : 1);

@@ -14,8 +14,9 @@ namespace p3d {
 
 constexpr int kWave = 64;
 constexpr int kMaxNz = 16;
-constexpr int kNumClasses = 6;          // net groups of 2, 4, 8, 16, 32, 64 lanes
 constexpr int kWaBlock = 256;           // threads per wirelength block
+constexpr int kPinsPerLane = 4;         // net pins a wirelength lane keeps in registers
+constexpr int kNumClasses = 7;          // nets by lane group: 1, 2, 4, ..., 64 lanes
 
 // Reduction slots (float64, device) inside the workspace.
 enum RedSlot {
@@ -25,7 +26,8 @@ enum RedSlot {
   R_COUNT = 32
 };
 
-struct ClassTab {       // net schedule: nets and workgroups of each lane-group class
+
+struct ClassTab {       // net schedule in layout order: position i holds groups of 2^(kNumClasses-1-i) lanes
   int32_t net_begin[kNumClasses + 1];
   int32_t block_begin[kNumClasses + 1];
 };

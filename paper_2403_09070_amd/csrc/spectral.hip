@@ -34,6 +34,9 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ bases
 
@@ -295,16 +298,19 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
       *reinterpret_cast<u16x8*>(&L[r][kg]) = rbl[q];
     }
   };
+  // hi = RNE(v), lo = RNE(v - hi), two values per hardware conversion
   auto split_store = [&](unsigned short* h, unsigned short* l, const float* v) {
-    u16x8 hh, ll;
+    u32x4 hh, ll;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const unsigned short hb = bf16_rne(v[e]);
-      hh[e] = hb;
-      ll[e] = bf16_rne(v[e] - bf16_to_f32(hb));
+    for (int e = 0; e < 4; ++e) {
+      const f32x2 x = {v[2 * e], v[2 * e + 1]};
+      const unsigned hp = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2v));
+      const f32x2 back = {__uint_as_float(hp << 16), __uint_as_float(hp & 0xffff0000u)};
+      hh[e] = hp;
+      ll[e] = __builtin_bit_cast(unsigned, __builtin_convertvector(x - back, bf16x2v));
     }
-    *reinterpret_cast<u16x8*>(h) = hh;
-    *reinterpret_cast<u16x8*>(l) = ll;
+    *reinterpret_cast<u32x4*>(h) = hh;
+    *reinterpret_cast<u32x4*>(l) = ll;
   };
   // left data operand (map as A [M][K]): thread takes row f >> 2, k group (f & 3) * 8
   auto load_left_data = [&](int k0) {

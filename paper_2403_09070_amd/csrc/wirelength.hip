@@ -2,236 +2,304 @@
 // (Sec. III-A: Eqs. wa-model-approx, optimal-region, wl-obj, wl-model, fda-grad, fda-normalize;
 // Sec. IV-B: incremental evaluation from first and second extremes).
 //
-// Work split: nets are processed by lane groups of G = 2..64 lanes inside a wavefront (G the
-// smallest power of two >= the degree, 64 for larger nets, which then loop).  A static schedule
-// built at context creation orders nets by G, so a workgroup holds groups of one size.  Each lane
-// takes the pins k = lane, lane + G, ...; per-group reductions are xor butterflies.
+// Work split: a net of degree d is taken by a group of G = 1, 2, 4, ..., 64 lanes, the smallest
+// with d <= kPinsPerLane * G (64 lanes for larger nets, whose lanes then loop); most nets have
+// few pins and are taken by a single lane.  Lane l of a group holds pins l, l + G, ... in
+// registers and the group walks them three times: (A) first and second largest and smallest pin
+// coordinate per die set and axis, z extremes, set sizes; (B) max-shifted exponential sums per
+// set and axis, and over the whole net in z; (C) per pin: its share of the gradient of the
+// chosen branch, its WA z-gradient and the FDA difference.  Group reductions after (A) and (B)
+// are xor butterflies, symmetric, so every lane of a group holds the same net values.  A static
+// schedule built at context creation lays out nets by class, widest groups first, so a workgroup
+// holds groups of one size.
 //
-// Per net and axis the group reduces, for the top set e+ and the bottom set e-, the first and
-// second largest and smallest pin coordinates (Sec. IV-B) and max-shifted exponential sums for
-// the WA model.  Whole-net sums are the two partial sums rescaled to the whole-net shift.
+// Pin coordinates are taken relative to the x, y of the net's first pin's owner: the rounding of
+// each relative coordinate is then bounded by the net's span, not by the die size, and every
+// quantity computed here is invariant to that shift.
+//
+// Per net and axis:
 //   p^_S = (M_S + t+_S/s+_S) - (m_S + t-_S/s-_S)  with t+ = sum (u - M) e^{(u - M)/gamma}
 //   W^_u = max{p^_e, p^_e+ + p^_e-} for a net crossing the dies, else p^_e
 //   W_u  = max{p_e, p_e+ + p_e-}  (exact, the FDA and HPWL metric)
-// Each pin then writes its share of the gradient of the chosen branch, its WA z-gradient and
-// (4/d_z)(W_Bi(owner on top) - W_Bi(owner on bottom)) evaluated in O(1) from the extremes: the
-// pin leaves its set (the second extreme replaces it when it was the first) and joins the other
-// set at its other-die offset.
-//
-// Pin coordinates x + o are carried as an exact float pair (hi, lo) so that differences between
-// nearby pins keep full precision even at large absolute coordinates.
+// where the whole-net sums are the two set sums rescaled to the whole-net shifts.  The FDA of
+// a pin is (4/d_z)(W(owner on top) - W(owner on bottom)) in O(1): the pin leaves its set (the
+// second extreme replaces it when it was the first) and joins the other set at its other-die
+// offset.
 #include "internal.h"
 
 namespace p3d {
 namespace {
 
-struct DF { float h, l; };   // exact value h + l
-
-__device__ __forceinline__ DF two_sum(float a, float b) {
-  const float s = a + b;
-  const float bb = s - a;
-  const float err = (a - (s - bb)) + (b - bb);
-  return {s, err};
-}
-__device__ __forceinline__ float dsub(DF a, DF b) { return (a.h - b.h) + (a.l - b.l); }
-__device__ __forceinline__ bool dgt(DF a, DF b) { return a.h > b.h || (a.h == b.h && a.l > b.l); }
-__device__ __forceinline__ bool deq(DF a, DF b) { return a.h == b.h && a.l == b.l; }
-
 constexpr float kNegInf = -__builtin_huge_valf();
 constexpr float kPosInf = __builtin_huge_valf();
 
-// first and second largest of a multiset (duplicates kept); "min" versions store the smallest
-struct Top2 { DF a1, a2; };
-__device__ __forceinline__ Top2 top2_empty_max() { return {{kNegInf, 0.f}, {kNegInf, 0.f}}; }
-__device__ __forceinline__ Top2 top2_empty_min() { return {{kPosInf, 0.f}, {kPosInf, 0.f}}; }
-__device__ __forceinline__ void top2_put_max(Top2& t, DF v) {
-  if (dgt(v, t.a1)) { t.a2 = t.a1; t.a1 = v; }
-  else if (dgt(v, t.a2)) { t.a2 = v; }
-}
-__device__ __forceinline__ void top2_put_min(Top2& t, DF v) {
-  if (dgt(t.a1, v)) { t.a2 = t.a1; t.a1 = v; }
-  else if (dgt(t.a2, v)) { t.a2 = v; }
-}
-__device__ __forceinline__ DF shfl(DF v, int m) { return {__shfl_xor(v.h, m), __shfl_xor(v.l, m)}; }
-__device__ __forceinline__ void top2_merge_max(Top2& t, int m) {
-  Top2 o = {shfl(t.a1, m), shfl(t.a2, m)};
-  const DF hi = dgt(o.a1, t.a1) ? o.a1 : t.a1;
-  const DF lo = dgt(o.a1, t.a1) ? t.a1 : o.a1;     // the smaller of the two firsts
-  const DF s2 = dgt(o.a2, t.a2) ? o.a2 : t.a2;
-  t.a1 = hi;
-  t.a2 = dgt(lo, s2) ? lo : s2;
-}
-__device__ __forceinline__ void top2_merge_min(Top2& t, int m) {
-  Top2 o = {shfl(t.a1, m), shfl(t.a2, m)};
-  const DF lo = dgt(t.a1, o.a1) ? o.a1 : t.a1;
-  const DF hi = dgt(t.a1, o.a1) ? t.a1 : o.a1;
-  const DF s2 = dgt(t.a2, o.a2) ? o.a2 : t.a2;
-  t.a1 = lo;
-  t.a2 = dgt(s2, hi) ? hi : s2;
-}
-
-struct Ext {           // extremes of one set along one axis
-  Top2 mx, mn;
-};
-
-struct SetSums {       // max/min-shifted exponential sums of one set along one axis
-  float sp, tp, sm, tm;
-};
-
-struct PinData {
-  DF ux, uy;           // position on the current die
-  DF fx, fy;           // position on the other die
+struct PinRel {        // one pin, relative to the net anchor
+  float ux, uy;        // on its owner's current die
+  float fx, fy;        // on the other die
   float z;
   bool top;
-  int node;
 };
 
-__device__ __forceinline__ PinData load_pin(const float* __restrict__ xyz, int n, const int32_t* __restrict__ pin_node,
-                                            const float4* __restrict__ off, int slot, float half_dz) {
-  PinData p;
-  p.node = pin_node[slot];
+__device__ __forceinline__ PinRel load_pin(const float* __restrict__ xyz, int n, const int32_t* __restrict__ pin_node,
+                                           const float4* __restrict__ off, int slot, float half_dz, float xa, float ya) {
+  const int node = pin_node[slot];
   const float4 o = off[slot];
-  const float x = xyz[p.node], y = xyz[n + p.node];
-  p.z = xyz[2 * n + p.node];
+  const float dx = xyz[node] - xa, dy = xyz[n + node] - ya;
+  PinRel p;
+  p.z = xyz[2 * n + node];
   p.top = p.z > half_dz;
-  p.ux = two_sum(x, p.top ? o.z : o.x);
-  p.uy = two_sum(y, p.top ? o.w : o.y);
-  p.fx = two_sum(x, p.top ? o.x : o.z);
-  p.fy = two_sum(y, p.top ? o.y : o.w);
+  p.ux = dx + (p.top ? o.z : o.x);
+  p.uy = dy + (p.top ? o.w : o.y);
+  p.fx = dx + (p.top ? o.x : o.z);
+  p.fy = dy + (p.top ? o.y : o.w);
   return p;
 }
 
-// exact minimal D2D wirelength along one axis from the first extremes of the two sets
-__device__ __forceinline__ float bistratal_exact(DF tmax, DF tmin, int ct, DF bmax, DF bmin, int cb) {
-  const float pt = ct > 0 ? dsub(tmax, tmin) : 0.f;
-  const float pb = cb > 0 ? dsub(bmax, bmin) : 0.f;
-  DF wmax, wmin;
+// first and second largest and smallest of a multiset (duplicates kept)
+struct Ext2 { float max1, max2, min1, min2; };
+
+__device__ __forceinline__ Ext2 ext_empty() { return {kNegInf, kNegInf, kPosInf, kPosInf}; }
+// vmax / vmin: the value, or the -inf / +inf sentinel for a pin outside the set
+__device__ __forceinline__ void ext_put(Ext2& e, float vmax, float vmin) {
+  e.max2 = fmaxf(e.max2, fminf(e.max1, vmax));
+  e.max1 = fmaxf(e.max1, vmax);
+  e.min2 = fminf(e.min2, fmaxf(e.min1, vmin));
+  e.min1 = fminf(e.min1, vmin);
+}
+__device__ __forceinline__ Ext2 ext_sel(bool c, const Ext2& a, const Ext2& b) {
+  return {c ? a.max1 : b.max1, c ? a.max2 : b.max2, c ? a.min1 : b.min1, c ? a.min2 : b.min2};
+}
+
+struct NetExt {
+  Ext2 tx, ty, bx, by;        // top / bottom set, x / y
+  float zmax, zmin;
+  int ct, cb;
+};
+
+// every set is updated with values or sentinels (no branch on the die): a branch would let
+// the compiler select between the sets' addresses and move them to scratch memory
+__device__ __forceinline__ void ext_add(NetExt& a, const PinRel& p) {
+  const float tx_hi = p.top ? p.ux : kNegInf, tx_lo = p.top ? p.ux : kPosInf;
+  const float bx_hi = p.top ? kNegInf : p.ux, bx_lo = p.top ? kPosInf : p.ux;
+  const float ty_hi = p.top ? p.uy : kNegInf, ty_lo = p.top ? p.uy : kPosInf;
+  const float by_hi = p.top ? kNegInf : p.uy, by_lo = p.top ? kPosInf : p.uy;
+  ext_put(a.tx, tx_hi, tx_lo);
+  ext_put(a.bx, bx_hi, bx_lo);
+  ext_put(a.ty, ty_hi, ty_lo);
+  ext_put(a.by, by_hi, by_lo);
+  a.ct += p.top ? 1 : 0;
+  a.cb += p.top ? 0 : 1;
+  a.zmax = fmaxf(a.zmax, p.z);
+  a.zmin = fminf(a.zmin, p.z);
+}
+
+__device__ __forceinline__ void ext_merge(Ext2& e, int m) {
+  const float a1 = __shfl_xor(e.max1, m), a2 = __shfl_xor(e.max2, m);
+  const float b1 = __shfl_xor(e.min1, m), b2 = __shfl_xor(e.min2, m);
+  e.max2 = fmaxf(fmaxf(e.max2, a2), fminf(e.max1, a1));
+  e.max1 = fmaxf(e.max1, a1);
+  e.min2 = fminf(fminf(e.min2, b2), fmaxf(e.min1, b1));
+  e.min1 = fminf(e.min1, b1);
+}
+
+struct Sums4 { float sp, tp, sm, tm; };
+
+__device__ __forceinline__ void sums_merge(Sums4& s, int m) {
+  s.sp += __shfl_xor(s.sp, m); s.tp += __shfl_xor(s.tp, m);
+  s.sm += __shfl_xor(s.sm, m); s.tm += __shfl_xor(s.tm, m);
+}   // max- and min-shifted exponential sums
+
+struct NetSums { Sums4 xt, xb, yt, yb, z; };
+
+__device__ __forceinline__ void sums_add(Sums4& s, bool in, float du, float dl, float ep, float em) {
+  s.sp += in ? ep : 0.f;
+  s.tp += in ? du * ep : 0.f;
+  s.sm += in ? em : 0.f;
+  s.tm += in ? dl * em : 0.f;
+}
+
+__device__ __forceinline__ void sums_pin(NetSums& S, const NetExt& a, const PinRel& p, float ig) {
+  const float Mx = p.top ? a.tx.max1 : a.bx.max1, mx = p.top ? a.tx.min1 : a.bx.min1;
+  const float My = p.top ? a.ty.max1 : a.by.max1, my = p.top ? a.ty.min1 : a.by.min1;
+  const float dux = p.ux - Mx, dlx = p.ux - mx, duy = p.uy - My, dly = p.uy - my;
+  const float epx = __expf(dux * ig), emx = __expf(-dlx * ig);
+  const float epy = __expf(duy * ig), emy = __expf(-dly * ig);
+  sums_add(S.xt, p.top, dux, dlx, epx, emx);
+  sums_add(S.xb, !p.top, dux, dlx, epx, emx);
+  sums_add(S.yt, p.top, duy, dly, epy, emy);
+  sums_add(S.yb, !p.top, duy, dly, epy, emy);
+  const float duz = p.z - a.zmax, dlz = p.z - a.zmin;
+  sums_add(S.z, true, duz, dlz, __expf(duz * ig), __expf(-dlz * ig));
+}
+
+// gradient coefficients of one set along one axis for the chosen branch:
+//   dW^/du = e^{(u-M)/g} ap (1 + (u - M - bp)/g) - e^{-(u-m)/g} am (1 - (u - m - bm)/g)
+struct SetCoef { float M, m, ap, bp, am, bm; };
+
+struct AxisCoef {
+  SetCoef t, b;
+  float W;                    // smoothed bistratal value
+};
+
+__device__ __forceinline__ AxisCoef axis_coef(const Ext2& T, const Sums4& st, int ct, const Ext2& B, const Sums4& sb,
+                                              int cb, float ig) {
+  const float Mt = T.max1, mt = T.min1, Mb = B.max1, mb = B.min1;
+  const float At_p = ct > 0 ? st.tp / st.sp : 0.f, At_m = ct > 0 ? st.tm / st.sm : 0.f;
+  const float Ab_p = cb > 0 ? sb.tp / sb.sp : 0.f, Ab_m = cb > 0 ? sb.tm / sb.sm : 0.f;
+  const float pt = ct > 0 ? (Mt - mt) + (At_p - At_m) : 0.f;
+  const float pb = cb > 0 ? (Mb - mb) + (Ab_p - Ab_m) : 0.f;
+  AxisCoef c;
   if (ct > 0 && cb > 0) {
-    wmax = dgt(tmax, bmax) ? tmax : bmax;
-    wmin = dgt(tmin, bmin) ? bmin : tmin;
-  } else if (ct > 0) { wmax = tmax; wmin = tmin; }
-  else { wmax = bmax; wmin = bmin; }
-  const float pe = (ct + cb) > 0 ? dsub(wmax, wmin) : 0.f;
+    // whole net: both set sums rescaled to the whole-net shifts
+    const float Me = fmaxf(Mt, Mb), me = fminf(mt, mb);
+    const float dt = Mt - Me, db = Mb - Me;          // <= 0
+    const float rt = __expf(dt * ig), rb = __expf(db * ig);
+    const float se_p = st.sp * rt + sb.sp * rb;
+    const float Ae_p = (rt * (st.tp + dt * st.sp) + rb * (sb.tp + db * sb.sp)) / se_p;
+    const float dtm = mt - me, dbm = mb - me;         // >= 0
+    const float qt = __expf(-dtm * ig), qb = __expf(-dbm * ig);
+    const float se_m = st.sm * qt + sb.sm * qb;
+    const float Ae_m = (qt * (st.tm + dtm * st.sm) + qb * (sb.tm + dbm * sb.sm)) / se_m;
+    const float pe = (Me - me) + (Ae_p - Ae_m);
+    const bool split = pt + pb > pe;
+    c.W = split ? pt + pb : pe;
+    if (split) {
+      c.t = {Mt, mt, 1.f / st.sp, At_p, 1.f / st.sm, At_m};
+      c.b = {Mb, mb, 1.f / sb.sp, Ab_p, 1.f / sb.sm, Ab_m};
+    } else {
+      const float ie_p = 1.f / se_p, ie_m = 1.f / se_m;
+      c.t = {Mt, mt, rt * ie_p, Ae_p - dt, qt * ie_m, Ae_m - dtm};
+      c.b = {Mb, mb, rb * ie_p, Ae_p - db, qb * ie_m, Ae_m - dbm};
+    }
+  } else {
+    // one set only: the whole net is that set
+    c.W = ct > 0 ? pt : pb;
+    c.t = {Mt, mt, ct > 0 ? 1.f / st.sp : 0.f, At_p, ct > 0 ? 1.f / st.sm : 0.f, At_m};
+    c.b = {Mb, mb, cb > 0 ? 1.f / sb.sp : 0.f, Ab_p, cb > 0 ? 1.f / sb.sm : 0.f, Ab_m};
+  }
+  return c;
+}
+
+__device__ __forceinline__ float axis_grad(const AxisCoef& c, bool top, float u, float ig) {
+  const float M = top ? c.t.M : c.b.M, m = top ? c.t.m : c.b.m;
+  const float ap = top ? c.t.ap : c.b.ap, bp = top ? c.t.bp : c.b.bp;
+  const float am = top ? c.t.am : c.b.am, bm = top ? c.t.bm : c.b.bm;
+  const float du = u - M, dl = u - m;
+  return __expf(du * ig) * ap * (1.f + (du - bp) * ig) - __expf(-dl * ig) * am * (1.f - (dl - bm) * ig);
+}
+
+// exact bistratal extent along one axis from the first extremes of the two sets (empty sets
+// hold the -inf / +inf sentinels)
+__device__ __forceinline__ float w_exact(float tmax, float tmin, int ct, float bmax, float bmin, int cb) {
+  const float pt = ct > 0 ? tmax - tmin : 0.f;
+  const float pb = cb > 0 ? bmax - bmin : 0.f;
+  const float pe = (ct + cb) > 0 ? fmaxf(tmax, bmax) - fminf(tmin, bmin) : 0.f;
   return fmaxf(pe, pt + pb);
 }
 
-// W along one axis with one pin moved from its set S to the other set O at position f
-__device__ __forceinline__ float bistratal_flip(const Ext& S, int cs, const Ext& O, int co, DF u, DF f) {
-  DF smax = S.mx.a1, smin = S.mn.a1;
-  if (deq(u, smax)) smax = S.mx.a2;
-  if (deq(u, smin)) smin = S.mn.a2;
-  const int cs2 = cs - 1;
-  DF omax = O.mx.a1, omin = O.mn.a1;
-  if (co == 0) { omax = f; omin = f; }
-  else {
-    if (dgt(f, omax)) omax = f;
-    if (dgt(omin, f)) omin = f;
-  }
-  return bistratal_exact(smax, smin, cs2, omax, omin, co + 1);
+// the same with one pin (at u in set S) moved to the other set O at f
+__device__ __forceinline__ float w_flip(Ext2 S, int cs, Ext2 O, int co, float u, float f) {
+  const float smax = u == S.max1 ? S.max2 : S.max1;
+  const float smin = u == S.min1 ? S.min2 : S.min1;
+  return w_exact(smax, smin, cs - 1, fmaxf(O.max1, f), fminf(O.min1, f), co + 1);
 }
 
-struct AxisWA {        // smoothed WA pieces along one axis, for the gradient of the chosen branch
-  float Mt, At_p, st_p, mt, At_m, st_m;   // top set: shift and (A - shift) terms
-  float Mb, Ab_p, sb_p, mb, Ab_m, sb_m;   // bottom set
-  float Me, Ae_p, se_p, me, Ae_m, se_m;   // whole net
-  float rt, rb, qt, qb;                   // e^{(M_S - M_e)/gamma}, e^{-(m_S - m_e)/gamma} per set
-  bool split;
-  float W;                                  // smoothed value
+struct NetCoef {
+  AxisCoef x, y;
+  float zmax, zmin, az_p, Az_p, az_m, Az_m;
+  float Wx, Wy;
 };
 
-// Combine partial sums into the WA extents.  Shifts are the hi parts of the first extremes;
-// A+_S = t+_S / s+_S is the weighted mean of (u - M_S) (<= 0).
-__device__ __forceinline__ AxisWA axis_wa(const Ext& T, const SetSums& st, int ct, const Ext& B, const SetSums& sb,
-                                          int cb, float inv_gamma) {
-  AxisWA a;
-  a.Mt = T.mx.a1.h; a.mt = T.mn.a1.h; a.Mb = B.mx.a1.h; a.mb = B.mn.a1.h;
-  a.st_p = st.sp; a.st_m = st.sm; a.sb_p = sb.sp; a.sb_m = sb.sm;
-  a.At_p = ct > 0 ? st.tp / st.sp : 0.f;
-  a.At_m = ct > 0 ? st.tm / st.sm : 0.f;
-  a.Ab_p = cb > 0 ? sb.tp / sb.sp : 0.f;
-  a.Ab_m = cb > 0 ? sb.tm / sb.sm : 0.f;
-  a.rt = a.rb = a.qt = a.qb = 1.f;
-  const float pt = ct > 0 ? (a.Mt - a.mt) + (a.At_p - a.At_m) : 0.f;
-  const float pb = cb > 0 ? (a.Mb - a.mb) + (a.Ab_p - a.Ab_m) : 0.f;
-  // whole net: rescale the partial sums to the whole-net shifts
-  if (ct > 0 && cb > 0) {
-    a.Me = fmaxf(a.Mt, a.Mb);
-    a.me = fminf(a.mt, a.mb);
-    const float dt = a.Mt - a.Me, db = a.Mb - a.Me;                 // <= 0
-    a.rt = __expf(dt * inv_gamma);
-    a.rb = __expf(db * inv_gamma);
-    a.se_p = st.sp * a.rt + sb.sp * a.rb;
-    const float te_p = a.rt * (st.tp + dt * st.sp) + a.rb * (sb.tp + db * sb.sp);
-    const float dtm = a.mt - a.me, dbm = a.mb - a.me;              // >= 0
-    a.qt = __expf(-dtm * inv_gamma);
-    a.qb = __expf(-dbm * inv_gamma);
-    a.se_m = st.sm * a.qt + sb.sm * a.qb;
-    const float te_m = a.qt * (st.tm + dtm * st.sm) + a.qb * (sb.tm + dbm * sb.sm);
-    a.Ae_p = te_p / a.se_p;
-    a.Ae_m = te_m / a.se_m;
-  } else if (ct > 0) {
-    a.Me = a.Mt; a.me = a.mt; a.se_p = st.sp; a.se_m = st.sm; a.Ae_p = a.At_p; a.Ae_m = a.At_m;
-  } else {
-    a.Me = a.Mb; a.me = a.mb; a.se_p = sb.sp; a.se_m = sb.sm; a.Ae_p = a.Ab_p; a.Ae_m = a.Ab_m;
+// per pin: (dW^/dx, dW^/dy, alpha dW^z/dz, FDA difference)
+__device__ __forceinline__ float4 pin_result(const PinRel& p, const NetExt& a, const NetCoef& c, float ig, float alpha,
+                                             float four_over_dz) {
+  const float gx = axis_grad(c.x, p.top, p.ux, ig);
+  const float gy = axis_grad(c.y, p.top, p.uy, ig);
+  const float duz = p.z - c.zmax, dlz = p.z - c.zmin;
+  const float gz = alpha * (__expf(duz * ig) * c.az_p * (1.f + (duz - c.Az_p) * ig) -
+                            __expf(-dlz * ig) * c.az_m * (1.f - (dlz - c.Az_m) * ig));
+  const int cs = p.top ? a.ct : a.cb, co = p.top ? a.cb : a.ct;
+  const float wfx = w_flip(ext_sel(p.top, a.tx, a.bx), cs, ext_sel(p.top, a.bx, a.tx), co, p.ux, p.fx);
+  const float wfy = w_flip(ext_sel(p.top, a.ty, a.by), cs, ext_sel(p.top, a.by, a.ty), co, p.uy, p.fy);
+  // (4/d_z) (W with the owner on top - W with it on the bottom)
+  const float dw = (wfx - c.Wx) + (wfy - c.Wy);
+  return make_float4(gx, gy, gz, four_over_dz * (p.top ? -dw : dw));
+}
+
+struct NetTotals { double wa_bi, wa_z, hpwl, hpwl3d, ncut; };
+
+// one net per group of G lanes; lane lg of the group holds pins lg + G j
+template <int G>
+__device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half_dz, float four_over_dz, float ig,
+                                              float alpha, const float* __restrict__ xyz,
+                                              const int32_t* __restrict__ s_net_start,
+                                              const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
+                                              const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out) {
+  const int s = s_net_start[net], d = s_net_start[net + 1] - s;
+  const int node0 = pin_node[s];
+  const float xa = xyz[node0], ya = xyz[n + node0];
+  PinRel pc[kPinsPerLane];
+
+  // ---- phase A: extremes
+  NetExt a = {ext_empty(), ext_empty(), ext_empty(), ext_empty(), kNegInf, kPosInf, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kPinsPerLane; ++j)
+    if (lg + G * j < d) {
+      pc[j] = load_pin(xyz, n, pin_node, off, s + lg + G * j, half_dz, xa, ya);
+      ext_add(a, pc[j]);
+    }
+  for (int k = lg + G * kPinsPerLane; k < d; k += G) ext_add(a, load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya));
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) {
+    ext_merge(a.tx, m); ext_merge(a.bx, m); ext_merge(a.ty, m); ext_merge(a.by, m);
+    a.zmax = fmaxf(a.zmax, __shfl_xor(a.zmax, m));
+    a.zmin = fminf(a.zmin, __shfl_xor(a.zmin, m));
+    a.ct += __shfl_xor(a.ct, m);
+    a.cb += __shfl_xor(a.cb, m);
   }
-  const float pe = (a.Me - a.me) + (a.Ae_p - a.Ae_m);
-  a.split = (ct > 0 && cb > 0) && (pt + pb > pe);
-  a.W = a.split ? pt + pb : pe;
-  return a;
-}
 
-// a pin's offsets from its set's shifts and the shifted exponentials (phase B), kept for phase C
-struct PinExp { float dux, dlx, epx, emx, duy, dly, epy, emy, duz, dlz, epz, emz; };
-
-__device__ __forceinline__ PinExp pin_exps(const PinData& p, const Ext& tx, const Ext& bx, const Ext& ty,
-                                           const Ext& by, float zmax, float zmin, float inv_gamma) {
-  PinExp e;
-  const float Mx = p.top ? tx.mx.a1.h : bx.mx.a1.h, mx = p.top ? tx.mn.a1.h : bx.mn.a1.h;
-  const float My = p.top ? ty.mx.a1.h : by.mx.a1.h, my = p.top ? ty.mn.a1.h : by.mn.a1.h;
-  e.dux = (p.ux.h - Mx) + p.ux.l; e.dlx = (p.ux.h - mx) + p.ux.l;
-  e.duy = (p.uy.h - My) + p.uy.l; e.dly = (p.uy.h - my) + p.uy.l;
-  e.duz = p.z - zmax; e.dlz = p.z - zmin;
-  e.epx = __expf(e.dux * inv_gamma); e.emx = __expf(-e.dlx * inv_gamma);
-  e.epy = __expf(e.duy * inv_gamma); e.emy = __expf(-e.dly * inv_gamma);
-  e.epz = __expf(e.duz * inv_gamma); e.emz = __expf(-e.dlz * inv_gamma);
-  return e;
-}
-
-__device__ __forceinline__ void add_sums(const PinExp& e, bool top, SetSums& sxt, SetSums& sxb, SetSums& syt,
-                                         SetSums& syb, SetSums& sz) {
-  if (top) {
-    sxt.sp += e.epx; sxt.tp += e.dux * e.epx; sxt.sm += e.emx; sxt.tm += e.dlx * e.emx;
-    syt.sp += e.epy; syt.tp += e.duy * e.epy; syt.sm += e.emy; syt.tm += e.dly * e.emy;
-  } else {
-    sxb.sp += e.epx; sxb.tp += e.dux * e.epx; sxb.sm += e.emx; sxb.tm += e.dlx * e.emx;
-    syb.sp += e.epy; syb.tp += e.duy * e.epy; syb.sm += e.emy; syb.tm += e.dly * e.emy;
+  // ---- phase B: shifted exponential sums
+  NetSums S = {};
+#pragma unroll
+  for (int j = 0; j < kPinsPerLane; ++j)
+    if (lg + G * j < d) sums_pin(S, a, pc[j], ig);
+  for (int k = lg + G * kPinsPerLane; k < d; k += G)
+    sums_pin(S, a, load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya), ig);
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) {
+    sums_merge(S.xt, m); sums_merge(S.xb, m); sums_merge(S.yt, m); sums_merge(S.yb, m); sums_merge(S.z, m);
   }
-  sz.sp += e.epz; sz.tp += e.duz * e.epz; sz.sm += e.emz; sz.tm += e.dlz * e.emz;
-}
 
-// d W^ / d u for one pin of the chosen branch, from its set-shifted offsets and exponentials.
-// Every field is passed by value so that the branch choice is a select between values.
-__device__ __forceinline__ float grad_branch(bool split, bool top, float du, float dl, float ep, float em,
-                                             float inv_gamma, float Mt, float Mb, float Me, float mt, float mb,
-                                             float me, float rt, float rb, float qt, float qb, float At_p, float Ab_p,
-                                             float Ae_p, float st_p, float sb_p, float se_p, float At_m, float Ab_m,
-                                             float Ae_m, float st_m, float sb_m, float se_m) {
-  const float Ap_s = top ? At_p : Ab_p, sp_s = top ? st_p : sb_p;
-  const float Am_s = top ? At_m : Ab_m, sm_s = top ? st_m : sb_m;
-  // whole-net branch: move from the set's shifts to the whole-net shifts
-  const float du_e = du + ((top ? Mt : Mb) - Me), dl_e = dl + ((top ? mt : mb) - me);
-  const float ep_e = ep * (top ? rt : rb), em_e = em * (top ? qt : qb);
-  const float Ap = split ? Ap_s : Ae_p, sp = split ? sp_s : se_p;
-  const float Am = split ? Am_s : Ae_m, sm = split ? sm_s : se_m;
-  const float u = split ? du : du_e, l = split ? dl : dl_e;
-  const float p = split ? ep : ep_e, q = split ? em : em_e;
-  return p / sp * (1.f + (u - Ap) * inv_gamma) - q / sm * (1.f - (l - Am) * inv_gamma);
-}
+  NetCoef c;
+  c.x = axis_coef(a.tx, S.xt, a.ct, a.bx, S.xb, a.cb, ig);
+  c.y = axis_coef(a.ty, S.yt, a.ct, a.by, S.yb, a.cb, ig);
+  c.zmax = a.zmax; c.zmin = a.zmin;
+  c.az_p = 1.f / S.z.sp; c.Az_p = S.z.tp * c.az_p;
+  c.az_m = 1.f / S.z.sm; c.Az_m = S.z.tm * c.az_m;
+  c.Wx = w_exact(a.tx.max1, a.tx.min1, a.ct, a.bx.max1, a.bx.min1, a.cb);
+  c.Wy = w_exact(a.ty.max1, a.ty.min1, a.ct, a.by.max1, a.by.min1, a.cb);
 
-#define P3D_AXIS_GRAD(a, top, du, dl, ep, em)                                                          \
-  grad_branch((a).split, top, du, dl, ep, em, inv_gamma, (a).Mt, (a).Mb, (a).Me, (a).mt, (a).mb, (a).me, \
-              (a).rt, (a).rb, (a).qt, (a).qb, (a).At_p, (a).Ab_p, (a).Ae_p, (a).st_p, (a).sb_p, (a).se_p, \
-              (a).At_m, (a).Ab_m, (a).Ae_m, (a).st_m, (a).sb_m, (a).se_m)
+  // ---- phase C: per-pin results, written at the pin's node-ordered position
+#pragma unroll
+  for (int j = 0; j < kPinsPerLane; ++j)
+    if (lg + G * j < d) pin_out[slot_pos[s + lg + G * j]] = pin_result(pc[j], a, c, ig, alpha, four_over_dz);
+  for (int k = lg + G * kPinsPerLane; k < d; k += G)
+    pin_out[slot_pos[s + k]] =
+        pin_result(load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
+
+  // ---- net totals, from the group's first lane
+  NetTotals t = {0, 0, 0, 0, 0};
+  if (lg == 0) {
+    t.wa_bi = (double)c.x.W + (double)c.y.W;
+    t.wa_z = (double)alpha * (double)((a.zmax - a.zmin) + (c.Az_p - c.Az_m));
+    t.hpwl = (double)c.Wx + (double)c.Wy;
+    t.hpwl3d = (double)(fmaxf(a.tx.max1, a.bx.max1) - fminf(a.tx.min1, a.bx.min1)) +
+               (double)(fmaxf(a.ty.max1, a.by.max1) - fminf(a.ty.min1, a.by.min1)) +
+               (double)alpha * (double)(a.zmax - a.zmin);
+    t.ncut = (a.ct > 0 && a.cb > 0) ? 1.0 : 0.0;
+  }
+  return t;
+}
 
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     int n, float half_dz, float four_over_dz, float gamma, float alpha, const float* __restrict__ xyz,
@@ -239,131 +307,30 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part,
     int stride) {
   __shared__ double shred[5][kWaBlock / kWave];
-  __shared__ int cls_s;
-  if (threadIdx.x == 0) {
-    int c = 0;
-    while (c + 1 < kNumClasses && (int)blockIdx.x >= tab.block_begin[c + 1]) ++c;
-    cls_s = c;
-  }
-  __syncthreads();
-  const int cls = cls_s;
-  const int G = 2 << cls;
-  const int lane = threadIdx.x & (G - 1);
-  const int group = threadIdx.x / G;
-  const int net = tab.net_begin[cls] + ((int)blockIdx.x - tab.block_begin[cls]) * (kWaBlock / G) + group;
-  const bool active = net < tab.net_begin[cls + 1];
-  const float inv_gamma = 1.f / gamma;
-
-  int s = 0, d = 0;
-  if (active) { s = s_net_start[net]; d = s_net_start[net + 1] - s; }
-  // the lane's first pin stays in registers through all phases; further pins (nets larger than
-  // the group, only in the 64-lane class) are reloaded per phase
-  const bool have0 = lane < d;
-  PinData p0;
-  if (have0) p0 = load_pin(xyz, n, pin_node, off, s + lane, half_dz);
-
-  // ---- phase A: extremes per set and axis, z extremes, set sizes
-  Ext tx = {top2_empty_max(), top2_empty_min()}, ty = tx, bx = tx, by = tx;
-  float zmax = kNegInf, zmin = kPosInf;
-  int ct = 0, cb = 0;
-#define P3D_PUT(p)                                                          \
-  do {                                                                      \
-    if ((p).top) {                                                          \
-      top2_put_max(tx.mx, (p).ux); top2_put_min(tx.mn, (p).ux);             \
-      top2_put_max(ty.mx, (p).uy); top2_put_min(ty.mn, (p).uy);             \
-      ++ct;                                                                 \
-    } else {                                                                \
-      top2_put_max(bx.mx, (p).ux); top2_put_min(bx.mn, (p).ux);             \
-      top2_put_max(by.mx, (p).uy); top2_put_min(by.mn, (p).uy);             \
-      ++cb;                                                                 \
-    }                                                                       \
-    zmax = fmaxf(zmax, (p).z); zmin = fminf(zmin, (p).z);                   \
-  } while (0)
-  if (have0) P3D_PUT(p0);
-  for (int k = lane + G; k < d; k += G) {
-    const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    P3D_PUT(p);
-  }
-#undef P3D_PUT
-  for (int m = G >> 1; m > 0; m >>= 1) {
-    top2_merge_max(tx.mx, m); top2_merge_min(tx.mn, m);
-    top2_merge_max(ty.mx, m); top2_merge_min(ty.mn, m);
-    top2_merge_max(bx.mx, m); top2_merge_min(bx.mn, m);
-    top2_merge_max(by.mx, m); top2_merge_min(by.mn, m);
-    zmax = fmaxf(zmax, __shfl_xor(zmax, m));
-    zmin = fminf(zmin, __shfl_xor(zmin, m));
-    ct += __shfl_xor(ct, m);
-    cb += __shfl_xor(cb, m);
-  }
-
-  // ---- phase B: shifted exponential sums per set and axis, and for z over the whole net
-  SetSums sxt = {0, 0, 0, 0}, sxb = sxt, syt = sxt, syb = sxt, sz = sxt;
-  PinExp e0 = {};
-  if (have0) {
-    e0 = pin_exps(p0, tx, bx, ty, by, zmax, zmin, inv_gamma);
-    add_sums(e0, p0.top, sxt, sxb, syt, syb, sz);
-  }
-  for (int k = lane + G; k < d; k += G) {
-    const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    add_sums(pin_exps(p, tx, bx, ty, by, zmax, zmin, inv_gamma), p.top, sxt, sxb, syt, syb, sz);
-  }
-  for (int m = G >> 1; m > 0; m >>= 1) {
-#define P3D_RED4(S) S.sp += __shfl_xor(S.sp, m); S.tp += __shfl_xor(S.tp, m); \
-                    S.sm += __shfl_xor(S.sm, m); S.tm += __shfl_xor(S.tm, m);
-    P3D_RED4(sxt) P3D_RED4(sxb) P3D_RED4(syt) P3D_RED4(syb) P3D_RED4(sz)
-#undef P3D_RED4
-  }
-
-  const AxisWA wx = axis_wa(tx, sxt, ct, bx, sxb, cb, inv_gamma);
-  const AxisWA wy = axis_wa(ty, syt, ct, by, syb, cb, inv_gamma);
-  const float Azp = d > 0 ? sz.tp / sz.sp : 0.f, Azm = d > 0 ? sz.tm / sz.sm : 0.f;
-  const float pz = d > 0 ? (zmax - zmin) + (Azp - Azm) : 0.f;
-  const float Wx = bistratal_exact(tx.mx.a1, tx.mn.a1, ct, bx.mx.a1, bx.mn.a1, cb);
-  const float Wy = bistratal_exact(ty.mx.a1, ty.mn.a1, ct, by.mx.a1, by.mn.a1, cb);
-
-  // ---- phase C: per-pin gradient shares and FDA differences
-#define P3D_EMIT(p, e, slot)                                                                   \
-  do {                                                                                         \
-    const float gx_ = P3D_AXIS_GRAD(wx, (p).top, (e).dux, (e).dlx, (e).epx, (e).emx);          \
-    const float gy_ = P3D_AXIS_GRAD(wy, (p).top, (e).duy, (e).dly, (e).epy, (e).emy);          \
-    const float gz_ = alpha * ((e).epz / sz.sp * (1.f + ((e).duz - Azp) * inv_gamma) -         \
-                               (e).emz / sz.sm * (1.f - ((e).dlz - Azm) * inv_gamma));         \
-    float wfx_, wfy_;                                                                          \
-    if ((p).top) {                                                                             \
-      wfx_ = bistratal_flip(tx, ct, bx, cb, (p).ux, (p).fx);                                   \
-      wfy_ = bistratal_flip(ty, ct, by, cb, (p).uy, (p).fy);                                   \
-    } else {                                                                                   \
-      wfx_ = bistratal_flip(bx, cb, tx, ct, (p).ux, (p).fx);                                   \
-      wfy_ = bistratal_flip(by, cb, ty, ct, (p).uy, (p).fy);                                   \
-    }                                                                                          \
-    /* (4/d_z) (W with the owner on top - W with it on the bottom) */                          \
-    const float dw_ = (wfx_ - Wx) + (wfy_ - Wy);                                               \
-    pin_out[slot_pos[slot]] = make_float4(gx_, gy_, gz_, four_over_dz * ((p).top ? -dw_ : dw_)); \
-  } while (0)
-  if (have0) P3D_EMIT(p0, e0, s + lane);
-  for (int k = lane + G; k < d; k += G) {
-    const PinData p = load_pin(xyz, n, pin_node, off, s + k, half_dz);
-    const PinExp e = pin_exps(p, tx, bx, ty, by, zmax, zmin, inv_gamma);
-    P3D_EMIT(p, e, s + k);
-  }
-#undef P3D_EMIT
-
-  // ---- net totals: one contribution per group, block-reduced in float64
-  double v[5] = {0, 0, 0, 0, 0};
-  if (active && lane == 0 && d > 0) {
-    DF xmax = tx.mx.a1, xmin = tx.mn.a1, ymax = ty.mx.a1, ymin = ty.mn.a1;
-    if (cb > 0) {
-      if (ct == 0 || dgt(bx.mx.a1, xmax)) xmax = bx.mx.a1;
-      if (ct == 0 || dgt(xmin, bx.mn.a1)) xmin = bx.mn.a1;
-      if (ct == 0 || dgt(by.mx.a1, ymax)) ymax = by.mx.a1;
-      if (ct == 0 || dgt(ymin, by.mn.a1)) ymin = by.mn.a1;
+  int pos = 0;                                     // layout position of this block's class
+  while (pos + 1 < kNumClasses && (int)blockIdx.x >= tab.block_begin[pos + 1]) ++pos;
+  const int lg2 = kNumClasses - 1 - pos;           // log2 of the group width
+  const int net = tab.net_begin[pos] + ((int)blockIdx.x - tab.block_begin[pos]) * (kWaBlock >> lg2) +
+                  ((int)threadIdx.x >> lg2);
+  const int lg = threadIdx.x & ((1 << lg2) - 1);
+  const float ig = 1.f / gamma;
+  NetTotals t = {0, 0, 0, 0, 0};
+  if (net < tab.net_begin[pos + 1]) {
+#define P3D_GROUP(G) \
+  wl_group<G>(net, lg, n, half_dz, four_over_dz, ig, alpha, xyz, s_net_start, pin_node, off, slot_pos, pin_out)
+    switch (lg2) {
+      case 0: t = P3D_GROUP(1); break;
+      case 1: t = P3D_GROUP(2); break;
+      case 2: t = P3D_GROUP(4); break;
+      case 3: t = P3D_GROUP(8); break;
+      case 4: t = P3D_GROUP(16); break;
+      case 5: t = P3D_GROUP(32); break;
+      default: t = P3D_GROUP(64); break;
     }
-    v[0] = (double)wx.W + (double)wy.W;
-    v[1] = (double)alpha * (double)pz;
-    v[2] = (double)Wx + (double)Wy;
-    v[3] = (double)dsub(xmax, xmin) + (double)dsub(ymax, ymin) + (double)alpha * (double)(zmax - zmin);
-    v[4] = (ct > 0 && cb > 0) ? 1.0 : 0.0;
+#undef P3D_GROUP
   }
+  const double v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
+#pragma unroll
   for (int q = 0; q < 5; ++q) {
     double x = v[q];
     for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
