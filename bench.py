@@ -34,13 +34,17 @@ PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 
 def gemm_flops_per_step(nx, ny, nz, dgrad_field, bf16x3):
     """Executed MFMA flops of the DCT contractions in one step (3 products per contraction in the
-    split form).  x passes: M = nz ny, N = K = nx; y passes: nz batches of M = ny, N = nx, K = ny."""
+    split form).  Dense: x passes M = nz ny, N = K = nx; y passes nz batches of M = ny, N = nx,
+    K = ny.  With even nx and ny every pass is folded into an even and an odd half of half the
+    size each, which halves its flops."""
     x_pass = 2.0 * nz * ny * nx * nx
     y_pass = 2.0 * nz * ny * nx * ny
     if dgrad_field:          # forward x, y; inverse y (cos, sin); inverse x (Ex, Ey, Ez)
         total = x_pass + y_pass + 2 * y_pass + 3 * x_pass
     else:                    # forward x, y; inverse y (cos); inverse x (phi)
         total = x_pass + y_pass + y_pass + x_pass
+    if nx % 2 == 0 and ny % 2 == 0:
+        total *= 0.5
     return total * (3.0 if bf16x3 else 1.0)
 
 
@@ -54,6 +58,29 @@ def density_bytes(n, bins):
     """Algorithmic bytes of the density map: per instance xyz and four sizes (28 B), per bin the
     fixed-instance map read and the map write (8 B)."""
     return 28.0 * n + 8.0 * bins
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+
+
+def recorded_traffic(stage, form):
+    """HBM bytes per launch of a stage, from the rocprofv3 FETCH_SIZE / WRITE_SIZE counts recorded in
+    profiles/hbm_traffic.txt (already scaled by the copy-kernel factors noted there), or None when
+    nothing is recorded for this stage and form or the stage's kernel source has changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("stage="):
+            continue
+        rec = dict(kv.split("=", 1) for kv in line.split())
+        if rec.get("stage") != stage or rec.get("form") != form:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    return None
 
 
 def run_form(case, precision, dgrad, steps, warmup, profile_steps, log):
@@ -135,6 +162,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,mixed")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
+                         "known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     if args.gpus != 1:
@@ -145,6 +175,14 @@ def main():
     from paper_2403_09070_amd import place3d, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     place3d.lib()
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] copied {args.copy_mb} MiB x3")
     log(f"[bench] generating {args.config} seed {args.seed}")
     case = synth.make_case(args.config, args.seed)
     forms = {"plain": (place3d.FP32, place3d.DGRAD_FIELD), "mixed": (place3d.BF16X3, place3d.DGRAD_FIELD),
@@ -179,8 +217,9 @@ def main():
         lps = launches / ps
         avg_ms = ms / launches
         achieved = (work / lps) / (avg_ms / 1e3)        # per launch / average launch duration
+        traffic = recorded_traffic(key, head_name)
         roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": key,
+                "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": key,
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_step": lps,
                 "stage_ms_per_step": {k: round(v, 4) for k, v in per_step_ms.items()}}
 

@@ -109,6 +109,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->slot_pos = w.take<int32_t>(P + 1);
   c->heavy_list = w.take<int32_t>(n);
   c->wl_gzwa = w.take<float>(n);
+  c->xyzp = w.take<float4>(n);
   c->gw = w.take<float>(3 * n);
   c->wl_fda = w.take<float>(n);
   c->den_grad = w.take<float>(3 * n);

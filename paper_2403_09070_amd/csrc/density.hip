@@ -212,11 +212,12 @@ __device__ __forceinline__ int pack_tiles(int tx0, int tx1, int ty0, int ty1) {
 }
 
 // Counts entries per (tile, block) and records each cell's packed tile range in cell_entry[0][i],
-// so that the scatter pass places a cell in exactly the tiles it was counted in.
+// so that the scatter pass places a cell in exactly the tiles it was counted in.  Every
+// instance's position is also written packed (x, y, z, 0) for the wirelength sweep.
 __global__ __launch_bounds__(256) void k_bucket_count(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                       const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                       const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
-                                                      int32_t* __restrict__ tiles_of) {
+                                                      int32_t* __restrict__ tiles_of, float4* __restrict__ xyzp) {
   extern __shared__ int hist[];
   for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) hist[k] = 0;
   __syncthreads();
@@ -224,6 +225,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(Geom g, TileGeom t, const 
   for (int c = threadIdx.x; c < t.cpb; c += blockDim.x) {
     const int i = base + c;
     if (i >= g.n) continue;
+    xyzp[i] = make_float4(xyz[i], xyz[g.n + i], xyz[2 * g.n + i], 0.f);
     if (cls[i] != kClsCell) { tiles_of[i] = -1; continue; }
     const Foot f = footprint(g, xyz, size, kind[i], i);
     int tx0, tx1, ty0, ty1;
@@ -369,13 +371,21 @@ __device__ __forceinline__ TileBox tile_box(const Geom& g, const TileGeom& t, in
 
 __device__ __forceinline__ int lds_index(const TileGeom& t, int bz, int ly, int lx) { return (bz * t.T + ly) * t.T + lx; }
 
-// The tile accumulates in 64-bit fixed point (2^-32 units): integer LDS atomics run at full rate
+// The tile accumulates in 64-bit fixed point (2^-31 units): integer LDS atomics run at full rate
 // where float LDS atomics serialise across lanes, and integer sums do not depend on the order in
-// which cells arrive, so the map is reproducible bit for bit.
-constexpr float kFix = 4294967296.f;          // 2^32
-constexpr double kUnfix = 1.0 / 4294967296.0;
+// which cells arrive, so the map is reproducible bit for bit.  One instance adds at most one
+// bin volume to a bin (a fraction <= 1), which converts through 32 bits; the fixed-instance map
+// (any value) takes the full 64-bit conversion.
+constexpr float kFix = 2147483648.f;          // 2^31
+constexpr double kUnfix = 1.0 / 2147483648.0;
 
 __device__ __forceinline__ unsigned long long to_fix(float v) { return __float2ull_rn(v * kFix); }
+__device__ __forceinline__ unsigned long long to_fix_unit(float v) {   // 0 <= v < 2
+  return (unsigned long long)__float2uint_rn(v * kFix);
+}
+
+// x bins of a bucketed entry whose overlap lengths are held in registers
+constexpr int kSpanX = 4;
 
 __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
@@ -407,7 +417,7 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
       for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
         const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
         const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz) * wgt;
-        S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix(v);   // one thread per bin within one instance
+        S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix_unit(v);   // one thread per bin within one instance
       }
       __syncthreads();
     }
@@ -419,13 +429,28 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     const float wgt = f.omega * inv_vol;
-    for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-      const float lz = len_z(g, f, bz) * wgt;
-      for (int by = by0; by <= by1; ++by) {
-        const float lyz = len_y(g, f, by) * lz;
-        for (int bx = bx0; bx <= bx1; ++bx) {
-          const float v = len_x(g, f, bx) * lyz;
-          if (v != 0.f) atomicAdd(&S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix(v));
+    const int nbx = bx1 - bx0 + 1;
+    if (nbx <= kSpanX) {
+      float lxs[kSpanX];
+#pragma unroll
+      for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
+      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+        const float lz = len_z(g, f, bz) * wgt;
+        for (int by = by0; by <= by1; ++by) {
+          const float lyz = len_y(g, f, by) * lz;
+          unsigned long long* row = &S64[lds_index(t, bz, by - tb.y0, bx0 - tb.x0)];
+#pragma unroll
+          for (int j = 0; j < kSpanX; ++j)
+            if (j < nbx) atomicAdd(row + j, to_fix_unit(lxs[j] * lyz));
+        }
+      }
+    } else {
+      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+        const float lz = len_z(g, f, bz) * wgt;
+        for (int by = by0; by <= by1; ++by) {
+          const float lyz = len_y(g, f, by) * lz;
+          for (int bx = bx0; bx <= bx1; ++bx)
+            atomicAdd(&S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix_unit(len_x(g, f, bx) * lyz));
         }
       }
     }
@@ -530,16 +555,38 @@ __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const 
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-      const float lz = len_z(g, f, bz);
-      for (int by = by0; by <= by1; ++by) {
-        const float lyz = len_y(g, f, by) * lz;
-        for (int bx = bx0; bx <= bx1; ++bx) {
-          const float v = len_x(g, f, bx) * lyz;
-          const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
-          sx += v * S[k];
-          sy += v * S[tsz + k];
-          sz += v * S[2 * tsz + k];
+    const int nbx = bx1 - bx0 + 1;
+    if (nbx <= kSpanX) {
+      float lxs[kSpanX];
+#pragma unroll
+      for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
+      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+        const float lz = len_z(g, f, bz);
+        for (int by = by0; by <= by1; ++by) {
+          const float lyz = len_y(g, f, by) * lz;
+          const int k0 = lds_index(t, bz, by - tb.y0, bx0 - tb.x0);
+#pragma unroll
+          for (int j = 0; j < kSpanX; ++j)
+            if (j < nbx) {
+              const float v = lxs[j] * lyz;
+              sx += v * S[k0 + j];
+              sy += v * S[tsz + k0 + j];
+              sz += v * S[2 * tsz + k0 + j];
+            }
+        }
+      }
+    } else {
+      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+        const float lz = len_z(g, f, bz);
+        for (int by = by0; by <= by1; ++by) {
+          const float lyz = len_y(g, f, by) * lz;
+          for (int bx = bx0; bx <= bx1; ++bx) {
+            const float v = len_x(g, f, bx) * lyz;
+            const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
+            sx += v * S[k];
+            sy += v * S[tsz + k];
+            sz += v * S[2 * tsz + k];
+          }
         }
       }
     }
@@ -878,7 +925,7 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
   }
   const size_t hist = sizeof(int) * t.ntiles;
   hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls, c->bk_counts,
-                     c->cell_entry);
+                     c->cell_entry, c->xyzp);
   P3D_LAUNCH(c, "k_bucket_count");
   hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_rows");

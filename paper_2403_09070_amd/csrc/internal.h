@@ -14,6 +14,7 @@ namespace p3d {
 
 constexpr int kWave = 64;
 constexpr int kMaxNz = 16;
+constexpr int kNumXcd = 8;              // accelerator dies; workgroups go to them round-robin
 constexpr int kWaBlock = 256;           // threads per wirelength block
 constexpr int kPinsPerLane = 4;         // net pins a wirelength lane keeps in registers
 constexpr int kNumClasses = 7;          // nets by lane group: 1, 2, 4, ..., 64 lanes
@@ -55,6 +56,7 @@ struct DctBases {
   uint16_t *Fx_h, *Fx_l, *Gx_h, *Gx_l, *Hx_h, *Hx_l;
   uint16_t *FyT_h, *FyT_l, *Gy_h, *Gy_l, *Hy_h, *Hy_l;
   float* zmat;              // small z matrices, see spectral.hip
+  int fold = 0;             // even x and y: folded contractions, spectra in even-first order
   float* inv_w2;            // [Nz][Ny][Nx] 1/|omega|^2 with the (0,0,0) entry 0
 };
 
@@ -117,6 +119,7 @@ struct place3d_ctx {
   p3d::ClassTab classes = {};
   int32_t n_wa_blocks = 0;
   // per-instance scratch
+  float4* xyzp = nullptr;              // [n] (x, y, z, 0) per instance, the net kernel's gather source
   float* wl_gzwa = nullptr;            // [n] alpha d p^(z)/dz per instance
   float* wl_fda = nullptr;             // [n] FDA z-gradient before normalisation
   float* gw = nullptr;                 // [3][n] wirelength gradient inside the GP step
@@ -148,6 +151,14 @@ int hip_fail(place3d_ctx* c, hipError_t e, const char* where);
 inline unsigned blocks_for(long long n, int threads) {
   long long b = (n + threads - 1) / threads;
   return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Workgroup b of a launch of nb runs on die b % kNumXcd.  This bijection hands die x the
+// contiguous work range [x q + min(x, r), ...) (q = nb / kNumXcd, r = nb % kNumXcd), so that
+// neighbouring work items, which read neighbouring data, share one die's L2.
+__host__ __device__ inline int xcd_swizzle(int b, int nb) {
+  const int q = nb / kNumXcd, r = nb % kNumXcd, x = b % kNumXcd, i = b / kNumXcd;
+  return x * q + (x < r ? x : r) + i;
 }
 
 // Profiler brackets (no-ops unless profiling is on).  prof_end records on the same stream.
@@ -188,7 +199,8 @@ int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, cons
 int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad,
                     int accumulate, hipStream_t s);
 
+// packed: c->xyzp already holds xyz (the bucket pass of the same positions wrote it)
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
-                    double* metrics, hipStream_t s);
+                    double* metrics, hipStream_t s, bool packed = false);
 
 }  // namespace p3d

@@ -40,33 +40,49 @@ typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ bases
 
-__global__ void k_basis_x(int n, double length, float* Fx, float* Gx, float* Hx) {
+// Spectral index order.  With an even axis length the DCT bases obey
+//   B[n-1-x][k] = (-1)^k B[x][k] (cosine),  (-1)^(k+1) B[x][k] (sine),
+// so every contraction splits into an even-frequency and an odd-frequency half of half the
+// size, on the data folded about the axis middle (x[i] +- x[n-1-i]).  Spectral arrays then hold
+// the even frequencies first: position p < n/2 is frequency 2p, position n/2 + p is 2p + 1.
+// Odd lengths keep the natural order and the dense contractions.
+__host__ __device__ inline int freq_of(int p, int n, int fold) {
+  if (!fold) return p;
+  const int h = n / 2;
+  return p < h ? 2 * p : 2 * (p - h) + 1;
+}
+
+__global__ void k_basis_x(int n, int fold, double length, float* Fx, float* Gx, float* Hx) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= (long long)n * n) return;
   const int r = (int)(t / n), c = (int)(t % n);
-  {  // Fx[x = r][j = c]
-    const double arg = M_PI * c * (r + 0.5) / n;
-    Fx[t] = (float)((c == 0 ? 1.0 : 2.0) / n * cos(arg));
+  {  // Fx[x = r][position c]
+    const int j = freq_of(c, n, fold);
+    const double arg = M_PI * j * (r + 0.5) / n;
+    Fx[t] = (float)((j == 0 ? 1.0 : 2.0) / n * cos(arg));
   }
-  {  // Gx[j = r][x = c], Hx[j = r][x = c]
-    const double arg = M_PI * r * (c + 0.5) / n;
+  {  // Gx[position r][x = c], Hx[position r][x = c]
+    const int j = freq_of(r, n, fold);
+    const double arg = M_PI * j * (c + 0.5) / n;
     Gx[t] = (float)cos(arg);
-    Hx[t] = (float)(M_PI * r / length * sin(arg));
+    Hx[t] = (float)(M_PI * j / length * sin(arg));
   }
 }
 
-__global__ void k_basis_y(int n, double length, float* FyT, float* Gy, float* Hy) {
+__global__ void k_basis_y(int n, int fold, double length, float* FyT, float* Gy, float* Hy) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= (long long)n * n) return;
   const int r = (int)(t / n), c = (int)(t % n);
-  {  // FyT[k = r][y = c]
-    const double arg = M_PI * r * (c + 0.5) / n;
-    FyT[t] = (float)((r == 0 ? 1.0 : 2.0) / n * cos(arg));
+  {  // FyT[position r][y = c]
+    const int k = freq_of(r, n, fold);
+    const double arg = M_PI * k * (c + 0.5) / n;
+    FyT[t] = (float)((k == 0 ? 1.0 : 2.0) / n * cos(arg));
   }
-  {  // Gy[y = r][k = c], Hy[y = r][k = c]
-    const double arg = M_PI * c * (r + 0.5) / n;
+  {  // Gy[y = r][position c], Hy[y = r][position c]
+    const int k = freq_of(c, n, fold);
+    const double arg = M_PI * k * (r + 0.5) / n;
     Gy[t] = (float)cos(arg);
-    Hy[t] = (float)(M_PI * c / length * sin(arg));
+    Hy[t] = (float)(M_PI * k / length * sin(arg));
   }
 }
 
@@ -87,12 +103,12 @@ __global__ void k_basis_z(int n, double length, float* zmat) {
   zmat[2 * kMaxNz * kMaxNz + t] = hz;
 }
 
-__global__ void k_inv_w2(int nx, int ny, int nz, double dx, double dy, double dz, float* out) {
+__global__ void k_inv_w2(int nx, int ny, int nz, int fold, double dx, double dy, double dz, float* out) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long total = (long long)nx * ny * nz;
   if (t >= total) return;
-  const int j = (int)(t % nx);
-  const int k = (int)((t / nx) % ny);
+  const int j = freq_of((int)(t % nx), nx, fold);
+  const int k = freq_of((int)((t / nx) % ny), ny, fold);
   const int l = (int)(t / ((long long)nx * ny));
   const double wx = M_PI * j / dx, wy = M_PI * k / dy, wz = M_PI * l / dz;
   const double w2 = wx * wx + wy * wy + wz * wz;
@@ -101,43 +117,59 @@ __global__ void k_inv_w2(int nx, int ny, int nz, double dx, double dy, double dz
 
 // ------------------------------------------------------------------ GEMM
 
+constexpr int kMaxProb = 8;
+
+// One contraction C = A . B of a launch: A is M x K, B is K x N, C is M x N, with the leading
+// dimensions of the launch.  One operand is a map (the data operand); with fold != 0 it is
+// folded along k about the middle of an axis of length fold_n: X(k) + fold * X(fold_n - 1 - k).
 struct GemmProb {
   const float* A;
   const float* B;
   float* C;
   long long sA, sB, sC;   // batch strides in elements (0 = shared operand)
+  float fold;
 };
 
 struct GemmArgs {
   int M, N, K, nbatch;    // every problem of a launch has the same shape and batch count
-  GemmProb p[4];
+  int lda, ldb, ldc;
+  int fold_n;
+  int fold_a;             // 1: A is the data operand, 0: B
+  GemmProb p[kMaxProb];
 };
 
 constexpr int BM = 128, BN = 128;
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+__device__ __forceinline__ bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Output tile of a workgroup.  The launch is one-dimensional over (n tile, m tile, problem x
+// batch), n fastest, and the XCD-aware order gives each die a contiguous run of tiles: the n
+// tiles of one m block (which share its rows of the data operand) then stay on one die's L2.
+struct TileIdx { int n, m, z; };
+__device__ __forceinline__ TileIdx tile_of(int M, int N) {
+  const int ntn = (N + BN - 1) / BN, ntm = (M + BM - 1) / BM;
+  const int w = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+  return {w % ntn, (w / ntn) % ntm, w / (ntn * ntm)};
 }
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // C[M][N] = A[M][K] . B[K][N] on float32 MFMA (32x32x2): 4 waves, each a 64 x 64 sub-tile.
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
   constexpr int BK = 16, PAD = 4;
   __shared__ float As[2][BK][BM + PAD];
   __shared__ float Bs[2][BK][BN + PAD];
-  const int M = args.M, N = args.N, K = args.K;
-  const int prob = blockIdx.z / args.nbatch, bat = blockIdx.z % args.nbatch;
+  const int M = args.M, N = args.N, K = args.K, lda = args.lda, ldb = args.ldb, ldc = args.ldc, fn = args.fold_n;
+  const TileIdx ti = tile_of(M, N);
+  const int prob = ti.z / args.nbatch, bat = ti.z % args.nbatch;
   const GemmProb P = args.p[prob];
   const float* __restrict__ A = P.A + bat * P.sA;
   const float* __restrict__ B = P.B + bat * P.sB;
   float* __restrict__ C = P.C + bat * P.sC;
+  const float fa = args.fold_a ? P.fold : 0.f, fb = args.fold_a ? 0.f : P.fold;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const bool vec = ((K & 3) == 0) && ((N & 3) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
+  const int m0 = ti.m * BM, n0 = ti.n * BN;
+  const bool vec = ((K & 3) == 0) && ((N & 3) == 0) && ((lda & 3) == 0) && ((ldb & 3) == 0) && ((fn & 3) == 0) &&
+                   al16(A) && al16(B);
 
   float ra[8], rb[8];
   auto load = [&](int k0) {
@@ -147,20 +179,42 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
       const int ar = f >> 2, ak = (f & 3) * 4;          // A: 128 rows x 4 float4
       const int gm = m0 + ar, gk = k0 + ak;
       if (vec && gm < M && gk + 3 < K) {
-        const float4 v = *reinterpret_cast<const float4*>(A + (size_t)gm * K + gk);
+        float4 v = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + gk);
+        if (fa != 0.f) {
+          const float4 w = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + fn - 4 - gk);
+          v.x += fa * w.w; v.y += fa * w.z; v.z += fa * w.y; v.w += fa * w.x;
+        }
         ra[4 * q] = v.x; ra[4 * q + 1] = v.y; ra[4 * q + 2] = v.z; ra[4 * q + 3] = v.w;
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ra[4 * q + e] = (gm < M && gk + e < K) ? A[(size_t)gm * K + gk + e] : 0.f;
+        for (int e = 0; e < 4; ++e) {
+          float v = 0.f;
+          if (gm < M && gk + e < K) {
+            v = A[(size_t)gm * lda + gk + e];
+            if (fa != 0.f) v += fa * A[(size_t)gm * lda + fn - 1 - gk - e];
+          }
+          ra[4 * q + e] = v;
+        }
       }
       const int br = f >> 5, bn = (f & 31) * 4;         // B: 16 rows x 32 float4
       const int gkb = k0 + br, gn = n0 + bn;
       if (vec && gkb < K && gn + 3 < N) {
-        const float4 v = *reinterpret_cast<const float4*>(B + (size_t)gkb * N + gn);
+        float4 v = *reinterpret_cast<const float4*>(B + (size_t)gkb * ldb + gn);
+        if (fb != 0.f) {
+          const float4 w = *reinterpret_cast<const float4*>(B + (size_t)(fn - 1 - gkb) * ldb + gn);
+          v.x += fb * w.x; v.y += fb * w.y; v.z += fb * w.z; v.w += fb * w.w;
+        }
         rb[4 * q] = v.x; rb[4 * q + 1] = v.y; rb[4 * q + 2] = v.z; rb[4 * q + 3] = v.w;
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rb[4 * q + e] = (gkb < K && gn + e < N) ? B[(size_t)gkb * N + gn + e] : 0.f;
+        for (int e = 0; e < 4; ++e) {
+          float v = 0.f;
+          if (gkb < K && gn + e < N) {
+            v = B[(size_t)gkb * ldb + gn + e];
+            if (fb != 0.f) v += fb * B[(size_t)(fn - 1 - gkb) * ldb + gn + e];
+          }
+          rb[4 * q + e] = v;
+        }
       }
     }
   };
@@ -215,28 +269,38 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row < M && col < N) C[(size_t)row * N + col] = acc[a][b][r];
+        if (row < M && col < N) C[(size_t)row * ldc + col] = acc[a][b][r];
       }
     }
 }
 
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
 // Same contraction with each float32 operand split into bfloat16 hi + lo (round to nearest
 // even) and three products hi.hi + hi.lo + lo.hi accumulated in float32 (32x32x16 bf16 MFMA).
 // One operand is a DCT basis, split once at context creation and stored with k contiguous
-// ([rows][K] for a left basis, transposed [N][K] for a right basis); the other is a map,
-// loaded as float32 and split on the way into LDS.  LDS holds both operands k-contiguous,
-// double-buffered, one barrier per 32-wide k step.
+// ([rows][ldb] for a left basis, transposed to [N][ldb] for a right basis); the other is a map,
+// loaded as float32 (folded if asked) and split on the way into LDS.  LDS holds both operands
+// k-contiguous, double-buffered, one barrier per 32-wide k step.
 struct GemmSplitProb {
   const float* data;                 // map operand, float32 row-major
   const uint16_t* bhi;               // basis hi, k contiguous
   const uint16_t* blo;               // basis lo
   float* C;
   long long s_data, s_C;             // batch strides (elements)
+  float fold;
 };
 
 struct GemmSplitArgs {
   int M, N, K, nbatch;
-  GemmSplitProb p[4];
+  int ldd, ldb, ldc;                 // leading dimensions: data, basis (split), output
+  int fold_n;
+  GemmSplitProb p[kMaxProb];
 };
 
 template <bool LEFT_BASIS>
@@ -244,17 +308,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
   constexpr int BK = 32, LDK = BK + 8;
   __shared__ unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
   __shared__ unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
-  const int M = args.M, N = args.N, K = args.K;
-  const int prob = blockIdx.z / args.nbatch, bat = blockIdx.z % args.nbatch;
+  const int M = args.M, N = args.N, K = args.K, ldd = args.ldd, ldb = args.ldb, ldc = args.ldc, fn = args.fold_n;
+  const TileIdx ti = tile_of(M, N);
+  const int prob = ti.z / args.nbatch, bat = ti.z % args.nbatch;
   const GemmSplitProb P = args.p[prob];
   const float* __restrict__ D = P.data + bat * P.s_data;
   const uint16_t* __restrict__ Bh_g = P.bhi;
   const uint16_t* __restrict__ Bl_g = P.blo;
   float* __restrict__ C = P.C + bat * P.s_C;
+  const float fold = P.fold;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0) && (N % 4 == 0) && (K % 8 == 0);
+  const int m0 = ti.m * BM, n0 = ti.n * BN;
+  const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0) && (ldd % 8 == 0) && (ldb % 8 == 0) &&
+                    (fn % 8 == 0) && al16(D) && al16(Bh_g) && al16(Bl_g);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -268,8 +335,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
   float rd[16];
   u16x8 rbh[2], rbl[2];
 
-  // basis tile: rows [r0, r0 + 128) of a k-contiguous [rows][K] array; thread takes row f >> 2,
-  // k group (f & 3) * 8 for f = tid, tid + 256
+  // basis tile: rows [r0, r0 + 128) of a k-contiguous array; thread takes row f >> 2, k group
+  // (f & 3) * 8 for f = tid, tid + 256
   auto load_basis = [&](int k0, int r0, int rows) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -277,14 +344,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
       const int r = f >> 2, kg = (f & 3) * 8;
       const int gr = r0 + r, gk = k0 + kg;
       if (full) {
-        rbh[q] = *reinterpret_cast<const u16x8*>(Bh_g + (size_t)gr * K + gk);
-        rbl[q] = *reinterpret_cast<const u16x8*>(Bl_g + (size_t)gr * K + gk);
+        rbh[q] = *reinterpret_cast<const u16x8*>(Bh_g + (size_t)gr * ldb + gk);
+        rbl[q] = *reinterpret_cast<const u16x8*>(Bl_g + (size_t)gr * ldb + gk);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const bool ok = gr < rows && gk + e < K;
-          rbh[q][e] = ok ? Bh_g[(size_t)gr * K + gk + e] : (unsigned short)0;
-          rbl[q][e] = ok ? Bl_g[(size_t)gr * K + gk + e] : (unsigned short)0;
+          rbh[q][e] = ok ? Bh_g[(size_t)gr * ldb + gk + e] : (unsigned short)0;
+          rbl[q][e] = ok ? Bl_g[(size_t)gr * ldb + gk + e] : (unsigned short)0;
         }
       }
     }
@@ -312,7 +379,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     *reinterpret_cast<u32x4*>(h) = hh;
     *reinterpret_cast<u32x4*>(l) = ll;
   };
-  // left data operand (map as A [M][K]): thread takes row f >> 2, k group (f & 3) * 8
+  // left data operand (map as A [M][K]): thread takes row f >> 2, k group (f & 3) * 8; a fold
+  // adds the mirrored group, read as two float4 and reversed
   auto load_left_data = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -320,13 +388,29 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
       const int r = f >> 2, kg = (f & 3) * 8;
       const int gm = m0 + r, gk = k0 + kg;
       if (full) {
-        const float4 v0 = *reinterpret_cast<const float4*>(D + (size_t)gm * K + gk);
-        const float4 v1 = *reinterpret_cast<const float4*>(D + (size_t)gm * K + gk + 4);
+        const float* row = D + (size_t)gm * ldd;
+        const float4 v0 = *reinterpret_cast<const float4*>(row + gk);
+        const float4 v1 = *reinterpret_cast<const float4*>(row + gk + 4);
         rd[8 * q + 0] = v0.x; rd[8 * q + 1] = v0.y; rd[8 * q + 2] = v0.z; rd[8 * q + 3] = v0.w;
         rd[8 * q + 4] = v1.x; rd[8 * q + 5] = v1.y; rd[8 * q + 6] = v1.z; rd[8 * q + 7] = v1.w;
+        if (fold != 0.f) {
+          const float4 w0 = *reinterpret_cast<const float4*>(row + fn - 8 - gk);   // mirror of gk+7..gk+4
+          const float4 w1 = *reinterpret_cast<const float4*>(row + fn - 4 - gk);   // mirror of gk+3..gk
+          rd[8 * q + 0] += fold * w1.w; rd[8 * q + 1] += fold * w1.z;
+          rd[8 * q + 2] += fold * w1.y; rd[8 * q + 3] += fold * w1.x;
+          rd[8 * q + 4] += fold * w0.w; rd[8 * q + 5] += fold * w0.z;
+          rd[8 * q + 6] += fold * w0.y; rd[8 * q + 7] += fold * w0.x;
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rd[8 * q + e] = (gm < M && gk + e < K) ? D[(size_t)gm * K + gk + e] : 0.f;
+        for (int e = 0; e < 8; ++e) {
+          float v = 0.f;
+          if (gm < M && gk + e < K) {
+            v = D[(size_t)gm * ldd + gk + e];
+            if (fold != 0.f) v += fold * D[(size_t)gm * ldd + fn - 1 - gk - e];
+          }
+          rd[8 * q + e] = v;
+        }
       }
     }
   };
@@ -339,7 +423,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     }
   };
   // right data operand (map as B [K][N]): thread takes columns 2 (tid & 63) + {0, 1} and k group
-  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers
+  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers;
+  // a fold adds the mirrored rows
   auto load_right_data = [&](int k0) {
     const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
     const int gn = n0 + cn;
@@ -347,12 +432,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     for (int e = 0; e < 8; ++e) {
       const int gk = k0 + kg + e;
       if (full) {
-        const float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * N + gn);
+        float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * ldd + gn);
+        if (fold != 0.f) {
+          const float2 w = *reinterpret_cast<const float2*>(D + (size_t)(fn - 1 - gk) * ldd + gn);
+          v.x += fold * w.x;
+          v.y += fold * w.y;
+        }
         rd[e] = v.x;
         rd[8 + e] = v.y;
       } else {
-        rd[e] = (gk < K && gn < N) ? D[(size_t)gk * N + gn] : 0.f;
-        rd[8 + e] = (gk < K && gn + 1 < N) ? D[(size_t)gk * N + gn + 1] : 0.f;
+        float v0 = 0.f, v1 = 0.f;
+        if (gk < K) {
+          if (gn < N) {
+            v0 = D[(size_t)gk * ldd + gn];
+            if (fold != 0.f) v0 += fold * D[(size_t)(fn - 1 - gk) * ldd + gn];
+          }
+          if (gn + 1 < N) {
+            v1 = D[(size_t)gk * ldd + gn + 1];
+            if (fold != 0.f) v1 += fold * D[(size_t)(fn - 1 - gk) * ldd + gn + 1];
+          }
+        }
+        rd[e] = v0;
+        rd[8 + e] = v1;
       }
     }
   };
@@ -410,7 +511,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row < M && col < N) C[(size_t)row * N + col] = acc[a][b][r];
+        if (row < M && col < N) C[(size_t)row * ldc + col] = acc[a][b][r];
       }
     }
 }
@@ -464,6 +565,74 @@ __global__ void k_zmix_inv(int plane, int nz, const float* __restrict__ zmat, co
   }
 }
 
+// Folded y axis: rows [0, h) of vg / vh hold the even-frequency half E and rows [h, ny) the
+// odd half O of the inverse-y contraction; row y is E + O and row ny-1-y is E - O for the
+// cosine basis, O - E for the sine basis.  One thread per (y < h, x) writes both rows.
+__global__ void k_zmix_inv_fold(int nx, int ny, int nz, const float* __restrict__ zmat, const float* __restrict__ vg,
+                                const float* __restrict__ vh, float* __restrict__ pc, float* __restrict__ ps,
+                                float* __restrict__ qc) {
+  const int h = ny / 2;
+  const long long plane = (long long)nx * ny;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)h * nx) return;
+  const int y = (int)(t / nx), x = (int)(t % nx);
+  const long long lo = (long long)y * nx + x, hi = (long long)(h + y) * nx + x, mir = (long long)(ny - 1 - y) * nx + x;
+  const float* Gz = zmat + kMaxNz * kMaxNz;
+  const float* Hz = zmat + 2 * kMaxNz * kMaxNz;
+  float g0[kMaxNz], g1[kMaxNz], h0[kMaxNz], h1[kMaxNz];
+  if (vg)
+    for (int l = 0; l < nz; ++l) {
+      const float e = vg[l * plane + lo], o = vg[l * plane + hi];
+      g0[l] = e + o;
+      g1[l] = e - o;
+    }
+  if (vh)
+    for (int l = 0; l < nz; ++l) {
+      const float e = vh[l * plane + lo], o = vh[l * plane + hi];
+      h0[l] = e + o;
+      h1[l] = o - e;
+    }
+  for (int z = 0; z < nz; ++z) {
+    if (pc) {
+      float a = 0.f, b = 0.f;
+      for (int l = 0; l < nz; ++l) { a += Gz[l * kMaxNz + z] * g0[l]; b += Gz[l * kMaxNz + z] * g1[l]; }
+      pc[z * plane + lo] = a; pc[z * plane + mir] = b;
+    }
+    if (ps) {
+      float a = 0.f, b = 0.f;
+      for (int l = 0; l < nz; ++l) { a += Hz[l * kMaxNz + z] * g0[l]; b += Hz[l * kMaxNz + z] * g1[l]; }
+      ps[z * plane + lo] = a; ps[z * plane + mir] = b;
+    }
+    if (qc) {
+      float a = 0.f, b = 0.f;
+      for (int l = 0; l < nz; ++l) { a += Gz[l * kMaxNz + z] * h0[l]; b += Gz[l * kMaxNz + z] * h1[l]; }
+      qc[z * plane + lo] = a; qc[z * plane + mir] = b;
+    }
+  }
+}
+
+// Folded x axis, in place: columns [0, h) of each row hold E, columns [h, nx) hold O; column x
+// becomes E + O and column nx-1-x becomes sign (E - O).  A thread takes the column pair
+// (x, h-1-x), whose four positions {x, h-1-x, h+x, nx-1-x} it alone reads and writes.
+struct Unfold { float* out[4]; float sign[4]; };
+
+__global__ void k_unfold_x(int rows, int nx, Unfold u) {
+  const int h = nx / 2, hp = (h + 1) / 2;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)rows * hp) return;
+  const int r = (int)(t / hp), x = (int)(t % hp), x2 = h - 1 - x;
+  float* row = u.out[blockIdx.y] + (size_t)r * nx;
+  const float sg = u.sign[blockIdx.y];
+  const float e1 = row[x], o1 = row[h + x];
+  const float e2 = row[x2], o2 = row[h + x2];
+  row[x] = e1 + o1;
+  row[nx - 1 - x] = sg * (e1 - o1);
+  if (x2 != x) {
+    row[x2] = e2 + o2;
+    row[nx - 1 - x2] = sg * (e2 - o2);
+  }
+}
+
 // partials of 1/2 vol(b) sum rho phi, one per block
 __global__ void k_energy(long long total, const float* __restrict__ rho, const float* __restrict__ phi, float half_vol,
                          double* __restrict__ part) {
@@ -482,31 +651,48 @@ __global__ void k_energy(long long total, const float* __restrict__ rho, const f
   }
 }
 
-// A basis operand of a contraction: its float32 matrix and its k-contiguous bfloat16 split
+// A basis operand of a contraction, possibly a sub-block of an n x n basis: its float32 view
+// and its k-contiguous bfloat16 split (leading dimension n for both)
 struct Basis { const float* f32; const uint16_t* hi; const uint16_t* lo; };
 
+// sub-block at row r, column c of the float32 basis (a right basis, K x N, is stored split
+// transposed, so the split offset swaps the roles of r and c)
+Basis sub(const Basis& b, int n, bool right, int r, int c) {
+  const size_t of = (size_t)r * n + c, os = right ? (size_t)c * n + r : of;
+  return {b.f32 + of, b.hi + os, b.lo + os};
+}
+
+struct GemmJob { const float* data; Basis basis; float* out; float fold; };
+
 // batched C = A . B where exactly one of A (left_basis) or B is a DCT basis shared by the batch
-int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, bool left_basis, const float* const* data,
-         long long s_data, const Basis* basis, float* const* out, long long s_out, int nprob, hipStream_t s) {
-  if (nprob <= 0) return PLACE3D_OK;
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nbatch * nprob);
+int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, bool left_basis, int ld_data, int ld_basis, int ldc,
+         int fold_n, long long s_data, long long s_out, const GemmJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return PLACE3D_OK;
+  if (njobs > kMaxProb) return set_err(c, PLACE3D_ERR_ARG, "too many contractions in one launch");
+  const long long tiles = (long long)((N + BN - 1) / BN) * ((M + BM - 1) / BM) * nbatch * njobs;
+  if (tiles > 0x7fffffffLL) return set_err(c, PLACE3D_ERR_SIZE, "contraction grid too large");
+  const dim3 grid((unsigned)tiles);
   ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
   if (c->prob.precision == PLACE3D_BF16X3) {
     GemmSplitArgs a;
     a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
-    for (int i = 0; i < 4; ++i) {
-      const int j = i < nprob ? i : 0;
-      a.p[i] = {data[j], basis[j].hi, basis[j].lo, out[j], s_data, s_out};
+    a.ldd = ld_data; a.ldb = ld_basis; a.ldc = ldc; a.fold_n = fold_n;
+    for (int i = 0; i < kMaxProb; ++i) {
+      const GemmJob& jb = jobs[i < njobs ? i : 0];
+      a.p[i] = {jb.data, jb.basis.hi, jb.basis.lo, jb.out, s_data, s_out, jb.fold};
     }
     if (left_basis) hipLaunchKernelGGL(k_gemm_bf16x3<true>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_gemm_bf16x3<false>, grid, dim3(256), 0, s, a);
   } else {
     GemmArgs a;
     a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
-    for (int i = 0; i < 4; ++i) {
-      const int j = i < nprob ? i : 0;
-      a.p[i] = left_basis ? GemmProb{basis[j].f32, data[j], out[j], 0, s_data, s_out}
-                          : GemmProb{data[j], basis[j].f32, out[j], s_data, 0, s_out};
+    a.lda = left_basis ? ld_basis : ld_data;
+    a.ldb = left_basis ? ld_data : ld_basis;
+    a.ldc = ldc; a.fold_n = fold_n; a.fold_a = left_basis ? 0 : 1;
+    for (int i = 0; i < kMaxProb; ++i) {
+      const GemmJob& jb = jobs[i < njobs ? i : 0];
+      a.p[i] = left_basis ? GemmProb{jb.basis.f32, jb.data, jb.out, 0, s_data, s_out, jb.fold}
+                          : GemmProb{jb.data, jb.basis.f32, jb.out, s_data, 0, s_out, jb.fold};
     }
     hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, a);
   }
@@ -520,11 +706,12 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s) {
   const Geom& g = c->g;
   const place3d_problem& p = c->prob;
   const double wb = p.die_x / p.nx, hb = p.die_y / p.ny, dz = p.nz * 0.5 * (wb + hb);
-  hipLaunchKernelGGL(k_basis_x, dim3(blocks_for((long long)g.nx * g.nx, 256)), dim3(256), 0, s, g.nx, p.die_x,
-                     c->dct.Fx, c->dct.Gx, c->dct.Hx);
+  c->dct.fold = (g.nx % 2 == 0 && g.ny % 2 == 0) ? 1 : 0;
+  hipLaunchKernelGGL(k_basis_x, dim3(blocks_for((long long)g.nx * g.nx, 256)), dim3(256), 0, s, g.nx, c->dct.fold,
+                     p.die_x, c->dct.Fx, c->dct.Gx, c->dct.Hx);
   P3D_LAUNCH(c, "k_basis_x");
-  hipLaunchKernelGGL(k_basis_y, dim3(blocks_for((long long)g.ny * g.ny, 256)), dim3(256), 0, s, g.ny, p.die_y,
-                     c->dct.FyT, c->dct.Gy, c->dct.Hy);
+  hipLaunchKernelGGL(k_basis_y, dim3(blocks_for((long long)g.ny * g.ny, 256)), dim3(256), 0, s, g.ny, c->dct.fold,
+                     p.die_y, c->dct.FyT, c->dct.Gy, c->dct.Hy);
   P3D_LAUNCH(c, "k_basis_y");
   {
     const DctBases& d = c->dct;
@@ -540,8 +727,8 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_basis_z, dim3(1), dim3(kMaxNz * kMaxNz), 0, s, g.nz, dz, c->dct.zmat);
   P3D_LAUNCH(c, "k_basis_z");
   const long long map = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL(k_inv_w2, dim3(blocks_for(map, 256)), dim3(256), 0, s, g.nx, g.ny, g.nz, p.die_x, p.die_y, dz,
-                     c->dct.inv_w2);
+  hipLaunchKernelGGL(k_inv_w2, dim3(blocks_for(map, 256)), dim3(256), 0, s, g.nx, g.ny, g.nz, c->dct.fold, p.die_x,
+                     p.die_y, dz, c->dct.inv_w2);
   P3D_LAUNCH(c, "k_inv_w2");
   return PLACE3D_OK;
 }
@@ -555,56 +742,117 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
   int rc;
   const Basis Fx{d.Fx, d.Fx_h, d.Fx_l}, Gx{d.Gx, d.Gx_h, d.Gx_l}, Hx{d.Hx, d.Hx_h, d.Hx_l};
   const Basis FyT{d.FyT, d.FyT_h, d.FyT_l}, Gy{d.Gy, d.Gy_h, d.Gy_l}, Hy{d.Hy, d.Hy_h, d.Hy_l};
-  // forward x: T = rho . Fx;  forward y: A[z] = FyT . T[z]
-  {
-    const float* in[1] = {rho};
-    float* out[1] = {c->map_t};
-    if ((rc = gemm(c, nz * ny, nx, nx, 1, false, in, 0, &Fx, out, 0, 1, s))) return rc;
-  }
-  {
-    const float* in[1] = {c->map_t};
-    float* out[1] = {c->map_a};
-    if ((rc = gemm(c, ny, nx, ny, nz, true, in, plane, &FyT, out, plane, 1, s))) return rc;
-  }
-  {
-    ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
-    hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat, d.inv_w2,
-                       c->map_a);
-    P3D_LAUNCH(c, "k_zmix_fwd");
-  }
-  // inverse y: Vg = Gy . b[l], Vh = Hy . b[l]
   const bool need_g = phi || ex || ez, need_h = ey != nullptr;
-  {
-    const float* in[2] = {c->map_a, c->map_a};
-    Basis bs[2];
-    float* out[2];
-    int np = 0;
-    if (need_g) { bs[np] = Gy; out[np++] = c->map_vg; }
-    if (need_h) { bs[np] = Hy; out[np++] = c->map_vh; }
-    if ((rc = gemm(c, ny, nx, ny, nz, true, in, plane, bs, out, plane, np, s))) return rc;
-  }
   float* pc = (phi || ex) ? c->map_pc : nullptr;
   float* ps = ez ? c->map_ps : nullptr;
   float* qc = ey ? c->map_qc : nullptr;
-  if (pc || ps || qc) {
+  // the x-inverse outputs: Ex = Pc . Hx, Ey = Qc . Gx, Ez = Ps . Gx, phi = Pc . Gx
+  struct XOut { const float* in; Basis b; float* out; float sign; };
+  XOut xo[4];
+  int nxo = 0;
+  if (ex) xo[nxo++] = {c->map_pc, Hx, ex, -1.f};
+  if (ey) xo[nxo++] = {c->map_qc, Gx, ey, 1.f};
+  if (ez) xo[nxo++] = {c->map_ps, Gx, ez, 1.f};
+  if (phi) xo[nxo++] = {c->map_pc, Gx, phi, 1.f};
+
+  if (d.fold) {
+    const int hx = nx / 2, hy = ny / 2;
+    // forward x: T[:, even half] = S . Fx_even, T[:, odd half] = D . Fx_odd with S, D the rows
+    // of rho folded about the x middle (+, -)
+    {
+      const GemmJob j[2] = {{rho, sub(Fx, nx, true, 0, 0), c->map_t, 1.f},
+                            {rho, sub(Fx, nx, true, 0, hx), c->map_t + hx, -1.f}};
+      if ((rc = gemm(c, nz * ny, hx, hx, 1, false, nx, nx, nx, nx, 0, 0, j, 2, s))) return rc;
+    }
+    // forward y, per layer: A[even half] = FyT_even . (T folded +), A[odd half] = FyT_odd . (T folded -)
+    {
+      const GemmJob j[2] = {{c->map_t, sub(FyT, ny, false, 0, 0), c->map_a, 1.f},
+                            {c->map_t, sub(FyT, ny, false, hy, 0), c->map_a + (size_t)hy * nx, -1.f}};
+      if ((rc = gemm(c, hy, nx, hy, nz, true, nx, ny, nx, ny, plane, plane, j, 2, s))) return rc;
+    }
     {
       ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat,
+                         d.inv_w2, c->map_a);
+      P3D_LAUNCH(c, "k_zmix_fwd");
+    }
+    // inverse y, per layer: E = Gy[:, even half] . b[even half], O = Gy[:, odd half] . b[odd half]
+    // into rows [0, hy) and [hy, ny) of vg (and the same with Hy into vh)
+    {
+      GemmJob j[4];
+      int nj = 0;
+      if (need_g) {
+        j[nj++] = {c->map_a, sub(Gy, ny, false, 0, 0), c->map_vg, 0.f};
+        j[nj++] = {c->map_a + (size_t)hy * nx, sub(Gy, ny, false, 0, hy), c->map_vg + (size_t)hy * nx, 0.f};
+      }
+      if (need_h) {
+        j[nj++] = {c->map_a, sub(Hy, ny, false, 0, 0), c->map_vh, 0.f};
+        j[nj++] = {c->map_a + (size_t)hy * nx, sub(Hy, ny, false, 0, hy), c->map_vh + (size_t)hy * nx, 0.f};
+      }
+      if ((rc = gemm(c, hy, nx, hy, nz, true, nx, ny, nx, 0, plane, plane, j, nj, s))) return rc;
+    }
+    if (pc || ps || qc) {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      hipLaunchKernelGGL(k_zmix_inv_fold, dim3(blocks_for((long long)hy * nx, 256)), dim3(256), 0, s, nx, ny, nz,
+                         d.zmat, need_g ? c->map_vg : nullptr, need_h ? c->map_vh : nullptr, pc, ps, qc);
+      P3D_LAUNCH(c, "k_zmix_inv_fold");
+    }
+    // inverse x: E = P[:, even half] . Gx[even half] into columns [0, hx), O likewise into
+    // [hx, nx); then each row is unfolded in place
+    {
+      GemmJob j[8];
+      int nj = 0;
+      for (int q = 0; q < nxo; ++q) {
+        j[nj++] = {xo[q].in, sub(xo[q].b, nx, true, 0, 0), xo[q].out, 0.f};
+        j[nj++] = {xo[q].in + hx, sub(xo[q].b, nx, true, hx, 0), xo[q].out + hx, 0.f};
+      }
+      if ((rc = gemm(c, nz * ny, hx, hx, 1, false, nx, nx, nx, 0, 0, 0, j, nj, s))) return rc;
+    }
+    if (nxo > 0) {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      Unfold u;
+      for (int q = 0; q < 4; ++q) {
+        u.out[q] = xo[q < nxo ? q : 0].out;
+        u.sign[q] = xo[q < nxo ? q : 0].sign;
+      }
+      const long long work = (long long)nz * ny * ((hx + 1) / 2);
+      hipLaunchKernelGGL(k_unfold_x, dim3(blocks_for(work, 256), nxo), dim3(256), 0, s, nz * ny, nx, u);
+      P3D_LAUNCH(c, "k_unfold_x");
+    }
+  } else {
+    // dense contractions in natural frequency order
+    {
+      const GemmJob j[1] = {{rho, Fx, c->map_t, 0.f}};
+      if ((rc = gemm(c, nz * ny, nx, nx, 1, false, nx, nx, nx, 0, 0, 0, j, 1, s))) return rc;
+    }
+    {
+      const GemmJob j[1] = {{c->map_t, FyT, c->map_a, 0.f}};
+      if ((rc = gemm(c, ny, nx, ny, nz, true, nx, ny, nx, 0, plane, plane, j, 1, s))) return rc;
+    }
+    {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
+      hipLaunchKernelGGL(k_zmix_fwd, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat,
+                         d.inv_w2, c->map_a);
+      P3D_LAUNCH(c, "k_zmix_fwd");
+    }
+    {
+      GemmJob j[2];
+      int nj = 0;
+      if (need_g) j[nj++] = {c->map_a, Gy, c->map_vg, 0.f};
+      if (need_h) j[nj++] = {c->map_a, Hy, c->map_vh, 0.f};
+      if ((rc = gemm(c, ny, nx, ny, nz, true, nx, ny, nx, 0, plane, plane, j, nj, s))) return rc;
+    }
+    if (pc || ps || qc) {
+      ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
       hipLaunchKernelGGL(k_zmix_inv, dim3(blocks_for(plane, 256)), dim3(256), 0, s, (int)plane, nz, d.zmat,
-                       need_g ? c->map_vg : nullptr, need_h ? c->map_vh : nullptr, pc, ps, qc);
+                         need_g ? c->map_vg : nullptr, need_h ? c->map_vh : nullptr, pc, ps, qc);
       P3D_LAUNCH(c, "k_zmix_inv");
     }
-  }
-  // inverse x: Ex = Pc . Hx, Ey = Qc . Gx, Ez = Ps . Gx, phi = Pc . Gx
-  {
-    const float* in[4];
-    Basis bs[4];
-    float* out[4];
-    int np = 0;
-    if (ex) { in[np] = c->map_pc; bs[np] = Hx; out[np++] = ex; }
-    if (ey) { in[np] = c->map_qc; bs[np] = Gx; out[np++] = ey; }
-    if (ez) { in[np] = c->map_ps; bs[np] = Gx; out[np++] = ez; }
-    if (phi) { in[np] = c->map_pc; bs[np] = Gx; out[np++] = phi; }
-    if ((rc = gemm(c, nz * ny, nx, nx, 1, false, in, 0, bs, out, 0, np, s))) return rc;
+    {
+      GemmJob j[4];
+      for (int q = 0; q < nxo; ++q) j[q] = {xo[q].in, xo[q].b, xo[q].out, 0.f};
+      if ((rc = gemm(c, nz * ny, nx, nx, 1, false, nx, nx, nx, 0, 0, 0, j, nxo, s))) return rc;
+    }
   }
   if (energy) {
     const long long map = plane * nz;

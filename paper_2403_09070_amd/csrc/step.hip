@@ -222,8 +222,8 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
 int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s) {
   int rc;
   if ((rc = launch_zero_f64(c, red, R_COUNT, s))) return rc;
-  if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, s))) return rc;
-  if ((rc = bucket_cells(c, xyz, s))) return rc;
+  if ((rc = bucket_cells(c, xyz, s))) return rc;     // also packs xyz for the wirelength sweep
+  if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, s, true))) return rc;
   if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;

@@ -40,13 +40,13 @@ struct PinRel {        // one pin, relative to the net anchor
   bool top;
 };
 
-__device__ __forceinline__ PinRel load_pin(const float* __restrict__ xyz, int n, const int32_t* __restrict__ pin_node,
+__device__ __forceinline__ PinRel load_pin(const float4* __restrict__ xyzp, const int32_t* __restrict__ pin_node,
                                            const float4* __restrict__ off, int slot, float half_dz, float xa, float ya) {
-  const int node = pin_node[slot];
+  const float4 q = xyzp[pin_node[slot]];
   const float4 o = off[slot];
-  const float dx = xyz[node] - xa, dy = xyz[n + node] - ya;
+  const float dx = q.x - xa, dy = q.y - ya;
   PinRel p;
-  p.z = xyz[2 * n + node];
+  p.z = q.z;
   p.top = p.z > half_dz;
   p.ux = dx + (p.top ? o.z : o.x);
   p.uy = dy + (p.top ? o.w : o.y);
@@ -230,14 +230,14 @@ struct NetTotals { double wa_bi, wa_z, hpwl, hpwl3d, ncut; };
 
 // one net per group of G lanes; lane lg of the group holds pins lg + G j
 template <int G>
-__device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half_dz, float four_over_dz, float ig,
-                                              float alpha, const float* __restrict__ xyz,
+__device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, float four_over_dz, float ig,
+                                              float alpha, const float4* __restrict__ xyzp,
                                               const int32_t* __restrict__ s_net_start,
                                               const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
                                               const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out) {
   const int s = s_net_start[net], d = s_net_start[net + 1] - s;
-  const int node0 = pin_node[s];
-  const float xa = xyz[node0], ya = xyz[n + node0];
+  const float4 q0 = xyzp[pin_node[s]];
+  const float xa = q0.x, ya = q0.y;
   PinRel pc[kPinsPerLane];
 
   // ---- phase A: extremes
@@ -245,10 +245,10 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half
 #pragma unroll
   for (int j = 0; j < kPinsPerLane; ++j)
     if (lg + G * j < d) {
-      pc[j] = load_pin(xyz, n, pin_node, off, s + lg + G * j, half_dz, xa, ya);
+      pc[j] = load_pin(xyzp, pin_node, off, s + lg + G * j, half_dz, xa, ya);
       ext_add(a, pc[j]);
     }
-  for (int k = lg + G * kPinsPerLane; k < d; k += G) ext_add(a, load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya));
+  for (int k = lg + G * kPinsPerLane; k < d; k += G) ext_add(a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya));
 #pragma unroll
   for (int m = G / 2; m > 0; m >>= 1) {
     ext_merge(a.tx, m); ext_merge(a.bx, m); ext_merge(a.ty, m); ext_merge(a.by, m);
@@ -264,7 +264,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half
   for (int j = 0; j < kPinsPerLane; ++j)
     if (lg + G * j < d) sums_pin(S, a, pc[j], ig);
   for (int k = lg + G * kPinsPerLane; k < d; k += G)
-    sums_pin(S, a, load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya), ig);
+    sums_pin(S, a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), ig);
 #pragma unroll
   for (int m = G / 2; m > 0; m >>= 1) {
     sums_merge(S.xt, m); sums_merge(S.xb, m); sums_merge(S.yt, m); sums_merge(S.yb, m); sums_merge(S.z, m);
@@ -285,7 +285,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half
     if (lg + G * j < d) pin_out[slot_pos[s + lg + G * j]] = pin_result(pc[j], a, c, ig, alpha, four_over_dz);
   for (int k = lg + G * kPinsPerLane; k < d; k += G)
     pin_out[slot_pos[s + k]] =
-        pin_result(load_pin(xyz, n, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
+        pin_result(load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
 
   // ---- net totals, from the group's first lane
   NetTotals t = {0, 0, 0, 0, 0};
@@ -302,22 +302,23 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, int n, float half
 }
 
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
-    int n, float half_dz, float four_over_dz, float gamma, float alpha, const float* __restrict__ xyz,
+    float half_dz, float four_over_dz, float gamma, float alpha, const float4* __restrict__ xyzp,
     const int32_t* __restrict__ s_net_start, const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
     const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part,
     int stride) {
   __shared__ double shred[5][kWaBlock / kWave];
+  // nets are in netlist (anchor) order within a class: each die takes a contiguous block range
+  const int blk = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
   int pos = 0;                                     // layout position of this block's class
-  while (pos + 1 < kNumClasses && (int)blockIdx.x >= tab.block_begin[pos + 1]) ++pos;
+  while (pos + 1 < kNumClasses && blk >= tab.block_begin[pos + 1]) ++pos;
   const int lg2 = kNumClasses - 1 - pos;           // log2 of the group width
-  const int net = tab.net_begin[pos] + ((int)blockIdx.x - tab.block_begin[pos]) * (kWaBlock >> lg2) +
-                  ((int)threadIdx.x >> lg2);
+  const int net = tab.net_begin[pos] + (blk - tab.block_begin[pos]) * (kWaBlock >> lg2) + ((int)threadIdx.x >> lg2);
   const int lg = threadIdx.x & ((1 << lg2) - 1);
   const float ig = 1.f / gamma;
   NetTotals t = {0, 0, 0, 0, 0};
   if (net < tab.net_begin[pos + 1]) {
 #define P3D_GROUP(G) \
-  wl_group<G>(net, lg, n, half_dz, four_over_dz, ig, alpha, xyz, s_net_start, pin_node, off, slot_pos, pin_out)
+  wl_group<G>(net, lg, half_dz, four_over_dz, ig, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
     switch (lg2) {
       case 0: t = P3D_GROUP(1); break;
       case 1: t = P3D_GROUP(2); break;
@@ -340,11 +341,15 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   if (threadIdx.x < 5) {
     double x = 0.0;
     for (int w = 0; w < kWaBlock / kWave; ++w) x += shred[threadIdx.x][w];
-    part[(size_t)(R_WA_BI + threadIdx.x) * stride + blockIdx.x] = x;
+    part[(size_t)(R_WA_BI + threadIdx.x) * stride + blk] = x;
   }
 }
 
-// per instance: sum its pin shares (contiguous, ascending slot order); L1 norms over movable instances
+__global__ void k_pack_xyz(int n, const float* __restrict__ xyz, float4* __restrict__ xyzp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) xyzp[i] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], 0.f);
+}
+
 // per instance: sum its pin shares (contiguous, ascending slot order); L1 norms over movable
 // instances.  Blocks [0, nlight) take one instance per thread; instances with more than
 // kHeavyPins pins are left to the blocks after them, one wavefront per instance.
@@ -434,14 +439,19 @@ __global__ void k_wl_finish_z(int n, const float* __restrict__ gz_wa, const floa
 }  // namespace
 
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
-                    double* metrics, hipStream_t s) {
+                    double* metrics, hipStream_t s, bool packed) {
   const Geom& g = c->g;
   const place3d_problem& p = c->prob;
   int rc;
   if (c->n_wa_blocks > 0) {
+    if (!packed) {
+      ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
+      hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, xyz, c->xyzp);
+      P3D_LAUNCH(c, "k_pack_xyz");
+    }
     ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
-    hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.n, g.half_dz, 4.f / g.dz,
-                       (float)p.gamma, (float)p.alpha, xyz, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
+    hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz,
+                       (float)p.gamma, (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
                        c->pin_out, c->classes, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
   }

@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "tiny": lambda: tiny_case(5),
     "ragged": lambda: ragged_case(6),
+    "ragged_even": lambda: ragged_case(7, nx=38, ny=30),
     "c1": lambda: synth.make_case("c1", 2403),
     "c2": lambda: synth.make_case("c2", 2403),
 }
