@@ -271,6 +271,9 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
 }  // namespace
 
 place3d_ctx::~place3d_ctx() {
+  if (side) hipStreamDestroy(side);
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
   for (auto& r : prof_pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
   for (auto& e : prof_free) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
 }
@@ -338,6 +341,16 @@ int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t by
   c->ws_bytes = bytes;
   fill_geom(c);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      g_create_err = std::string("side stream / events: ") + hipGetErrorString(e);
+      delete c;
+      return PLACE3D_ERR_HIP;
+    }
+  }
   rc = build_schedule(c, s);
   if (rc == PLACE3D_OK) rc = p3d::build_dct_bases(c, s);
   if (rc == PLACE3D_OK) rc = p3d::build_fixed_map(c, s);

@@ -74,6 +74,10 @@ struct place3d_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
   double prof_ms[PLACE3D_NSTAGES] = {0};
   long long prof_count[PLACE3D_NSTAGES] = {0};
+  // side stream (default priority) on which the wirelength sweep of a step runs concurrently with
+  // the density / spectral chain, and the events that fork it from and join it to the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~place3d_ctx();
   p3d::Geom g;
   char* ws = nullptr;

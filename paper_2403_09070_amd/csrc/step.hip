@@ -223,7 +223,12 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   int rc;
   if ((rc = launch_zero_f64(c, red, R_COUNT, s))) return rc;
   if ((rc = bucket_cells(c, xyz, s))) return rc;     // also packs xyz for the wirelength sweep
-  if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, s, true))) return rc;
+  // fork: the wirelength sweep (its own reduction slots, pin and instance scratch) runs on the
+  // side stream while the density, spectral and gather chain runs on s; joined below
+  P3D_HIP(c, hipEventRecord(c->ev_fork, s));
+  P3D_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, c->side, true))) return rc;
+  P3D_HIP(c, hipEventRecord(c->ev_join, c->side));
   if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;
@@ -232,6 +237,7 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
     if ((rc = spectral_field(c, c->rho, c->phi, nullptr, nullptr, nullptr, red + R_ENERGY, s))) return rc;
     if ((rc = adjoint_bucketed(c, xyz, c->phi, c->g.vol_bin, gd, 0, s))) return rc;
   }
+  P3D_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
   return PLACE3D_OK;
 }
 
