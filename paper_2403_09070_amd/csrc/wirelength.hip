@@ -33,6 +33,33 @@ namespace {
 constexpr float kNegInf = -__builtin_huge_valf();
 constexpr float kPosInf = __builtin_huge_valf();
 
+// DPP lane exchange inside a row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Exchange with the partner lane of a butterfly step of width 2M.  Steps 1 and 2 are xor 1 and
+// xor 2 (quad permutes); steps 4 and 8 use the half-row and row mirrors (xor 7, xor 15), which
+// pair lanes inside the same aligned group of 2M lanes and, with the other steps, still reach
+// every lane of a group; 16 and 32 use a cross-lane permute.  Every merge below is commutative,
+// so both partners of an exchange compute the same value.
+template <int M>
+__device__ __forceinline__ float xchg(float v) {
+  if constexpr (M == 1) return dpp<0xB1>(v);
+  else if constexpr (M == 2) return dpp<0x4E>(v);
+  else if constexpr (M == 4) return dpp<0x141>(v);
+  else if constexpr (M == 8) return dpp<0x140>(v);
+  else return __shfl_xor(v, M);
+}
+template <int M>
+__device__ __forceinline__ int xchg(int v) {
+  return __float_as_int(xchg<M>(__int_as_float(v)));
+}
+
 struct PinRel {        // one pin, relative to the net anchor
   float ux, uy;        // on its owner's current die
   float fx, fy;        // on the other die
@@ -93,9 +120,10 @@ __device__ __forceinline__ void ext_add(NetExt& a, const PinRel& p) {
   a.zmin = fminf(a.zmin, p.z);
 }
 
-__device__ __forceinline__ void ext_merge(Ext2& e, int m) {
-  const float a1 = __shfl_xor(e.max1, m), a2 = __shfl_xor(e.max2, m);
-  const float b1 = __shfl_xor(e.min1, m), b2 = __shfl_xor(e.min2, m);
+template <int M>
+__device__ __forceinline__ void ext_merge(Ext2& e) {
+  const float a1 = xchg<M>(e.max1), a2 = xchg<M>(e.max2);
+  const float b1 = xchg<M>(e.min1), b2 = xchg<M>(e.min2);
   e.max2 = fmaxf(fmaxf(e.max2, a2), fminf(e.max1, a1));
   e.max1 = fmaxf(e.max1, a1);
   e.min2 = fminf(fminf(e.min2, b2), fmaxf(e.min1, b1));
@@ -104,10 +132,11 @@ __device__ __forceinline__ void ext_merge(Ext2& e, int m) {
 
 struct Sums4 { float sp, tp, sm, tm; };
 
-__device__ __forceinline__ void sums_merge(Sums4& s, int m) {
-  s.sp += __shfl_xor(s.sp, m); s.tp += __shfl_xor(s.tp, m);
-  s.sm += __shfl_xor(s.sm, m); s.tm += __shfl_xor(s.tm, m);
-}   // max- and min-shifted exponential sums
+template <int M>
+__device__ __forceinline__ void sums_merge(Sums4& s) {
+  s.sp += xchg<M>(s.sp); s.tp += xchg<M>(s.tp);
+  s.sm += xchg<M>(s.sm); s.tm += xchg<M>(s.tm);
+}
 
 struct NetSums { Sums4 xt, xb, yt, yb, z; };
 
@@ -141,11 +170,17 @@ struct AxisCoef {
   float W;                    // smoothed bistratal value
 };
 
+// 1 / x by the hardware reciprocal (1 ulp); the sums it divides by are >= 1 (each holds its
+// set's extreme term e^0) or are not used
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ AxisCoef axis_coef(const Ext2& T, const Sums4& st, int ct, const Ext2& B, const Sums4& sb,
                                               int cb, float ig) {
   const float Mt = T.max1, mt = T.min1, Mb = B.max1, mb = B.min1;
-  const float At_p = ct > 0 ? st.tp / st.sp : 0.f, At_m = ct > 0 ? st.tm / st.sm : 0.f;
-  const float Ab_p = cb > 0 ? sb.tp / sb.sp : 0.f, Ab_m = cb > 0 ? sb.tm / sb.sm : 0.f;
+  const float rt_p = ct > 0 ? rcp(st.sp) : 0.f, rt_m = ct > 0 ? rcp(st.sm) : 0.f;
+  const float rb_p = cb > 0 ? rcp(sb.sp) : 0.f, rb_m = cb > 0 ? rcp(sb.sm) : 0.f;
+  const float At_p = st.tp * rt_p, At_m = st.tm * rt_m;
+  const float Ab_p = sb.tp * rb_p, Ab_m = sb.tm * rb_m;
   const float pt = ct > 0 ? (Mt - mt) + (At_p - At_m) : 0.f;
   const float pb = cb > 0 ? (Mb - mb) + (Ab_p - Ab_m) : 0.f;
   AxisCoef c;
@@ -154,28 +189,27 @@ __device__ __forceinline__ AxisCoef axis_coef(const Ext2& T, const Sums4& st, in
     const float Me = fmaxf(Mt, Mb), me = fminf(mt, mb);
     const float dt = Mt - Me, db = Mb - Me;          // <= 0
     const float rt = __expf(dt * ig), rb = __expf(db * ig);
-    const float se_p = st.sp * rt + sb.sp * rb;
-    const float Ae_p = (rt * (st.tp + dt * st.sp) + rb * (sb.tp + db * sb.sp)) / se_p;
+    const float ie_p = rcp(st.sp * rt + sb.sp * rb);
+    const float Ae_p = (rt * (st.tp + dt * st.sp) + rb * (sb.tp + db * sb.sp)) * ie_p;
     const float dtm = mt - me, dbm = mb - me;         // >= 0
     const float qt = __expf(-dtm * ig), qb = __expf(-dbm * ig);
-    const float se_m = st.sm * qt + sb.sm * qb;
-    const float Ae_m = (qt * (st.tm + dtm * st.sm) + qb * (sb.tm + dbm * sb.sm)) / se_m;
+    const float ie_m = rcp(st.sm * qt + sb.sm * qb);
+    const float Ae_m = (qt * (st.tm + dtm * st.sm) + qb * (sb.tm + dbm * sb.sm)) * ie_m;
     const float pe = (Me - me) + (Ae_p - Ae_m);
     const bool split = pt + pb > pe;
     c.W = split ? pt + pb : pe;
     if (split) {
-      c.t = {Mt, mt, 1.f / st.sp, At_p, 1.f / st.sm, At_m};
-      c.b = {Mb, mb, 1.f / sb.sp, Ab_p, 1.f / sb.sm, Ab_m};
+      c.t = {Mt, mt, rt_p, At_p, rt_m, At_m};
+      c.b = {Mb, mb, rb_p, Ab_p, rb_m, Ab_m};
     } else {
-      const float ie_p = 1.f / se_p, ie_m = 1.f / se_m;
       c.t = {Mt, mt, rt * ie_p, Ae_p - dt, qt * ie_m, Ae_m - dtm};
       c.b = {Mb, mb, rb * ie_p, Ae_p - db, qb * ie_m, Ae_m - dbm};
     }
   } else {
     // one set only: the whole net is that set
     c.W = ct > 0 ? pt : pb;
-    c.t = {Mt, mt, ct > 0 ? 1.f / st.sp : 0.f, At_p, ct > 0 ? 1.f / st.sm : 0.f, At_m};
-    c.b = {Mb, mb, cb > 0 ? 1.f / sb.sp : 0.f, Ab_p, cb > 0 ? 1.f / sb.sm : 0.f, Ab_m};
+    c.t = {Mt, mt, rt_p, At_p, rt_m, At_m};
+    c.b = {Mb, mb, rb_p, Ab_p, rb_m, Ab_m};
   }
   return c;
 }
@@ -226,7 +260,40 @@ __device__ __forceinline__ float4 pin_result(const PinRel& p, const NetExt& a, c
   return make_float4(gx, gy, gz, four_over_dz * (p.top ? -dw : dw));
 }
 
-struct NetTotals { double wa_bi, wa_z, hpwl, hpwl3d, ncut; };
+template <int M>
+__device__ __forceinline__ void merge_step(NetExt& a) {
+  ext_merge<M>(a.tx); ext_merge<M>(a.bx); ext_merge<M>(a.ty); ext_merge<M>(a.by);
+  a.zmax = fmaxf(a.zmax, xchg<M>(a.zmax));
+  a.zmin = fminf(a.zmin, xchg<M>(a.zmin));
+  a.ct += xchg<M>(a.ct);
+  a.cb += xchg<M>(a.cb);
+}
+template <int M>
+__device__ __forceinline__ void merge_step(NetSums& S) {
+  sums_merge<M>(S.xt); sums_merge<M>(S.xb); sums_merge<M>(S.yt); sums_merge<M>(S.yb); sums_merge<M>(S.z);
+}
+// reduce over a group of G lanes, widest step first
+template <int G, class T>
+__device__ __forceinline__ void group_merge(T& v) {
+  if constexpr (G >= 64) merge_step<32>(v);
+  if constexpr (G >= 32) merge_step<16>(v);
+  if constexpr (G >= 16) merge_step<8>(v);
+  if constexpr (G >= 8) merge_step<4>(v);
+  if constexpr (G >= 4) merge_step<2>(v);
+  if constexpr (G >= 2) merge_step<1>(v);
+}
+
+struct NetTotals { float wa_bi, wa_z, hpwl, hpwl3d, ncut; };
+
+// Sum over the wavefront in a fixed order: quad, half-row and row sums by DPP exchanges
+// (xor 1, xor 2, mirror 8, mirror 16), then the four row sums.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp<0xB1>(v);     // quad_perm(1, 0, 3, 2)
+  v += dpp<0x4E>(v);     // quad_perm(2, 3, 0, 1)
+  v += dpp<0x141>(v);    // row_half_mirror
+  v += dpp<0x140>(v);    // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
 
 // one net per group of G lanes; lane lg of the group holds pins lg + G j
 template <int G>
@@ -249,14 +316,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
       ext_add(a, pc[j]);
     }
   for (int k = lg + G * kPinsPerLane; k < d; k += G) ext_add(a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya));
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) {
-    ext_merge(a.tx, m); ext_merge(a.bx, m); ext_merge(a.ty, m); ext_merge(a.by, m);
-    a.zmax = fmaxf(a.zmax, __shfl_xor(a.zmax, m));
-    a.zmin = fminf(a.zmin, __shfl_xor(a.zmin, m));
-    a.ct += __shfl_xor(a.ct, m);
-    a.cb += __shfl_xor(a.cb, m);
-  }
+  group_merge<G>(a);
 
   // ---- phase B: shifted exponential sums
   NetSums S = {};
@@ -265,17 +325,14 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
     if (lg + G * j < d) sums_pin(S, a, pc[j], ig);
   for (int k = lg + G * kPinsPerLane; k < d; k += G)
     sums_pin(S, a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), ig);
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) {
-    sums_merge(S.xt, m); sums_merge(S.xb, m); sums_merge(S.yt, m); sums_merge(S.yb, m); sums_merge(S.z, m);
-  }
+  group_merge<G>(S);
 
   NetCoef c;
   c.x = axis_coef(a.tx, S.xt, a.ct, a.bx, S.xb, a.cb, ig);
   c.y = axis_coef(a.ty, S.yt, a.ct, a.by, S.yb, a.cb, ig);
   c.zmax = a.zmax; c.zmin = a.zmin;
-  c.az_p = 1.f / S.z.sp; c.Az_p = S.z.tp * c.az_p;
-  c.az_m = 1.f / S.z.sm; c.Az_m = S.z.tm * c.az_m;
+  c.az_p = rcp(S.z.sp); c.Az_p = S.z.tp * c.az_p;
+  c.az_m = rcp(S.z.sm); c.Az_m = S.z.tm * c.az_m;
   c.Wx = w_exact(a.tx.max1, a.tx.min1, a.ct, a.bx.max1, a.bx.min1, a.cb);
   c.Wy = w_exact(a.ty.max1, a.ty.min1, a.ct, a.by.max1, a.by.min1, a.cb);
 
@@ -288,15 +345,14 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
         pin_result(load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
 
   // ---- net totals, from the group's first lane
-  NetTotals t = {0, 0, 0, 0, 0};
+  NetTotals t = {0.f, 0.f, 0.f, 0.f, 0.f};
   if (lg == 0) {
-    t.wa_bi = (double)c.x.W + (double)c.y.W;
-    t.wa_z = (double)alpha * (double)((a.zmax - a.zmin) + (c.Az_p - c.Az_m));
-    t.hpwl = (double)c.Wx + (double)c.Wy;
-    t.hpwl3d = (double)(fmaxf(a.tx.max1, a.bx.max1) - fminf(a.tx.min1, a.bx.min1)) +
-               (double)(fmaxf(a.ty.max1, a.by.max1) - fminf(a.ty.min1, a.by.min1)) +
-               (double)alpha * (double)(a.zmax - a.zmin);
-    t.ncut = (a.ct > 0 && a.cb > 0) ? 1.0 : 0.0;
+    t.wa_bi = c.x.W + c.y.W;
+    t.wa_z = alpha * ((a.zmax - a.zmin) + (c.Az_p - c.Az_m));
+    t.hpwl = c.Wx + c.Wy;
+    t.hpwl3d = (fmaxf(a.tx.max1, a.bx.max1) - fminf(a.tx.min1, a.bx.min1)) +
+               (fmaxf(a.ty.max1, a.by.max1) - fminf(a.ty.min1, a.by.min1)) + alpha * (a.zmax - a.zmin);
+    t.ncut = (a.ct > 0 && a.cb > 0) ? 1.f : 0.f;
   }
   return t;
 }
@@ -315,7 +371,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const int net = tab.net_begin[pos] + (blk - tab.block_begin[pos]) * (kWaBlock >> lg2) + ((int)threadIdx.x >> lg2);
   const int lg = threadIdx.x & ((1 << lg2) - 1);
   const float ig = 1.f / gamma;
-  NetTotals t = {0, 0, 0, 0, 0};
+  NetTotals t = {0.f, 0.f, 0.f, 0.f, 0.f};
   if (net < tab.net_begin[pos + 1]) {
 #define P3D_GROUP(G) \
   wl_group<G>(net, lg, half_dz, four_over_dz, ig, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
@@ -330,12 +386,12 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     }
 #undef P3D_GROUP
   }
-  const double v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
+  // net totals: float within the wavefront (at most 64 nets), float64 across wavefronts
+  const float v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    double x = v[q];
-    for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m);
-    if ((threadIdx.x & (kWave - 1)) == 0) shred[q][threadIdx.x / kWave] = x;
+    const float x = wave_sum(v[q]);
+    if ((threadIdx.x & (kWave - 1)) == 0) shred[q][threadIdx.x / kWave] = (double)x;
   }
   __syncthreads();
   if (threadIdx.x < 5) {
