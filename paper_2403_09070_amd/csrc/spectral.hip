@@ -36,6 +36,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ bases
@@ -171,7 +172,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
   const bool vec = ((K & 3) == 0) && ((N & 3) == 0) && ((lda & 3) == 0) && ((ldb & 3) == 0) && ((fn & 3) == 0) &&
                    al16(A) && al16(B);
 
-  float ra[8], rb[8];
+  // staged operands; wa / wb hold the scaled mirrored values of a fold (zero otherwise)
+  float ra[8], rb[8], wa[8], wb[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) wa[e] = wb[e] = 0.f;
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -179,41 +183,43 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
       const int ar = f >> 2, ak = (f & 3) * 4;          // A: 128 rows x 4 float4
       const int gm = m0 + ar, gk = k0 + ak;
       if (vec && gm < M && gk + 3 < K) {
-        float4 v = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + gk);
-        if (fa != 0.f) {
-          const float4 w = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + fn - 4 - gk);
-          v.x += fa * w.w; v.y += fa * w.z; v.z += fa * w.y; v.w += fa * w.x;
-        }
+        const float4 v = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + gk);
         ra[4 * q] = v.x; ra[4 * q + 1] = v.y; ra[4 * q + 2] = v.z; ra[4 * q + 3] = v.w;
+        if (fa != 0.f) {   // mirrored group, added when the stage is stored
+          const float4 w = *reinterpret_cast<const float4*>(A + (size_t)gm * lda + fn - 4 - gk);
+          wa[4 * q] = fa * w.w; wa[4 * q + 1] = fa * w.z; wa[4 * q + 2] = fa * w.y; wa[4 * q + 3] = fa * w.x;
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          float v = 0.f;
+          float v = 0.f, w = 0.f;
           if (gm < M && gk + e < K) {
             v = A[(size_t)gm * lda + gk + e];
-            if (fa != 0.f) v += fa * A[(size_t)gm * lda + fn - 1 - gk - e];
+            if (fa != 0.f) w = fa * A[(size_t)gm * lda + fn - 1 - gk - e];
           }
           ra[4 * q + e] = v;
+          wa[4 * q + e] = w;
         }
       }
       const int br = f >> 5, bn = (f & 31) * 4;         // B: 16 rows x 32 float4
       const int gkb = k0 + br, gn = n0 + bn;
       if (vec && gkb < K && gn + 3 < N) {
-        float4 v = *reinterpret_cast<const float4*>(B + (size_t)gkb * ldb + gn);
+        const float4 v = *reinterpret_cast<const float4*>(B + (size_t)gkb * ldb + gn);
+        rb[4 * q] = v.x; rb[4 * q + 1] = v.y; rb[4 * q + 2] = v.z; rb[4 * q + 3] = v.w;
         if (fb != 0.f) {
           const float4 w = *reinterpret_cast<const float4*>(B + (size_t)(fn - 1 - gkb) * ldb + gn);
-          v.x += fb * w.x; v.y += fb * w.y; v.z += fb * w.z; v.w += fb * w.w;
+          wb[4 * q] = fb * w.x; wb[4 * q + 1] = fb * w.y; wb[4 * q + 2] = fb * w.z; wb[4 * q + 3] = fb * w.w;
         }
-        rb[4 * q] = v.x; rb[4 * q + 1] = v.y; rb[4 * q + 2] = v.z; rb[4 * q + 3] = v.w;
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          float v = 0.f;
+          float v = 0.f, w = 0.f;
           if (gkb < K && gn + e < N) {
             v = B[(size_t)gkb * ldb + gn + e];
-            if (fb != 0.f) v += fb * B[(size_t)(fn - 1 - gkb) * ldb + gn + e];
+            if (fb != 0.f) w = fb * B[(size_t)(fn - 1 - gkb) * ldb + gn + e];
           }
           rb[4 * q + e] = v;
+          wb[4 * q + e] = w;
         }
       }
     }
@@ -224,10 +230,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs args) {
       const int f = tid + 256 * q;
       const int ar = f >> 2, ak = (f & 3) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[buf][ak + e][ar] = ra[4 * q + e];
+      for (int e = 0; e < 4; ++e) As[buf][ak + e][ar] = ra[4 * q + e] + wa[4 * q + e];
       const int br = f >> 5, bn = (f & 31) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[buf][br][bn + e] = rb[4 * q + e];
+      for (int e = 0; e < 4; ++e) Bs[buf][br][bn + e] = rb[4 * q + e] + wb[4 * q + e];
     }
   };
 
@@ -331,9 +337,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  // staging registers: 16 data floats, 2 x 2 basis groups of 8 bf16
-  float rd[16];
+  // staging registers: two groups of 8 data floats (and, on the full path, the scaled mirrored
+  // values of a fold, added when the stage is stored so that no load of the next stage is
+  // waited for before the MFMAs), 2 x 2 basis groups of 8 bf16
+  f32x8 rd[2], rw[2];
   u16x8 rbh[2], rbl[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) rw[q] = (f32x8)(0.f);
 
   // basis tile: rows [r0, r0 + 128) of a k-contiguous array; thread takes row f >> 2, k group
   // (f & 3) * 8 for f = tid, tid + 256
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     }
   };
   // hi = RNE(v), lo = RNE(v - hi), two values per hardware conversion
-  auto split_store = [&](unsigned short* h, unsigned short* l, const float* v) {
+  auto split_store = [&](unsigned short* h, unsigned short* l, f32x8 v) {
     u32x4 hh, ll;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -380,38 +390,41 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     *reinterpret_cast<u32x4*>(l) = ll;
   };
   // left data operand (map as A [M][K]): thread takes row f >> 2, k group (f & 3) * 8; a fold
-  // adds the mirrored group, read as two float4 and reversed
+  // reads the mirrored group as two float4 and reverses it
   auto load_left_data = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
       const int gm = m0 + r, gk = k0 + kg;
+      float v[8], w[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = 0.f;
       if (full) {
         const float* row = D + (size_t)gm * ldd;
         const float4 v0 = *reinterpret_cast<const float4*>(row + gk);
         const float4 v1 = *reinterpret_cast<const float4*>(row + gk + 4);
-        rd[8 * q + 0] = v0.x; rd[8 * q + 1] = v0.y; rd[8 * q + 2] = v0.z; rd[8 * q + 3] = v0.w;
-        rd[8 * q + 4] = v1.x; rd[8 * q + 5] = v1.y; rd[8 * q + 6] = v1.z; rd[8 * q + 7] = v1.w;
+        v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+        v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
         if (fold != 0.f) {
           const float4 w0 = *reinterpret_cast<const float4*>(row + fn - 8 - gk);   // mirror of gk+7..gk+4
           const float4 w1 = *reinterpret_cast<const float4*>(row + fn - 4 - gk);   // mirror of gk+3..gk
-          rd[8 * q + 0] += fold * w1.w; rd[8 * q + 1] += fold * w1.z;
-          rd[8 * q + 2] += fold * w1.y; rd[8 * q + 3] += fold * w1.x;
-          rd[8 * q + 4] += fold * w0.w; rd[8 * q + 5] += fold * w0.z;
-          rd[8 * q + 6] += fold * w0.y; rd[8 * q + 7] += fold * w0.x;
+          w[0] = fold * w1.w; w[1] = fold * w1.z; w[2] = fold * w1.y; w[3] = fold * w1.x;
+          w[4] = fold * w0.w; w[5] = fold * w0.z; w[6] = fold * w0.y; w[7] = fold * w0.x;
         }
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          float v = 0.f;
+          float a = 0.f;
           if (gm < M && gk + e < K) {
-            v = D[(size_t)gm * ldd + gk + e];
-            if (fold != 0.f) v += fold * D[(size_t)gm * ldd + fn - 1 - gk - e];
+            a = D[(size_t)gm * ldd + gk + e];
+            if (fold != 0.f) a += fold * D[(size_t)gm * ldd + fn - 1 - gk - e];
           }
-          rd[8 * q + e] = v;
+          v[e] = a;
         }
       }
+      rd[q] = (f32x8){v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+      rw[q] = (f32x8){w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]};
     }
   };
   auto store_left_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
@@ -419,55 +432,72 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
-      split_store(&H[r][kg], &L[r][kg], rd + 8 * q);
+      split_store(&H[r][kg], &L[r][kg], rd[q] + rw[q]);
     }
   };
   // right data operand (map as B [K][N]): thread takes columns 2 (tid & 63) + {0, 1} and k group
-  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers;
-  // a fold adds the mirrored rows
+  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers
+  // (rd[0] column 2 (tid & 63), rd[1] the next); a fold adds the mirrored rows
   auto load_right_data = [&](int k0) {
     const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
     const int gn = n0 + cn;
+    float v0[8], v1[8], w0[8], w1[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int gk = k0 + kg + e;
-      if (full) {
-        float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * ldd + gn);
-        if (fold != 0.f) {
+    for (int e = 0; e < 8; ++e) w0[e] = w1[e] = 0.f;
+    if (full) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + kg + e;
+        const float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * ldd + gn);
+        v0[e] = v.x;
+        v1[e] = v.y;
+      }
+      if (fold != 0.f) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int gk = k0 + kg + e;
           const float2 w = *reinterpret_cast<const float2*>(D + (size_t)(fn - 1 - gk) * ldd + gn);
-          v.x += fold * w.x;
-          v.y += fold * w.y;
+          w0[e] = fold * w.x;
+          w1[e] = fold * w.y;
         }
-        rd[e] = v.x;
-        rd[8 + e] = v.y;
-      } else {
-        float v0 = 0.f, v1 = 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + kg + e;
+        float a = 0.f, b = 0.f;
         if (gk < K) {
           if (gn < N) {
-            v0 = D[(size_t)gk * ldd + gn];
-            if (fold != 0.f) v0 += fold * D[(size_t)(fn - 1 - gk) * ldd + gn];
+            a = D[(size_t)gk * ldd + gn];
+            if (fold != 0.f) a += fold * D[(size_t)(fn - 1 - gk) * ldd + gn];
           }
           if (gn + 1 < N) {
-            v1 = D[(size_t)gk * ldd + gn + 1];
-            if (fold != 0.f) v1 += fold * D[(size_t)(fn - 1 - gk) * ldd + gn + 1];
+            b = D[(size_t)gk * ldd + gn + 1];
+            if (fold != 0.f) b += fold * D[(size_t)(fn - 1 - gk) * ldd + gn + 1];
           }
         }
-        rd[e] = v0;
-        rd[8 + e] = v1;
+        v0[e] = a;
+        v1[e] = b;
       }
     }
+    // one assignment of the staging vectors after both paths (no store is sunk into a choice
+    // between the arrays, which would move them to scratch memory)
+    rd[0] = (f32x8){v0[0], v0[1], v0[2], v0[3], v0[4], v0[5], v0[6], v0[7]};
+    rd[1] = (f32x8){v1[0], v1[1], v1[2], v1[3], v1[4], v1[5], v1[6], v1[7]};
+    rw[0] = (f32x8){w0[0], w0[1], w0[2], w0[3], w0[4], w0[5], w0[6], w0[7]};
+    rw[1] = (f32x8){w1[0], w1[1], w1[2], w1[3], w1[4], w1[5], w1[6], w1[7]};
   };
   auto store_right_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
     const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
-    split_store(&H[cn][kg], &L[cn][kg], rd);
-    split_store(&H[cn + 1][kg], &L[cn + 1][kg], rd + 8);
+    split_store(&H[cn][kg], &L[cn][kg], rd[0] + rw[0]);
+    split_store(&H[cn + 1][kg], &L[cn + 1][kg], rd[1] + rw[1]);
   };
   auto load = [&](int k0) {
-    if (LEFT_BASIS) { load_basis(k0, m0, M); load_right_data(k0); }
+    if constexpr (LEFT_BASIS) { load_basis(k0, m0, M); load_right_data(k0); }
     else { load_left_data(k0); load_basis(k0, n0, N); }
   };
   auto store = [&](int buf) {
-    if (LEFT_BASIS) { store_basis(Ah[buf], Al[buf]); store_right_data(Bh[buf], Bl[buf]); }
+    if constexpr (LEFT_BASIS) { store_basis(Ah[buf], Al[buf]); store_right_data(Bh[buf], Bl[buf]); }
     else { store_left_data(Ah[buf], Al[buf]); store_basis(Bh[buf], Bl[buf]); }
   };
 
