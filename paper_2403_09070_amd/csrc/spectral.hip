@@ -311,9 +311,13 @@ struct GemmSplitArgs {
 
 template <bool LEFT_BASIS>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
-  constexpr int BK = 32, LDK = BK + 8;
+  // LDS rows of 32 bf16 (four 16-byte units), unit u of row r stored at u ^ ((r >> 1) & 3): the
+  // MFMA fragment reads (8 consecutive rows, one unit) and the staging writes (2 rows x 4 units,
+  // or 8 consecutive rows x 1 unit) then touch distinct banks
+  constexpr int BK = 32, LDK = BK;
   __shared__ unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
   __shared__ unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
+  auto sw = [](int r, int unit) { return 8 * (unit ^ ((r >> 1) & 3)); };
   const int M = args.M, N = args.N, K = args.K, ldd = args.ldd, ldb = args.ldb, ldc = args.ldc, fn = args.fold_n;
   const TileIdx ti = tile_of(M, N);
   const int prob = ti.z / args.nbatch, bat = ti.z % args.nbatch;
@@ -371,8 +375,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
-      *reinterpret_cast<u16x8*>(&H[r][kg]) = rbh[q];
-      *reinterpret_cast<u16x8*>(&L[r][kg]) = rbl[q];
+      *reinterpret_cast<u16x8*>(&H[r][sw(r, kg >> 3)]) = rbh[q];
+      *reinterpret_cast<u16x8*>(&L[r][sw(r, kg >> 3)]) = rbl[q];
     }
   };
   // hi = RNE(v), lo = RNE(v - hi), two values per hardware conversion
@@ -432,33 +436,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     for (int q = 0; q < 2; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
-      split_store(&H[r][kg], &L[r][kg], rd[q] + rw[q]);
+      split_store(&H[r][sw(r, kg >> 3)], &L[r][sw(r, kg >> 3)], rd[q] + rw[q]);
     }
   };
-  // right data operand (map as B [K][N]): thread takes columns 2 (tid & 63) + {0, 1} and k group
-  // (tid >> 6) * 8, loading 8 rows of 2 consecutive columns and transposing them in registers
-  // (rd[0] column 2 (tid & 63), rd[1] the next); a fold adds the mirrored rows
+  // right data operand (map as B [K][N]): thread takes columns c0 = tid & 63 and c0 + 64 and k
+  // group (tid >> 6) * 8, loading 8 rows of each column (coalesced across the wavefront) and
+  // transposing them in registers (rd[0] column c0, rd[1] column c0 + 64); a fold adds the
+  // mirrored rows
   auto load_right_data = [&](int k0) {
-    const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
-    const int gn = n0 + cn;
+    const int c0 = tid & 63, kg = (tid >> 6) * 8;
+    const int gn0 = n0 + c0, gn1 = gn0 + 64;
     float v0[8], v1[8], w0[8], w1[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) w0[e] = w1[e] = 0.f;
     if (full) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + kg + e;
-        const float2 v = *reinterpret_cast<const float2*>(D + (size_t)gk * ldd + gn);
-        v0[e] = v.x;
-        v1[e] = v.y;
+        const float* row = D + (size_t)(k0 + kg + e) * ldd;
+        v0[e] = row[gn0];
+        v1[e] = row[gn1];
       }
       if (fold != 0.f) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int gk = k0 + kg + e;
-          const float2 w = *reinterpret_cast<const float2*>(D + (size_t)(fn - 1 - gk) * ldd + gn);
-          w0[e] = fold * w.x;
-          w1[e] = fold * w.y;
+          const float* row = D + (size_t)(fn - 1 - (k0 + kg + e)) * ldd;
+          w0[e] = fold * row[gn0];
+          w1[e] = fold * row[gn1];
         }
       }
     } else {
@@ -467,13 +470,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
         const int gk = k0 + kg + e;
         float a = 0.f, b = 0.f;
         if (gk < K) {
-          if (gn < N) {
-            a = D[(size_t)gk * ldd + gn];
-            if (fold != 0.f) a += fold * D[(size_t)(fn - 1 - gk) * ldd + gn];
+          if (gn0 < N) {
+            a = D[(size_t)gk * ldd + gn0];
+            if (fold != 0.f) a += fold * D[(size_t)(fn - 1 - gk) * ldd + gn0];
           }
-          if (gn + 1 < N) {
-            b = D[(size_t)gk * ldd + gn + 1];
-            if (fold != 0.f) b += fold * D[(size_t)(fn - 1 - gk) * ldd + gn + 1];
+          if (gn1 < N) {
+            b = D[(size_t)gk * ldd + gn1];
+            if (fold != 0.f) b += fold * D[(size_t)(fn - 1 - gk) * ldd + gn1];
           }
         }
         v0[e] = a;
@@ -488,9 +491,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     rw[1] = (f32x8){w1[0], w1[1], w1[2], w1[3], w1[4], w1[5], w1[6], w1[7]};
   };
   auto store_right_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
-    const int cn = 2 * (tid & 63), kg = (tid >> 6) * 8;
-    split_store(&H[cn][kg], &L[cn][kg], rd[0] + rw[0]);
-    split_store(&H[cn + 1][kg], &L[cn + 1][kg], rd[1] + rw[1]);
+    const int c0 = tid & 63, c1 = c0 + 64, u = tid >> 6;
+    split_store(&H[c0][sw(c0, u)], &L[c0][sw(c0, u)], rd[0] + rw[0]);
+    split_store(&H[c1][sw(c1, u)], &L[c1][sw(c1, u)], rd[1] + rw[1]);
   };
   auto load = [&](int k0) {
     if constexpr (LEFT_BASIS) { load_basis(k0, m0, M); load_right_data(k0); }
@@ -516,10 +519,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
       for (int t = 0; t < 2; ++t) {
         const int ar = wm * 64 + t * 32 + (lane & 31);
         const int bc = wn * 64 + t * 32 + (lane & 31);
-        ah[t] = *reinterpret_cast<const bf16x8*>(&Ah[cur][ar][ko]);
-        al[t] = *reinterpret_cast<const bf16x8*>(&Al[cur][ar][ko]);
-        bh[t] = *reinterpret_cast<const bf16x8*>(&Bh[cur][bc][ko]);
-        bl[t] = *reinterpret_cast<const bf16x8*>(&Bl[cur][bc][ko]);
+        ah[t] = *reinterpret_cast<const bf16x8*>(&Ah[cur][ar][sw(ar, ko >> 3)]);
+        al[t] = *reinterpret_cast<const bf16x8*>(&Al[cur][ar][sw(ar, ko >> 3)]);
+        bh[t] = *reinterpret_cast<const bf16x8*>(&Bh[cur][bc][sw(bc, ko >> 3)]);
+        bl[t] = *reinterpret_cast<const bf16x8*>(&Bl[cur][bc][sw(bc, ko >> 3)]);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
