@@ -147,8 +147,9 @@ __device__ __forceinline__ bool al16(const void* p) { return (reinterpret_cast<u
 // batch), n fastest, and the XCD-aware order gives each die a contiguous run of tiles: the n
 // tiles of one m block (which share its rows of the data operand) then stay on one die's L2.
 struct TileIdx { int n, m, z; };
+template <int BMT = BM>
 __device__ __forceinline__ TileIdx tile_of(int M, int N) {
-  const int ntn = (N + BN - 1) / BN, ntm = (M + BM - 1) / BM;
+  const int ntn = (N + BN - 1) / BN, ntm = (M + BMT - 1) / BMT;
   const int w = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
   return {w % ntn, (w / ntn) % ntm, w / (ntn * ntm)};
 }
@@ -309,17 +310,21 @@ struct GemmSplitArgs {
   GemmSplitProb p[kMaxProb];
 };
 
-template <bool LEFT_BASIS>
+// BMT: block rows, 128 or 64 (64 doubles the workgroups of a launch that would otherwise not
+// fill the chip); each of the 2 x 2 wavefronts computes BMT/2 x 64 of the block's BMT x 128.
+template <bool LEFT_BASIS, int BMT>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
+  constexpr int QA = BMT / 64;       // 256-thread passes over the A tile (BMT rows x 4 units)
+  constexpr int TA = BMT / 64;       // 32-row MFMA tiles per wavefront
   // LDS rows of 32 bf16 (four 16-byte units), unit u of row r stored at u ^ ((r >> 1) & 3): the
   // MFMA fragment reads (8 consecutive rows, one unit) and the staging writes (2 rows x 4 units,
   // or 8 consecutive rows x 1 unit) then touch distinct banks
   constexpr int BK = 32, LDK = BK;
-  __shared__ unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
+  __shared__ unsigned short Ah[2][BMT][LDK], Al[2][BMT][LDK];
   __shared__ unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
   auto sw = [](int r, int unit) { return 8 * (unit ^ ((r >> 1) & 3)); };
   const int M = args.M, N = args.N, K = args.K, ldd = args.ldd, ldb = args.ldb, ldc = args.ldc, fn = args.fold_n;
-  const TileIdx ti = tile_of(M, N);
+  const TileIdx ti = tile_of<BMT>(M, N);
   const int prob = ti.z / args.nbatch, bat = ti.z % args.nbatch;
   const GemmSplitProb P = args.p[prob];
   const float* __restrict__ D = P.data + bat * P.s_data;
@@ -329,13 +334,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
   const float fold = P.fold;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = ti.m * BM, n0 = ti.n * BN;
-  const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0) && (ldd % 8 == 0) && (ldb % 8 == 0) &&
+  const int m0 = ti.m * BMT, n0 = ti.n * BN;
+  const bool full = (m0 + BMT <= M) && (n0 + BN <= N) && (K % BK == 0) && (ldd % 8 == 0) && (ldb % 8 == 0) &&
                     (fn % 8 == 0) && al16(D) && al16(Bh_g) && al16(Bl_g);
 
-  f32x16 acc[2][2];
+  f32x16 acc[TA][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -349,11 +354,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) rw[q] = (f32x8)(0.f);
 
-  // basis tile: rows [r0, r0 + 128) of a k-contiguous array; thread takes row f >> 2, k group
-  // (f & 3) * 8 for f = tid, tid + 256
-  auto load_basis = [&](int k0, int r0, int rows) {
+  // basis tile: rows [r0, r0 + 64 nq) of a k-contiguous array; thread takes row f >> 2, k group
+  // (f & 3) * 8 for f = tid + 256 q, q < nq
+  auto load_basis = [&](int k0, int r0, int rows, int nq) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
+      if (q >= nq) break;
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
       const int gr = r0 + r, gk = k0 + kg;
@@ -370,9 +376,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
       }
     }
   };
-  auto store_basis = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
+  auto store_basis = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK], int nq) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
+      if (q >= nq) break;
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
       *reinterpret_cast<u16x8*>(&H[r][sw(r, kg >> 3)]) = rbh[q];
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
   // reads the mirrored group as two float4 and reverses it
   auto load_left_data = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
       const int gm = m0 + r, gk = k0 + kg;
@@ -433,7 +440,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
   };
   auto store_left_data = [&](unsigned short (*H)[LDK], unsigned short (*L)[LDK]) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int f = tid + 256 * q;
       const int r = f >> 2, kg = (f & 3) * 8;
       split_store(&H[r][sw(r, kg >> 3)], &L[r][sw(r, kg >> 3)], rd[q] + rw[q]);
@@ -496,12 +503,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     split_store(&H[c1][sw(c1, u)], &L[c1][sw(c1, u)], rd[1] + rw[1]);
   };
   auto load = [&](int k0) {
-    if constexpr (LEFT_BASIS) { load_basis(k0, m0, M); load_right_data(k0); }
-    else { load_left_data(k0); load_basis(k0, n0, N); }
+    if constexpr (LEFT_BASIS) { load_basis(k0, m0, M, QA); load_right_data(k0); }
+    else { load_left_data(k0); load_basis(k0, n0, N, 2); }
   };
   auto store = [&](int buf) {
-    if constexpr (LEFT_BASIS) { store_basis(Ah[buf], Al[buf]); store_right_data(Bh[buf], Bl[buf]); }
-    else { store_left_data(Ah[buf], Al[buf]); store_basis(Bh[buf], Bl[buf]); }
+    if constexpr (LEFT_BASIS) { store_basis(Ah[buf], Al[buf], QA); store_right_data(Bh[buf], Bl[buf]); }
+    else { store_left_data(Ah[buf], Al[buf]); store_basis(Bh[buf], Bl[buf], 2); }
   };
 
   const int KT = (K + BK - 1) / BK;
@@ -514,18 +521,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int ko = kk + 8 * (lane >> 5);
-      bf16x8 ah[2], al[2], bh[2], bl[2];
+      bf16x8 ah[TA], al[TA], bh[2], bl[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int ar = wm * 64 + t * 32 + (lane & 31);
-        const int bc = wn * 64 + t * 32 + (lane & 31);
+      for (int t = 0; t < TA; ++t) {
+        const int ar = wm * (BMT / 2) + t * 32 + (lane & 31);
         ah[t] = *reinterpret_cast<const bf16x8*>(&Ah[cur][ar][sw(ar, ko >> 3)]);
         al[t] = *reinterpret_cast<const bf16x8*>(&Al[cur][ar][sw(ar, ko >> 3)]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int bc = wn * 64 + t * 32 + (lane & 31);
         bh[t] = *reinterpret_cast<const bf16x8*>(&Bh[cur][bc][sw(bc, ko >> 3)]);
         bl[t] = *reinterpret_cast<const bf16x8*>(&Bl[cur][bc][sw(bc, ko >> 3)]);
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < TA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
@@ -537,13 +547,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmSplitArgs args) {
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int col = n0 + wn * 64 + b * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int row = m0 + wm * (BMT / 2) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (row < M && col < N) C[(size_t)row * ldc + col] = acc[a][b][r];
       }
     }
@@ -707,6 +717,10 @@ int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, bool left_basis, int l
   const dim3 grid((unsigned)tiles);
   ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
   if (c->prob.precision == PLACE3D_BF16X3) {
+    // 64-row blocks when 128-row ones would leave the chip with fewer than two per compute unit
+    const bool half = tiles < 512 && M > 64;
+    const long long tiles64 = (long long)((N + BN - 1) / BN) * ((M + 63) / 64) * nbatch * njobs;
+    const dim3 grid_s(half ? (unsigned)tiles64 : (unsigned)tiles);
     GemmSplitArgs a;
     a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
     a.ldd = ld_data; a.ldb = ld_basis; a.ldc = ldc; a.fold_n = fold_n;
@@ -714,8 +728,13 @@ int gemm(place3d_ctx* c, int M, int N, int K, int nbatch, bool left_basis, int l
       const GemmJob& jb = jobs[i < njobs ? i : 0];
       a.p[i] = {jb.data, jb.basis.hi, jb.basis.lo, jb.out, s_data, s_out, jb.fold};
     }
-    if (left_basis) hipLaunchKernelGGL(k_gemm_bf16x3<true>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_gemm_bf16x3<false>, grid, dim3(256), 0, s, a);
+    if (left_basis) {
+      if (half) hipLaunchKernelGGL((k_gemm_bf16x3<true, 64>), grid_s, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_bf16x3<true, 128>), grid_s, dim3(256), 0, s, a);
+    } else {
+      if (half) hipLaunchKernelGGL((k_gemm_bf16x3<false, 64>), grid_s, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_bf16x3<false, 128>), grid_s, dim3(256), 0, s, a);
+    }
   } else {
     GemmArgs a;
     a.M = M; a.N = N; a.K = K; a.nbatch = nbatch;
