@@ -102,6 +102,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->part = w.take<double>((size_t)p3d::R_COUNT * c->part_stride);
   c->npins = w.take<float>(n);
   c->s_net_start = w.take<int32_t>(m + 1);
+  c->wa_block_order = w.take<int32_t>(m / 256 + P / 512 + 16);
   c->s_pin_node = w.take<int32_t>(P + 1);
   c->s_off = w.take<float4>(P + 1);
   c->pin_out = w.take<float4>(P + 1);
@@ -164,8 +165,9 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
 
   // nets by lane-group class: a net of degree d takes G = 2^c lanes, the smallest with
   // d <= kPinsPerLane * G (64 lanes for larger nets, which then loop).  Classes are laid out
-  // from the widest groups down, nets by degree (descending, stable in net index) within a class
-  // so that a wavefront holds nets of (near) equal degree; empty nets are dropped.
+  // from the widest groups down, nets in netlist order within a class; empty nets are dropped.
+  // The workgroups of all classes then run in the order of their first net (block_order), so
+  // the whole sweep walks the netlist once and the owners it gathers stay cache-resident.
   auto net_class = [](int d) {
     int cl = 0;
     while (p3d::kPinsPerLane * (1 << cl) < d && cl < p3d::kNumClasses - 1) ++cl;
@@ -176,7 +178,7 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   for (int e = 0; e < m; ++e)
     if (ns[e + 1] > ns[e]) order.push_back(e);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return ns[a + 1] - ns[a] > ns[b + 1] - ns[b];
+    return net_class(ns[a + 1] - ns[a]) > net_class(ns[b + 1] - ns[b]);
   });
   {
     int nb = 0;
@@ -194,6 +196,19 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     c->classes.net_begin[p3d::kNumClasses] = (int32_t)order.size();
     c->classes.block_begin[p3d::kNumClasses] = nb;
     c->n_wa_blocks = nb;
+  }
+  if ((size_t)c->n_wa_blocks > (size_t)m / 256 + (size_t)P / 512 + 16)
+    return set_err(c, PLACE3D_ERR_NETLIST, "net schedule exceeds its workgroup bound");
+  std::vector<int32_t> block_order(c->n_wa_blocks);
+  {
+    std::vector<int32_t> first(c->n_wa_blocks);
+    for (int i = 0; i < p3d::kNumClasses; ++i) {
+      const int per_block = p3d::kWaBlock >> (p3d::kNumClasses - 1 - i);
+      for (int b = c->classes.block_begin[i]; b < c->classes.block_begin[i + 1]; ++b)
+        first[b] = order[c->classes.net_begin[i] + (size_t)(b - c->classes.block_begin[i]) * per_block];
+    }
+    for (int b = 0; b < c->n_wa_blocks; ++b) block_order[b] = b;
+    std::stable_sort(block_order.begin(), block_order.end(), [&](int32_t a, int32_t b) { return first[a] < first[b]; });
   }
 
   const int ms = (int)order.size();
@@ -259,6 +274,9 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     P3D_HIP(c, hipMemcpyAsync(c->slot_pos, nsl.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
   }
   P3D_HIP(c, hipMemcpyAsync(c->node_slot_start, nss.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+  if (c->n_wa_blocks > 0)
+    P3D_HIP(c, hipMemcpyAsync(c->wa_block_order, block_order.data(), sizeof(int32_t) * c->n_wa_blocks,
+                              hipMemcpyHostToDevice, s));
   P3D_HIP(c, hipMemcpyAsync(c->npins, npins.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
   if (!large.empty())
     P3D_HIP(c, hipMemcpyAsync(c->large_list, large.data(), sizeof(int32_t) * large.size(), hipMemcpyHostToDevice, s));

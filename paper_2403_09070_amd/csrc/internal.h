@@ -121,6 +121,7 @@ struct place3d_ctx {
   int32_t* heavy_list = nullptr;       // instances with more than 32 pins (summed per wavefront)
   int32_t n_heavy = 0;
   p3d::ClassTab classes = {};
+  int32_t* wa_block_order = nullptr;   // [n_wa_blocks] schedule blocks in order of their first net
   int32_t n_wa_blocks = 0;
   // per-instance scratch
   float4* xyzp = nullptr;              // [n] (x, y, z, 0) per instance, the net kernel's gather source

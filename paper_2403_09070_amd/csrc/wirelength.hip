@@ -360,11 +360,11 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     float half_dz, float four_over_dz, float gamma, float alpha, const float4* __restrict__ xyzp,
     const int32_t* __restrict__ s_net_start, const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
-    const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out, ClassTab tab, double* __restrict__ part,
-    int stride) {
+    const int32_t* __restrict__ slot_pos, float4* __restrict__ pin_out, ClassTab tab,
+    const int32_t* __restrict__ block_order, double* __restrict__ part, int stride) {
   __shared__ double shred[5][kWaBlock / kWave];
-  // nets are in netlist (anchor) order within a class: each die takes a contiguous block range
-  const int blk = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+  // workgroups run in netlist order of their first net; each die takes a contiguous range
+  const int blk = block_order[xcd_swizzle((int)blockIdx.x, (int)gridDim.x)];
   int pos = 0;                                     // layout position of this block's class
   while (pos + 1 < kNumClasses && blk >= tab.block_begin[pos + 1]) ++pos;
   const int lg2 = kNumClasses - 1 - pos;           // log2 of the group width
@@ -508,7 +508,7 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
     ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
     hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz,
                        (float)p.gamma, (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
-                       c->pin_out, c->classes, c->part, c->part_stride);
+                       c->pin_out, c->classes, c->wa_block_order, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
   }
   if ((rc = reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, red + R_WA_BI, s))) return rc;
