@@ -370,6 +370,10 @@ int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t by
     }
   }
   rc = build_schedule(c, s);
+  if (rc == PLACE3D_OK) {
+    hipError_t e = hipMemsetAsync(c->red, 0, sizeof(double) * p3d::R_COUNT, s);
+    if (e != hipSuccess) rc = p3d::hip_fail(c, e, "hipMemsetAsync(create)");
+  }
   if (rc == PLACE3D_OK) rc = p3d::build_dct_bases(c, s);
   if (rc == PLACE3D_OK) rc = p3d::build_fixed_map(c, s);
   if (rc == PLACE3D_OK) {

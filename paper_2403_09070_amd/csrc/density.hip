@@ -214,11 +214,23 @@ __device__ __forceinline__ int pack_tiles(int tx0, int tx1, int ty0, int ty1) {
 // Counts entries per (tile, block) and records each cell's packed tile range in cell_entry[0][i],
 // so that the scatter pass places a cell in exactly the tiles it was counted in.  Every
 // instance's position is also written packed (x, y, z, 0) for the wirelength sweep.
+__device__ __forceinline__ void large_record(const Geom& g, const float* __restrict__ xyz,
+                                             const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                                             const int32_t* __restrict__ large, int j, float4* __restrict__ rec);
+
+// Blocks [0, nblk) count; the blocks after them write the large-instance records.
 __global__ __launch_bounds__(256) void k_bucket_count(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                       const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                       const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
-                                                      int32_t* __restrict__ tiles_of, float4* __restrict__ xyzp) {
+                                                      int32_t* __restrict__ tiles_of, float4* __restrict__ xyzp,
+                                                      const int32_t* __restrict__ large, int nlarge,
+                                                      float4* __restrict__ lrec) {
   extern __shared__ int hist[];
+  if ((int)blockIdx.x >= t.nblk) {
+    const int j = ((int)blockIdx.x - t.nblk) * blockDim.x + threadIdx.x;
+    if (j < nlarge) large_record(g, xyz, size, kind, large, j, lrec);
+    return;
+  }
   for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) hist[k] = 0;
   __syncthreads();
   const int base = blockIdx.x * t.cpb;
@@ -318,11 +330,9 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(Geom g, TileGeom t, cons
   }
 }
 
-__global__ void k_large_records(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
-                                const uint8_t* __restrict__ kind, const int32_t* __restrict__ large, int nlarge,
-                                float4* __restrict__ rec) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nlarge) return;
+__device__ __forceinline__ void large_record(const Geom& g, const float* __restrict__ xyz,
+                                             const float* __restrict__ size, const uint8_t* __restrict__ kind,
+                                             const int32_t* __restrict__ large, int j, float4* __restrict__ rec) {
   const int i = large[j];
   const Foot f = footprint(g, xyz, size, kind[i], i);
   rec[4 * (size_t)j] = make_float4(__uint_as_float((unsigned)f.cbx | ((unsigned)f.cby << 16)), f.rx, f.ry, f.z);
@@ -918,14 +928,10 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
   ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
-  if (c->n_large > 0) {
-    hipLaunchKernelGGL(k_large_records, dim3(blocks_for(c->n_large, 256)), dim3(256), 0, s, g, xyz, p.size, p.kind,
-                       c->large_list, c->n_large, c->large_rec);
-    P3D_LAUNCH(c, "k_large_records");
-  }
   const size_t hist = sizeof(int) * t.ntiles;
-  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls, c->bk_counts,
-                     c->cell_entry, c->xyzp);
+  const int nrec = (c->n_large + 255) / 256;
+  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk + nrec), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls,
+                     c->bk_counts, c->cell_entry, c->xyzp, c->large_list, c->n_large, c->large_rec);
   P3D_LAUNCH(c, "k_bucket_count");
   hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_rows");

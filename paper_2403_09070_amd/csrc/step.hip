@@ -221,7 +221,8 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
 // The cells are bucketed once and the buckets serve the density map and its gradient.
 int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s) {
   int rc;
-  if ((rc = launch_zero_f64(c, red, R_COUNT, s))) return rc;
+  // every reduction slot read after an evaluation is written by it (the energy slot, read only
+  // for the scalars, stays as gp_init zeroed it in the field-gather form)
   if ((rc = bucket_cells(c, xyz, s))) return rc;     // also packs xyz for the wirelength sweep
   // fork: the wirelength sweep (its own reduction slots, pin and instance scratch) runs on the
   // side stream while the density, spectral and gather chain runs on s; joined below
@@ -271,6 +272,7 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
     P3D_LAUNCH(c, "k_clamp_copy");
   }
   // gradients at v0, lambda_0
+  if ((rc = launch_zero_f64(c, c->red, R_COUNT, s))) return rc;
   if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
