@@ -968,7 +968,7 @@ static bool large_in_tiles(const place3d_ctx* c) {
 }
 
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
-                    float* grad, int accumulate, hipStream_t s) {
+                    float* grad, int accumulate, hipStream_t s, bool cells) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
@@ -987,6 +987,8 @@ int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const flo
                        ey, ez, scale, grad, accumulate);
     P3D_LAUNCH(c, "k_gather_large");
   }
+  c->cell_scale = scale;
+  if (!cells) return PLACE3D_OK;
   hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
                      c->entry_out, scale, grad, accumulate);
   P3D_LAUNCH(c, "k_cells_combine");
@@ -994,7 +996,7 @@ int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const flo
 }
 
 int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
-                     hipStream_t s) {
+                     hipStream_t s, bool cells) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
@@ -1013,6 +1015,8 @@ int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float 
                        scale, grad, accumulate);
     P3D_LAUNCH(c, "k_adjoint_large");
   }
+  c->cell_scale = scale / g.vol_bin;
+  if (!cells) return PLACE3D_OK;
   hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
                      c->entry_out, scale / g.vol_bin, grad, accumulate);
   P3D_LAUNCH(c, "k_cells_combine");

@@ -121,6 +121,7 @@ struct place3d_ctx {
   int32_t* heavy_list = nullptr;       // instances with more than 32 pins (summed per wavefront)
   int32_t n_heavy = 0;
   p3d::ClassTab classes = {};
+  float cell_scale = 0.f;              // factor of the per-(cell, tile) gradient shares of the last gather
   int32_t* wa_block_order = nullptr;   // [n_wa_blocks] schedule blocks in order of their first net
   int32_t n_wa_blocks = 0;
   // per-instance scratch
@@ -195,9 +196,9 @@ int build_fixed_map(place3d_ctx* c, hipStream_t s);
 int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s);
 int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s);
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
-                    float* grad, int accumulate, hipStream_t s);
+                    float* grad, int accumulate, hipStream_t s, bool cells = true);
 int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
-                     hipStream_t s);
+                     hipStream_t s, bool cells = true);
 int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s);
 int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey,
                          const float* ez, float scale, float* grad, int accumulate, hipStream_t s);

@@ -103,10 +103,41 @@ __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float
 // g = (gw + lambda gd) / H.  Mode 0 (init): write g to `gout` and track max|g|.  Mode 1 (step):
 // accumulate |v - v_prev|^2 and |g - g_prev|^2, store g over g_prev, and the movable charge
 // per die (overflow denominators).
+// Cell density gradients held as per-(cell, tile) shares (CellShares.entry != nullptr) are summed
+// here, in the order the separate combine pass uses, instead of being materialised first.
+struct CellShares {
+  const uint8_t* cls;
+  const int32_t* cell_entry;
+  const float4* entry;
+  float scale;
+};
+
+__device__ __forceinline__ void density_grad_of(const CellShares& cs, const float* __restrict__ gd, int n, int i,
+                                                float (&d)[3]) {
+  if (!cs.entry) {
+    for (int a = 0; a < 3; ++a) d[a] = gd[a * n + i];
+    return;
+  }
+  const uint8_t c = cs.cls[i];
+  if (c == kClsLarge) {
+    for (int a = 0; a < 3; ++a) d[a] = gd[a * n + i];
+    return;
+  }
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  if (c == kClsCell) {
+    for (int q = 0; q < 4; ++q) {
+      const int e = cs.cell_entry[(size_t)q * n + i];
+      if (e >= 0) { const float4 v = cs.entry[e]; sx += v.x; sy += v.y; sz += v.z; }
+    }
+    sx *= cs.scale; sy *= cs.scale; sz *= cs.scale;
+  }
+  d[0] = sx; d[1] = sy; d[2] = sz;
+}
+
 __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
                           const float* __restrict__ npins, const float* __restrict__ v,
                           const float* __restrict__ v_prev, const float* __restrict__ gw,
-                          const float* __restrict__ gd, const double* __restrict__ lam_ptr, int lam_slot,
+                          const float* __restrict__ gd, CellShares cs, const double* __restrict__ lam_ptr, int lam_slot,
                           int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ part, int stride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
@@ -118,8 +149,10 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
     const float z = v[2 * n + i];
     if (!(k & PLACE3D_KIND_FIXED)) {
       const float H = precond(g, size, npins, k, i, z, lam, mode_pre);
+      float d[3];
+      density_grad_of(cs, gd, n, i, d);
       for (int a = 0; a < 3; ++a)
-        gv[a] = (float)(((double)gw[a * n + i] + lam * (double)gd[a * n + i]) / (double)H);
+        gv[a] = (float)(((double)gw[a * n + i] + lam * (double)d[a]) / (double)H);
       if (mode == 1) {
         for (int a = 0; a < 3; ++a) {
           const double dv = (double)v[a * n + i] - (double)v_prev[a * n + i];
@@ -219,7 +252,9 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
 
 // wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red.
 // The cells are bucketed once and the buckets serve the density map and its gradient.
-int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s) {
+// cells_in_combine: leave the cells' density-gradient shares for k_combine to sum
+int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s,
+               bool cells_in_combine = false) {
   int rc;
   // every reduction slot read after an evaluation is written by it (the energy slot, read only
   // for the scalars, stays as gp_init zeroed it in the field-gather form)
@@ -233,10 +268,10 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;
-    if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s))) return rc;
+    if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s, !cells_in_combine))) return rc;
   } else {
     if ((rc = spectral_field(c, c->rho, c->phi, nullptr, nullptr, nullptr, red + R_ENERGY, s))) return rc;
-    if ((rc = adjoint_bucketed(c, xyz, c->phi, c->g.vol_bin, gd, 0, s))) return rc;
+    if ((rc = adjoint_bucketed(c, xyz, c->phi, c->g.vol_bin, gd, 0, s, !cells_in_combine))) return rc;
   }
   P3D_HIP(c, hipStreamWaitEvent(s, c->ev_join, 0));
   return PLACE3D_OK;
@@ -289,7 +324,7 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
-                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
+                     c->gw, c->den_grad, CellShares{}, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
                      c->part, c->part_stride);
     P3D_LAUNCH(c, "k_combine(init)");
   }
@@ -305,7 +340,7 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v_prev, st->v_prev,
-                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
+                     c->gw, c->den_grad, CellShares{}, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
                      c->part, c->part_stride);
     P3D_LAUNCH(c, "k_combine(init2)");
   }
@@ -320,11 +355,12 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
   const place3d_problem& p = c->prob;
   const unsigned nb = blocks_for(g.n, 256);
   int rc;
-  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s))) return rc;
+  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s, true))) return rc;
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+    const CellShares cs{c->cls, c->cell_entry, c->entry_out, c->cell_scale};
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
-                     c->gw, c->den_grad, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 1, st->g_prev,
+                     c->gw, c->den_grad, cs, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 1, st->g_prev,
                      c->part, c->part_stride);
     P3D_LAUNCH(c, "k_combine");
   }
