@@ -537,10 +537,14 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
 
 // every (cell, tile) entry: sum over the tile's bins of overlap * map, for three maps; then, for
 // every large instance overlapping the tile, its partial sums over the tile (to lpart[j][tile])
+// Field maps stored as even / odd x halves (on = 1): column x < hx is E + O, column nx-1-x is
+// sign (E - O), with E at column x and O at column hx + x of the stored map.
+struct FoldX { int on, hx; float sx, sy, sz; };
+
 __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                       const int32_t* __restrict__ tile_start,
                                                       const float* __restrict__ mx, const float* __restrict__ my,
-                                                      const float* __restrict__ mz, float4* __restrict__ out,
+                                                      const float* __restrict__ mz, FoldX fx, float4* __restrict__ out,
                                                       const float4* __restrict__ lrec, int nlarge,
                                                       float4* __restrict__ lpart) {
   extern __shared__ float S[];
@@ -552,11 +556,25 @@ __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const 
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
-    const bool in = lx < tb.wx && ly < tb.wy;
-    const size_t b = in ? bin_index(g, bz, tb.y0 + ly, tb.x0 + lx) : 0;
-    S[k] = in ? mx[b] : 0.f;
-    S[tsz + k] = in ? my[b] : 0.f;
-    S[2 * tsz + k] = in ? mz[b] : 0.f;
+    float a = 0.f, b = 0.f, d = 0.f;
+    if (lx < tb.wx && ly < tb.wy) {
+      const int gx = tb.x0 + lx;
+      if (fx.on) {
+        const bool up = gx >= fx.hx;
+        const size_t e = bin_index(g, bz, tb.y0 + ly, up ? g.nx - 1 - gx : gx), o = e + fx.hx;
+        a = up ? fx.sx * (mx[e] - mx[o]) : mx[e] + mx[o];
+        b = up ? fx.sy * (my[e] - my[o]) : my[e] + my[o];
+        d = up ? fx.sz * (mz[e] - mz[o]) : mz[e] + mz[o];
+      } else {
+        const size_t q = bin_index(g, bz, tb.y0 + ly, gx);
+        a = mx[q];
+        b = my[q];
+        d = mz[q];
+      }
+    }
+    S[k] = a;
+    S[tsz + k] = b;
+    S[2 * tsz + k] = d;
   }
   __syncthreads();
   const int e1 = tile_start[tile + 1];
@@ -962,20 +980,18 @@ int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s)
   return density_tiles(c, xyz, rho, c->red2, s);
 }
 
-// large instances go through the tiles when their per-tile partials fit the workspace
-static bool large_in_tiles(const place3d_ctx* c) {
-  return (long long)c->n_large * c->tg.ntiles <= c->lpart_cap;
-}
-
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
-                    float* grad, int accumulate, hipStream_t s, bool cells) {
+                    float* grad, int accumulate, hipStream_t s, bool cells, bool xfold) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
   const bool tiled = large_in_tiles(c);
   ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
+  if (xfold && !tiled) return set_err(c, PLACE3D_ERR_ARG, "x-folded field maps need the tiled large-instance path");
+  // Ex comes from the sine basis (unfold sign -1), Ey and Ez from the cosine basis (+1)
+  const FoldX fx{xfold ? 1 : 0, g.nx / 2, -1.f, 1.f, 1.f};
   hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 3), s, g, t, c->bk_entries,
-                     c->bk_tile_start, ex, ey, ez, c->entry_out, c->large_rec, c->n_large,
+                     c->bk_tile_start, ex, ey, ez, fx, c->entry_out, c->large_rec, c->n_large,
                      tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_gather_tiles");
   if (c->n_large > 0 && tiled) {

@@ -121,6 +121,7 @@ struct place3d_ctx {
   int32_t* heavy_list = nullptr;       // instances with more than 32 pins (summed per wavefront)
   int32_t n_heavy = 0;
   p3d::ClassTab classes = {};
+  int field_xfold = 0;                 // the last spectral_field left its field maps x-folded
   float cell_scale = 0.f;              // factor of the per-(cell, tile) gradient shares of the last gather
   int32_t* wa_block_order = nullptr;   // [n_wa_blocks] schedule blocks in order of their first net
   int32_t n_wa_blocks = 0;
@@ -154,6 +155,11 @@ int hip_fail(place3d_ctx* c, hipError_t e, const char* where);
     if (e_ != hipSuccess) return p3d::hip_fail((ctx), e_, what);               \
   } while (0)
 
+// large instances go through the density tiles when their per-tile partials fit the workspace
+inline bool large_in_tiles(const place3d_ctx* c) {
+  return (long long)c->n_large * c->tg.ntiles <= c->lpart_cap;
+}
+
 inline unsigned blocks_for(long long n, int threads) {
   long long b = (n + threads - 1) / threads;
   return (unsigned)(b < 1 ? 1 : b);
@@ -186,8 +192,11 @@ int launch_zero_f64(place3d_ctx* c, double* p, int n, hipStream_t s);
 int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t s);
 
 int build_dct_bases(place3d_ctx* c, hipStream_t s);
+// x_folded_out: with folded contractions, leave ex / ey / ez as even and odd x halves (columns
+// [0, nx/2) and [nx/2, nx)) for a consumer that unfolds them on load; ctx->field_xfold says
+// whether that happened
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
-                   double* energy, hipStream_t s);
+                   double* energy, hipStream_t s, bool x_folded_out = false);
 
 // out[0..nq) = sums (max if is_max) of partial slots slot0.. over nparts blocks, fixed order
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);
@@ -196,7 +205,8 @@ int build_fixed_map(place3d_ctx* c, hipStream_t s);
 int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s);
 int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s);
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
-                    float* grad, int accumulate, hipStream_t s, bool cells = true);
+                    float* grad, int accumulate, hipStream_t s, bool cells = true,
+                    bool xfold = false);
 int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
                      hipStream_t s, bool cells = true);
 int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s);

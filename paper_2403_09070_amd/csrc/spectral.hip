@@ -786,7 +786,7 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s) {
 }
 
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
-                   double* energy, hipStream_t s) {
+                   double* energy, hipStream_t s, bool x_folded_out) {
   const Geom& g = c->g;
   const DctBases& d = c->dct;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -860,7 +860,8 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
       }
       if ((rc = gemm(c, nz * ny, hx, hx, 1, false, nx, nx, nx, 0, 0, 0, j, nj, s))) return rc;
     }
-    if (nxo > 0) {
+    c->field_xfold = x_folded_out && !phi && !energy;
+    if (nxo > 0 && !c->field_xfold) {
       ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
       Unfold u;
       for (int q = 0; q < 4; ++q) {
@@ -872,6 +873,7 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
       P3D_LAUNCH(c, "k_unfold_x");
     }
   } else {
+    c->field_xfold = 0;
     // dense contractions in natural frequency order
     {
       const GemmJob j[1] = {{rho, Fx, c->map_t, 0.f}};

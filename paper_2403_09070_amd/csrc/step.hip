@@ -267,8 +267,10 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   P3D_HIP(c, hipEventRecord(c->ev_join, c->side));
   if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
-    if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s))) return rc;
-    if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s, !cells_in_combine))) return rc;
+    // the field stays x-folded for the gather, which unfolds it while staging its tiles
+    if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s, large_in_tiles(c)))) return rc;
+    if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s, !cells_in_combine, c->field_xfold != 0)))
+      return rc;
   } else {
     if ((rc = spectral_field(c, c->rho, c->phi, nullptr, nullptr, nullptr, red + R_ENERGY, s))) return rc;
     if ((rc = adjoint_bucketed(c, xyz, c->phi, c->g.vol_bin, gd, 0, s, !cells_in_combine))) return rc;
