@@ -97,7 +97,11 @@ def _check(rc, ctx=None):
 
 
 def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("arrays passed to the library must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream():
@@ -197,6 +201,13 @@ class Problem:
         return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(self.device) \
             if not isinstance(a, torch.Tensor) else a.to(device=self.device, dtype=torch.float32).contiguous()
 
+    def map_in(self, m):
+        """A (nz, ny, nx) input map as a contiguous float32 device tensor."""
+        t = torch.as_tensor(m).to(device=self.device, dtype=torch.float32).contiguous()
+        if tuple(t.shape) != (self.nz, self.ny, self.nx):
+            raise ValueError(f"map of shape {tuple(t.shape)}, expected {(self.nz, self.ny, self.nx)}")
+        return t
+
     def new_map(self):
         return torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device=self.device)
 
@@ -213,7 +224,7 @@ class Problem:
     def field(self, rho, want=("phi", "ex", "ey", "ez"), energy=False):
         out = {k: self.new_map() for k in want}
         e = torch.zeros(1, dtype=torch.float64, device=self.device) if energy else None
-        _check(lib().place3d_field(self._ctx, _ptr(rho.contiguous()), _ptr(out.get("phi")), _ptr(out.get("ex")),
+        _check(lib().place3d_field(self._ctx, _ptr(self.map_in(rho)), _ptr(out.get("phi")), _ptr(out.get("ex")),
                                    _ptr(out.get("ey")), _ptr(out.get("ez")), _ptr(e), _stream()), self._ctx)
         if energy:
             out["energy"] = e
@@ -222,6 +233,7 @@ class Problem:
     def field_force(self, xyz, ex, ey, ez, lam=1.0, out=None, accumulate=False):
         xyz = self.xyz(xyz)
         g = self._grad(out)
+        ex, ey, ez = self.map_in(ex), self.map_in(ey), self.map_in(ez)
         _check(lib().place3d_field_force(self._ctx, _ptr(xyz), _ptr(ex), _ptr(ey), _ptr(ez), float(lam), _ptr(g),
                                          int(accumulate), _stream()), self._ctx)
         return g
@@ -229,7 +241,7 @@ class Problem:
     def density_vjp(self, xyz, g_rho, out=None, accumulate=False):
         xyz = self.xyz(xyz)
         g = self._grad(out)
-        _check(lib().place3d_density_vjp(self._ctx, _ptr(xyz), _ptr(g_rho.contiguous()), _ptr(g), int(accumulate),
+        _check(lib().place3d_density_vjp(self._ctx, _ptr(xyz), _ptr(self.map_in(g_rho)), _ptr(g), int(accumulate),
                                          _stream()), self._ctx)
         return g
 

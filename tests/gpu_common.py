@@ -50,3 +50,54 @@ def oracle_problem(case):
 
 def log(msg):
     print(msg, flush=True)
+
+
+def with_nets(case, nets, seed=0):
+    """The case with its netlist replaced: nets is a list of arrays of distinct instance indices;
+    pin offsets are drawn like the generator's (uniform inside the bottom-die extent, scaled by
+    0.7 on the top die)."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    deg = np.array([len(m) for m in nets], dtype=np.int64)
+    net_start = np.zeros(len(nets) + 1, dtype=np.int64)
+    np.cumsum(deg, out=net_start[1:])
+    pin2node = (np.concatenate([np.asarray(m, dtype=np.int64) for m in nets]) if len(nets)
+                else np.zeros(0, dtype=np.int64))
+    P = int(pin2node.shape[0])
+    off = np.empty((4, P), dtype=np.float64)
+    off[0] = (rng.random(P) - 0.5) * case.size[0, pin2node]
+    off[1] = (rng.random(P) - 0.5) * case.size[1, pin2node]
+    off[2] = 0.7 * off[0]
+    off[3] = 0.7 * off[1]
+    return dataclasses.replace(case, net_start=net_start.astype(np.int32), pin2node=pin2node.astype(np.int32),
+                               pin_off=off.astype(np.float32))
+
+
+def wide_net_case(seed=8):
+    """Nets of every lane-group width, including the degrees that exceed four pins per lane of a
+    64-lane group (the lanes then loop: 257 and 300 pins), single-pin nets and two-pin nets whose
+    pins share a bin."""
+    cfg = synth.small_config(n_cells=900, n_nets=10, die=150.0, nx=32, ny=32, nz=4,
+                             macros=("uniform", 3, 0.01, 0.03), degree=("geo", 0.6, 8))
+    case = synth.make_case(config=cfg, seed=seed)
+    rng = np.random.default_rng(seed)
+    n = case.n_inst
+    nets = [rng.choice(n, size=d, replace=False) for d in
+            [300, 257, 256, 200, 129, 64, 63, 33, 17, 16, 9, 8, 5, 4, 3, 2, 1, 1, 2]]
+    nets += [rng.choice(n, size=int(d), replace=False) for d in rng.integers(1, 12, size=400)]
+    return with_nets(case, nets, seed)
+
+
+def one_die_case(seed=9):
+    """Every instance on the bottom die: no net crosses the dies."""
+    case = tiny_case(seed)
+    xyz = case.xyz0.copy()
+    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
+    xyz[2] = np.minimum(xyz[2], 0.25 * dz)
+    import dataclasses
+    return dataclasses.replace(case, xyz0=xyz)
+
+
+def no_net_case(seed=10):
+    """Instances and macros but an empty netlist."""
+    return with_nets(tiny_case(seed), [], seed)

@@ -1,0 +1,111 @@
+"""Parity at the full 1.2M-cell workload (1.3M nets, 4.5M pins, grid 1024 x 1024 x 4) in the
+configuration the benchmark times: split-bf16 contractions, field-gather density gradient,
+launched exactly as place3d_step launches them (folded contractions, the net schedule and the
+tile bucketing of that size).  Every output is compared in full against the oracle on the same
+seeded inputs, with the tolerances of the small-case parity tests:
+  density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
+  many overlapping cells), field rel L2 <= 1e-4, wirelength totals rel <= 1e-5, WA x/y gradient
+  rel L2 <= 1e-5, FDA z-gradient within (4/d_z) npins 8 ulp(d_x) per instance, field gather rel L2
+  <= 1e-5.  Inputs of a stage come from the oracle (rounded to float32 for both sides).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_problem, log, need_gpu, oracle_problem, rel_l2
+from oracle import density as oden
+from oracle import density_grad as odg
+from oracle import poisson as opois
+from oracle import wirelength as owl
+from oracle.geometry import geometry_of
+from paper_2403_09070_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    need_gpu()
+    from paper_2403_09070_amd import place3d
+    log("[full] generating the 1.2M-cell workload")
+    case = synth.make_case("c4", 2403)
+    prob = gpu_problem(case, precision=place3d.BF16X3, dgrad=place3d.DGRAD_FIELD)
+    geo = geometry_of(case)
+    log("[full] oracle density map")
+    rho = oden.density_map(case.size, case.kind, case.xyz0, geo)
+    return case, prob, geo, rho
+
+
+def _clustered(case, seed=11):
+    """Movable instances pulled to a quarter of the die around its centre (seeded jitter kept),
+    so that many cells overlap in each bin."""
+    rng = np.random.default_rng(seed)
+    xyz = case.xyz0.astype(np.float64).copy()
+    mov = (case.kind & 2) == 0
+    for a, d in ((0, case.die_x), (1, case.die_y)):
+        xyz[a, mov] = 0.5 * d + 0.25 * (xyz[a, mov] - 0.5 * d) + rng.normal(0.0, 0.01 * d, mov.sum())
+        xyz[a, mov] = np.clip(xyz[a, mov], 0.0, d)
+    return xyz.astype(np.float32)
+
+
+@pytest.mark.parametrize("where", ["generated", "clustered"])
+def test_density_full(full, where):
+    case, prob, geo, rho_gen = full
+    xyz = case.xyz0 if where == "generated" else _clustered(case)
+    ref = rho_gen if where == "generated" else oden.density_map(case.size, case.kind, xyz, geo)
+    got = prob.density(xyz).cpu().numpy()
+    err = rel_l2(got, ref)
+    log(f"[full] density {where} rel_l2={err:.3e} max bin {ref.max():.2f}")
+    assert err <= 1e-6
+    assert abs(got.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
+
+
+def test_field_full(full):
+    import torch
+    case, prob, geo, rho = full
+    rho32 = rho.astype(np.float32)
+    out = prob.field(torch.from_numpy(rho32).cuda(), want=("phi", "ex", "ey", "ez"))
+    ref = opois.solve(rho32.astype(np.float64), geo)
+    for k in ("phi", "ex", "ey", "ez"):
+        err = rel_l2(out[k].cpu().numpy(), ref[k])
+        log(f"[full] field {k} rel_l2={err:.3e}")
+        assert err <= 1e-4, k
+
+
+def test_field_gather_full(full):
+    import torch
+    case, prob, geo, rho = full
+    sol = opois.solve(rho.astype(np.float32).astype(np.float64), geo, want=("ex", "ey", "ez"))
+    maps = [sol[k].astype(np.float32) for k in ("ex", "ey", "ez")]
+    g = prob.field_force(case.xyz0, *(torch.from_numpy(m).cuda() for m in maps), lam=1.0).cpu().numpy()
+    log("[full] oracle field gather")
+    ref = odg.field_gather(case.size, case.kind, case.xyz0, *(m.astype(np.float64) for m in maps), geo)
+    err = rel_l2(g, ref)
+    log(f"[full] field-gather rel_l2={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_wirelength_full(full):
+    case, prob, geo, rho = full
+    pb = oracle_problem(case)
+    g, met = prob.wl_grad(case.xyz0)
+    g = g.cpu().numpy()
+    met = met.cpu().numpy()
+    log("[full] oracle wirelength")
+    ref = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+    for key, slot in (("wa_bi", 0), ("wa_z", 1), ("hpwl_d2d", 2), ("hpwl_3d", 3)):
+        err = abs(met[slot] - ref[key]) / abs(ref[key])
+        log(f"[full] {key} gpu={met[slot]:.10g} ref={ref[key]:.10g} rel={err:.2e}")
+        assert err <= 1e-5, key
+    assert int(round(met[4])) == ref["ncut"]
+    ex, ey = rel_l2(g[0], ref["grad_x"]), rel_l2(g[1], ref["grad_y"])
+    log(f"[full] wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
+    assert ex <= 1e-5 and ey <= 1e-5
+    scale = met[8]
+    assert abs(scale - ref["fda_scale"]) <= 1e-5 * ref["fda_scale"]
+    ulp = float(np.spacing(np.float32(geo.die_x)))
+    npins = np.bincount(case.pin2node, minlength=case.n_inst)
+    want = scale * ref["fda"] + ref["grad_zwa"]
+    bound = scale * 4.0 / geo.dz * npins * 8 * ulp + 1e-5 * np.abs(ref["grad_zwa"]).max() + 1e-6 * np.abs(want)
+    diff = np.abs(g[2] - want)
+    log(f"[full] z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e}")
+    assert np.all(diff <= bound)

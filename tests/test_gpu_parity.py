@@ -1,8 +1,8 @@
 """GPU-vs-oracle parity of every hot-path call through the C ABI.
 
-Inputs are the seeded synthetic cases; where a stage is compared in isolation, the oracle is fed
-the same float32 input the GPU stage received (e.g. the GPU density map for the field), so the
-comparison measures that stage's arithmetic only.  Tolerances:
+Inputs are the seeded synthetic cases; where a stage is compared in isolation, both sides take the
+same input produced by the oracle and rounded to float32 (e.g. the oracle's density map for the
+field), so the comparison measures that stage's arithmetic only.  Tolerances:
   density map        rel L2 <= 1e-6, total volume rel <= 1e-6   (float32 sums of <= 27 terms)
   field phi, E       rel L2 <= 1e-4                            (float32 and split-bf16 MFMA)
   wirelength totals  rel <= 1e-5
@@ -13,7 +13,8 @@ comparison measures that stage's arithmetic only.  Tolerances:
 import numpy as np
 import pytest
 
-from gpu_common import gpu_problem, log, need_gpu, oracle_problem, ragged_case, rel_l2, tiny_case
+from gpu_common import (gpu_problem, log, need_gpu, no_net_case, one_die_case, oracle_problem, ragged_case, rel_l2,
+                        tiny_case, wide_net_case)
 from oracle import density as oden
 from oracle import density_grad as odg
 from oracle import poisson as opois
@@ -27,6 +28,9 @@ CASES = {
     "tiny": lambda: tiny_case(5),
     "ragged": lambda: ragged_case(6),
     "ragged_even": lambda: ragged_case(7, nx=38, ny=30),
+    "wide_nets": lambda: wide_net_case(8),
+    "one_die": lambda: one_die_case(9),
+    "no_nets": lambda: no_net_case(10),
     "c1": lambda: synth.make_case("c1", 2403),
     "c2": lambda: synth.make_case("c2", 2403),
 }
@@ -58,12 +62,14 @@ def test_density_map(setup):
 def test_field(setup, precision):
     name, case, prob = setup
     from paper_2403_09070_amd import place3d
+    import torch
     if precision == "bf16x3":
         prob = gpu_problem(case, precision=place3d.BF16X3)
     geo = geometry_of(case)
-    rho = prob.density(case.xyz0)
-    out = prob.field(rho, energy=True)
-    rho64 = rho.cpu().numpy().astype(np.float64)
+    # both sides take the oracle's density map, rounded to float32
+    rho32 = oden.density_map(case.size, case.kind, case.xyz0, geo).astype(np.float32)
+    out = prob.field(torch.from_numpy(rho32).cuda(), energy=True)
+    rho64 = rho32.astype(np.float64)
     ref = opois.solve(rho64, geo)
     for k in ("phi", "ex", "ey", "ez"):
         err = rel_l2(out[k].cpu().numpy(), ref[k])
@@ -105,12 +111,14 @@ def test_wirelength(setup):
 
 def test_field_gather(setup):
     name, case, prob = setup
+    import torch
     geo = geometry_of(case)
-    rho = prob.density(case.xyz0)
-    f = prob.field(rho, want=("ex", "ey", "ez"))
-    g = prob.field_force(case.xyz0, f["ex"], f["ey"], f["ez"], lam=1.0).cpu().numpy()
-    ref = odg.field_gather(case.size, case.kind, case.xyz0, *(f[k].cpu().numpy().astype(np.float64)
-                                                               for k in ("ex", "ey", "ez")), geo)
+    # field maps from the oracle's solve of the oracle's density, rounded to float32 for both sides
+    rho = oden.density_map(case.size, case.kind, case.xyz0, geo)
+    sol = opois.solve(rho, geo, want=("ex", "ey", "ez"))
+    maps = [sol[k].astype(np.float32) for k in ("ex", "ey", "ez")]
+    g = prob.field_force(case.xyz0, *(torch.from_numpy(m).cuda() for m in maps), lam=1.0).cpu().numpy()
+    ref = odg.field_gather(case.size, case.kind, case.xyz0, *(m.astype(np.float64) for m in maps), geo)
     err = rel_l2(g, ref)
     log(f"[parity] {name} field-gather rel_l2={err:.3e}")
     assert err <= 1e-5
