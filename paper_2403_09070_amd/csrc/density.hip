@@ -200,6 +200,10 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
 
 // ------------------------------------------------------------------ bucketing
 
+// threads of a bucketing workgroup: its 2048 instances take two rounds, and 16 wavefronts per
+// workgroup keep enough loads in flight at a few workgroups per compute unit
+constexpr int kBucketThreads = 1024;
+
 // tiles overlapped by a bucketed cell (at most 2 x 2 for the cells this path takes)
 __device__ __forceinline__ void cell_tiles(const Foot& f, const TileGeom& t, int& tx0, int& tx1, int& ty0, int& ty1) {
   tx0 = f.bx0 / t.T; tx1 = f.bx1 / t.T;
@@ -219,7 +223,7 @@ __device__ __forceinline__ void large_record(const Geom& g, const float* __restr
                                              const int32_t* __restrict__ large, int j, float4* __restrict__ rec);
 
 // Blocks [0, nblk) count; the blocks after them write the large-instance records.
-__global__ __launch_bounds__(256) void k_bucket_count(Geom g, TileGeom t, const float* __restrict__ xyz,
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_count(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                       const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                       const uint8_t* __restrict__ cls, int32_t* __restrict__ counts,
                                                       int32_t* __restrict__ tiles_of, float4* __restrict__ xyzp,
@@ -295,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan_tiles(int ntiles, const in
   if (threadIdx.x == 1023) tile_start[ntiles] = sh[1023];
 }
 
-__global__ __launch_bounds__(256) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                         const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                         const uint8_t* __restrict__ cls, const int32_t* __restrict__ counts,
                                                         const int32_t* __restrict__ tile_start,
@@ -947,15 +951,15 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
   const place3d_problem& p = c->prob;
   ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
   const size_t hist = sizeof(int) * t.ntiles;
-  const int nrec = (c->n_large + 255) / 256;
-  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk + nrec), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls,
+  const int nrec = (c->n_large + kBucketThreads - 1) / kBucketThreads;
+  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk + nrec), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
                      c->bk_counts, c->cell_entry, c->xyzp, c->large_list, c->n_large, c->large_rec);
   P3D_LAUNCH(c, "k_bucket_count");
   hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_rows");
   hipLaunchKernelGGL(k_bucket_scan_tiles, dim3(1), dim3(1024), 0, s, t.ntiles, c->bk_totals, c->bk_tile_start);
   P3D_LAUNCH(c, "k_bucket_scan_tiles");
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(256), hist, s, g, t, xyz, p.size, p.kind, c->cls,
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
                      c->bk_counts, c->bk_tile_start, c->bk_entries, c->cell_entry);
   P3D_LAUNCH(c, "k_bucket_scatter");
   return PLACE3D_OK;
