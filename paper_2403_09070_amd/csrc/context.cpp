@@ -80,6 +80,21 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   for (uint16_t** q : {&d.Fx_h, &d.Fx_l, &d.Gx_h, &d.Gx_l, &d.Hx_h, &d.Hx_l}) *q = w.take<uint16_t>(nx * nx);
   for (uint16_t** q : {&d.FyT_h, &d.FyT_l, &d.Gy_h, &d.Gy_l, &d.Hy_h, &d.Hy_l}) *q = w.take<uint16_t>(ny * ny);
   d.zmat = w.take<float>(4 * p3d::kMaxNz * p3d::kMaxNz);
+  {
+    auto& q = c->sc;
+    q = p3d::SplitChain{};
+    q.on = p.precision == PLACE3D_BF16X3 && nx % 2 == 0 && ny % 2 == 0 && (nz == 1 || nz == 2 || nz == 4);
+    if (q.on) {
+      const size_t hx = nx / 2, hy = ny / 2, rx = (hx + 31) / 32 * 32, ry = (hy + 31) / 32 * 32;
+      q.hx = (int)hx; q.hy = (int)hy; q.rx = (int)rx; q.ry = (int)ry;
+      auto hl = [&](p3d::HL& x, size_t count) { x.h = w.take<uint16_t>(count); x.l = w.take<uint16_t>(count); };
+      for (int i = 0; i < 2; ++i) { hl(q.fx[i], hx * rx); hl(q.fy[i], hy * ry); }
+      hl(q.gy, hy * 2 * ry); hl(q.hy_s, hy * 2 * ry); hl(q.gx, hx * 2 * rx); hl(q.hx_s, hx * 2 * rx);
+      for (int i = 0; i < 2; ++i) { hl(q.xs[i], nz * ny * rx); hl(q.ys[i], nz * nx * ry); }
+      hl(q.bb, nz * nx * 2 * ry);
+      hl(q.pc, nz * ny * 2 * rx); hl(q.ps, nz * ny * 2 * rx); hl(q.qc, nz * ny * 2 * rx);
+    }
+  }
   d.inv_w2 = w.take<float>(map);
   c->map_t = w.take<float>(map); c->map_a = w.take<float>(map);
   c->map_vg = w.take<float>(map); c->map_vh = w.take<float>(map);

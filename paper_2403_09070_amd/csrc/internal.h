@@ -60,6 +60,26 @@ struct DctBases {
   float* inv_w2;            // [Nz][Ny][Nx] 1/|omega|^2 with the (0,0,0) entry 0
 };
 
+// hi / lo bfloat16 planes of one split operand
+struct HL { uint16_t* h = nullptr; uint16_t* l = nullptr; };
+
+// Split-bfloat16 chain of the folded solve (even x and y, Nz of 1, 2 or 4): every contraction
+// operand lives in HBM as hi / lo planes whose rows are k-contiguous, padded with zeros to a
+// multiple of 32, so that the contractions stream both operands straight into LDS.  hx, hy are
+// the axis halves, rx, ry their padded widths.
+struct SplitChain {
+  int on = 0;
+  int hx = 0, hy = 0, rx = 0, ry = 0;
+  HL fx[2];              // forward x, even / odd frequencies: [hx][rx], row = frequency, k = x
+  HL fy[2];              // forward y: [hy][ry], row = frequency, k = y
+  HL gy, hy_s;           // inverse y (cosine, sine): [hy][2 ry], row = y, k = even then odd frequencies
+  HL gx, hx_s;           // inverse x: [hx][2 rx], row = x, k = even then odd frequencies
+  HL xs[2];              // x-folded map (sum, difference): [Nz Ny][rx]
+  HL ys[2];              // y-folded x spectra (sum, difference): [Nz Nx][ry], row = (z, x frequency)
+  HL bb;                 // potential coefficients: [Nz Nx][2 ry], row = (z frequency, x frequency)
+  HL pc, ps, qc;         // inverse-y results mixed along z: [Nz Ny][2 rx], row = (z, y)
+};
+
 }  // namespace p3d
 
 namespace p3d {
@@ -85,6 +105,7 @@ struct place3d_ctx {
   std::string err;
   // spectral
   p3d::DctBases dct;
+  p3d::SplitChain sc;
   float *map_t = nullptr, *map_a = nullptr, *map_vg = nullptr, *map_vh = nullptr;
   float *map_pc = nullptr, *map_ps = nullptr, *map_qc = nullptr;
   // step scratch maps (rho, phi, ex, ey, ez)
@@ -197,6 +218,10 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s);
 // whether that happened
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
                    double* energy, hipStream_t s, bool x_folded_out = false);
+// the split chain's bases (at creation) and its contractions; x-inverse outputs are left as even
+// and odd x halves, like the folded float32 path before its unfold
+int build_split_chain(place3d_ctx* c, hipStream_t s);
+int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez, hipStream_t s);
 
 // out[0..nq) = sums (max if is_max) of partial slots slot0.. over nparts blocks, fixed order
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);

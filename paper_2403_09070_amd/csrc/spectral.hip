@@ -782,7 +782,7 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_inv_w2, dim3(blocks_for(map, 256)), dim3(256), 0, s, g.nx, g.ny, g.nz, c->dct.fold, p.die_x,
                      p.die_y, dz, c->dct.inv_w2);
   P3D_LAUNCH(c, "k_inv_w2");
-  return PLACE3D_OK;
+  return build_split_chain(c, s);
 }
 
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
@@ -809,6 +809,9 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
 
   if (d.fold) {
     const int hx = nx / 2, hy = ny / 2;
+    if (c->sc.on) {
+      if ((rc = field_split(c, rho, phi, ex, ey, ez, s))) return rc;
+    } else {
     // forward x: T[:, even half] = S . Fx_even, T[:, odd half] = D . Fx_odd with S, D the rows
     // of rho folded about the x middle (+, -)
     {
@@ -859,6 +862,7 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
         j[nj++] = {xo[q].in + hx, sub(xo[q].b, nx, true, hx, 0), xo[q].out + hx, 0.f};
       }
       if ((rc = gemm(c, nz * ny, hx, hx, 1, false, nx, nx, nx, 0, 0, 0, j, nj, s))) return rc;
+    }
     }
     c->field_xfold = x_folded_out && !phi && !energy;
     if (nxo > 0 && !c->field_xfold) {
