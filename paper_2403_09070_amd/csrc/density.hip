@@ -945,16 +945,19 @@ int build_fixed_map(place3d_ctx* c, hipStream_t s) {
   return PLACE3D_OK;
 }
 
-int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s) {
+int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
   ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
   const size_t hist = sizeof(int) * t.ntiles;
   const int nrec = (c->n_large + kBucketThreads - 1) / kBucketThreads;
-  hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk + nrec), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
-                     c->bk_counts, c->cell_entry, c->xyzp, c->large_list, c->n_large, c->large_rec);
-  P3D_LAUNCH(c, "k_bucket_count");
+  if (part != 2) {
+    hipLaunchKernelGGL(k_bucket_count, dim3(t.nblk + nrec), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind,
+                       c->cls, c->bk_counts, c->cell_entry, c->xyzp, c->large_list, c->n_large, c->large_rec);
+    P3D_LAUNCH(c, "k_bucket_count");
+  }
+  if (part == 1) return PLACE3D_OK;
   hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_rows");
   hipLaunchKernelGGL(k_bucket_scan_tiles, dim3(1), dim3(1024), 0, s, t.ntiles, c->bk_totals, c->bk_tile_start);

@@ -227,7 +227,8 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);
 
 int build_fixed_map(place3d_ctx* c, hipStream_t s);
-int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s);
+// part 0: the whole bucketing; 1: only the count pass (which also packs xyzp); 2: the rest
+int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part = 0);
 int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s);
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
                     float* grad, int accumulate, hipStream_t s, bool cells = true,
