@@ -36,7 +36,6 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
-constexpr int kStages = 3;          // LDS ring depth (32 KiB per stage)
 constexpr int kTile = 128;          // output tile is 128 x 128, four 64 x 64 wavefront tiles
 constexpr int kStep = 32;           // k per stage
 
@@ -134,6 +133,12 @@ __device__ __forceinline__ float group_lane(float v) {
   else return dpp<Z * 0x55>(v);                                     // quad_perm (Z,Z,Z,Z)
 }
 
+// 16 bytes per lane from global memory into LDS: lane i fills bytes [16 i, 16 i + 16) of the
+// wavefront's 1 KiB at dst (the LDS address is wavefront-uniform)
+__device__ __forceinline__ void lds_load16(const uint16_t* src, unsigned short* dst) {
+  __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+
 __device__ __forceinline__ float inv_w2(const SArgs& g, int j, int k, int l) {
   const float wx = g.px * (float)j, wy = g.py * (float)k, wz = g.pz * (float)l;
   const float w2 = wx * wx + wy * wy + wz * wz;
@@ -144,7 +149,8 @@ __device__ __forceinline__ int xfreq(int pos, int h) { return pos < h ? 2 * pos 
 
 // ------------------------------------------------------------------ contraction
 
-template <int KIND, int NZ>
+// kStages: LDS ring depth (32 KiB per stage)
+template <int KIND, int NZ, int kStages>
 __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
   constexpr bool DUAL = KIND == YI;
   // stage s: [0] A hi, [1] A lo, [2] B hi, [3] B lo, each 128 rows of 32 bfloat16 (four 16-byte
@@ -176,14 +182,16 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
   auto issue = [&](int kt) {
     const int st = kt % kStages;
     const size_t ka = kt * sa, kb = kt * sb;
-    __builtin_amdgcn_global_load_lds(J.ah + oa0 + ka, &L[st][0][w * 32][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.ah + oa1 + ka, &L[st][0][w * 32 + 16][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.al + oa0 + ka, &L[st][1][w * 32][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.al + oa1 + ka, &L[st][1][w * 32 + 16][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.bh + ob0 + kb, &L[st][2][w * 32][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.bh + ob1 + kb, &L[st][2][w * 32 + 16][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.bl + ob0 + kb, &L[st][3][w * 32][0], 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(J.bl + ob1 + kb, &L[st][3][w * 32 + 16][0], 16, 0, 0);
+    unsigned short* d = &L[st][0][w * 32][0];   // [0] A hi; the arrays are kTile * kStep apart
+    constexpr int ARR = kTile * kStep;
+    lds_load16(J.ah + oa0 + ka, d);
+    lds_load16(J.ah + oa1 + ka, d + 16 * kStep);
+    lds_load16(J.al + oa0 + ka, d + ARR);
+    lds_load16(J.al + oa1 + ka, d + ARR + 16 * kStep);
+    lds_load16(J.bh + ob0 + kb, d + 2 * ARR);
+    lds_load16(J.bh + ob1 + kb, d + 2 * ARR + 16 * kStep);
+    lds_load16(J.bl + ob0 + kb, d + 3 * ARR);
+    lds_load16(J.bl + ob1 + kb, d + 3 * ARR + 16 * kStep);
   };
   constexpr int kLoadsPerStage = 8;
 
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
   } else {
     // x inverse: column x' of the even (sel 0) or odd (sel 1) half of the output rows; the tile
     // is staged in LDS and written as 512-byte row runs
-    constexpr int SR = kTile + 4;
+    constexpr int SR = kTile;
     static_assert(kTile * SR * 4 <= (int)sizeof(L), "staging does not fit");
     float* S = reinterpret_cast<float*>(&L[0][0][0][0]);
     __syncthreads();
@@ -530,10 +538,13 @@ int launch(place3d_ctx* c, SArgs& a, int njobs, hipStream_t s) {
   for (int i = njobs; i < kMaxJobs; ++i) a.job[i] = a.job[0];
   ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
   const dim3 grid((unsigned)tiles), block(256);
+  // three stages for the launches of one workgroup per compute unit, two for the x inverse,
+  // whose 768 workgroups then run two per compute unit
+  constexpr int ST = KIND == XI ? 2 : 3;
   switch (a.nz) {
-    case 1: hipLaunchKernelGGL((k_sgemm<KIND, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sgemm<KIND, 2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_sgemm<KIND, 4>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_sgemm<KIND, 1, ST>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sgemm<KIND, 2, ST>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_sgemm<KIND, 4, ST>), grid, block, 0, s, a); break;
   }
   P3D_LAUNCH(c, "k_sgemm");
   return PLACE3D_OK;
