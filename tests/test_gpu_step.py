@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 FORMS = {
     "field-fp32": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.FP32),
+    "field-bf16x3": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.BF16X3),
     "adjoint-bf16x3": dict(dgrad=place3d.DGRAD_ADJOINT, precision=place3d.BF16X3),
 }
 
