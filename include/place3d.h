@@ -110,14 +110,15 @@ enum {
 
 /* Stages timed by the optional profiler (place3d_profile_enable / place3d_profile_read). */
 enum {
-  PLACE3D_STAGE_DENSITY = 0,   /* density map: fixed-map copy, cell and macro scatter            */
-  PLACE3D_STAGE_GEMM = 1,      /* every DCT contraction launch (k_gemm_f32 or k_gemm_bf16x3)     */
-  PLACE3D_STAGE_ZMIX = 2,      /* z mixing and spectral scaling between contractions             */
+  PLACE3D_STAGE_DENSITY = 0,   /* density map by tiles: fixed-map copy, cell and macro deposits  */
+  PLACE3D_STAGE_GEMM = 1,      /* every DCT contraction launch (k_gemm_f32, k_gemm_bf16x3, k_sgemm) */
+  PLACE3D_STAGE_ZMIX = 2,      /* z mixing, spectral scaling, x fold / unfold between contractions */
   PLACE3D_STAGE_DGRAD = 3,     /* density gradient: field gather or exact adjoint                */
   PLACE3D_STAGE_WL_NETS = 4,   /* per-net WA / bistratal / FDA kernel                            */
   PLACE3D_STAGE_WL_NODES = 5,  /* per-instance gather of pin shares and z normalisation          */
   PLACE3D_STAGE_UPDATE = 6,    /* preconditioning, Nesterov move, reductions                     */
-  PLACE3D_NSTAGES = 7
+  PLACE3D_STAGE_BUCKET = 7,    /* bucketing of the cells by density tile (count, scans, scatter) */
+  PLACE3D_NSTAGES = 8
 };
 
 typedef struct place3d_problem {

@@ -949,7 +949,7 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
-  ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
+  ProfScope prof_(c, PLACE3D_STAGE_BUCKET, s);
   const size_t hist = sizeof(int) * t.ntiles;
   const int nrec = (c->n_large + kBucketThreads - 1) / kBucketThreads;
   if (part != 2) {

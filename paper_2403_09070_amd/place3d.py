@@ -25,7 +25,7 @@ KIND_MACRO, KIND_FIXED = 1, 2
 NMETRICS, NSCALARS = 16, 32
 M = dict(wa_bi=0, wa_z=1, hpwl=2, hpwl3d=3, ncut=4, norm_x=5, norm_y=6, norm_fda=7, fda_scale=8)
 S = dict(a=0, lam=1, step=2, it=3, ovfl_bot=4, ovfl_top=5, energy=6, wl=8)
-STAGES = ("density", "gemm", "zmix", "dgrad", "wl_nets", "wl_nodes", "update")
+STAGES = ("density", "gemm", "zmix", "dgrad", "wl_nets", "wl_nodes", "update", "bucket")
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SIZE", -3: "ERR_HIP", -4: "ERR_NONFINITE",
           -5: "ERR_UNSUPPORTED", -6: "ERR_NETLIST"}
 
