@@ -218,8 +218,7 @@ int build_dct_bases(place3d_ctx* c, hipStream_t s);
 // whether that happened
 int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez,
                    double* energy, hipStream_t s, bool x_folded_out = false);
-// the split chain's bases (at creation) and its contractions; x-inverse outputs are left as even
-// and odd x halves, like the folded float32 path before its unfold
+// the split chain's bases (at creation) and its contractions; outputs in natural x order
 int build_split_chain(place3d_ctx* c, hipStream_t s);
 int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* ey, float* ez, hipStream_t s);
 

@@ -864,8 +864,9 @@ int spectral_field(place3d_ctx* c, const float* rho, float* phi, float* ex, floa
       if ((rc = gemm(c, nz * ny, hx, hx, 1, false, nx, nx, nx, 0, 0, 0, j, nj, s))) return rc;
     }
     }
-    c->field_xfold = x_folded_out && !phi && !energy;
-    if (nxo > 0 && !c->field_xfold) {
+    // the split chain unfolds x in its last contraction
+    c->field_xfold = x_folded_out && !phi && !energy && !c->sc.on;
+    if (nxo > 0 && !c->field_xfold && !c->sc.on) {
       ProfScope prof_(c, PLACE3D_STAGE_ZMIX, s);
       Unfold u;
       for (int q = 0; q < 4; ++q) {

@@ -17,7 +17,7 @@
 //              (Fz), divides by |omega|^2 and writes the coefficients [l][x frequency][y frequency]
 //   y inverse  V = Gy . b (even and odd frequency halves into two accumulators); epilogue
 //              unfolds y, mixes z (Gz, Hz) and writes Pc, Ps, Qc transposed, [z][y][x frequency]
-//   x inverse  E = P . Gx_even, O = P . Gx_odd into the even and odd x halves of the output
+//   x inverse  E = P . Gx_even, O = P . Gx_odd (two accumulators); epilogue unfolds x
 // Rows of a tile are chosen so that everything an epilogue combines sits in one lane's
 // accumulator registers or in the lane 32 apart: the y fold pairs a row with its mirror across
 // lane halves, the z mixing keeps the layers of a point in one lane (y inverse, layers in the
@@ -61,6 +61,7 @@ struct SJob {
   int sel;                             // which half / basis the job computes (per kind)
   uint16_t *oh0, *ol0, *oh1, *ol1;     // split outputs
   float* of;                           // float32 output (x inverse)
+  float sg;                            // x inverse: parity sign of the basis (-1 sine, +1 cosine)
 };
 
 constexpr int kMaxJobs = 8;
@@ -152,7 +153,7 @@ __device__ __forceinline__ int xfreq(int pos, int h) { return pos < h ? 2 * pos 
 // kStages: LDS ring depth (32 KiB per stage)
 template <int KIND, int NZ, int kStages>
 __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
-  constexpr bool DUAL = KIND == YI;
+  constexpr bool DUAL = KIND == YI || KIND == XI;
   // stage s: [0] A hi, [1] A lo, [2] B hi, [3] B lo, each 128 rows of 32 bfloat16 (four 16-byte
   // units); unit u of row r sits at position u ^ ((r >> 1) & 3), so that the MFMA fragment reads
   // (8 consecutive rows, one unit) touch distinct banks
@@ -431,36 +432,25 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
         __syncthreads();
       }
   } else {
-    // x inverse: column x' of the even (sel 0) or odd (sel 1) half of the output rows; the tile
-    // is staged in LDS and written as 512-byte row runs
-    constexpr int SR = kTile;
-    static_assert(kTile * SR * 4 <= (int)sizeof(L), "staging does not fit");
-    float* S = reinterpret_cast<float*>(&L[0][0][0][0]);
-    __syncthreads();
+    // x inverse: E (even x frequencies) and O (odd) of column x' < nx/2; the output row gets
+    // E + O at x' and sg (E - O) at its mirror nx-1-x'
+    const int M = g.nz * g.ny;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b) {
+        const int xp = tn * kTile + wn * 64 + b * 32 + (lane & 31);
+        if (xp >= g.hx) continue;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int rl = wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          S[rl * SR + wn * 64 + b * 32 + (lane & 31)] = acc[0][a][b][r];
+          const int m = tm * kTile + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (m >= M) continue;
+          const float E = acc[0][a][b][r], O = acc[1][a][b][r];
+          float* row = J.of + (size_t)m * g.nx;
+          row[xp] = E + O;
+          row[g.nx - 1 - xp] = J.sg * (E - O);
         }
-    __syncthreads();
-    const int M = g.nz * g.ny;
-    const bool vec = (g.nx & 3) == 0 && (g.hx & 3) == 0;
-    for (int idx = tid; idx < kTile * (kTile / 4); idx += 256) {
-      const int rl = idx / (kTile / 4), c4 = idx % (kTile / 4);
-      const int m = tm * kTile + rl, xp = tn * kTile + 4 * c4;
-      if (m >= M || xp >= g.hx) continue;
-      const float* src = S + rl * SR + 4 * c4;
-      float* dst = J.of + (size_t)m * g.nx + J.sel * g.hx + xp;
-      if (vec && xp + 4 <= g.hx) {
-        *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
-      } else {
-        for (int e = 0; e < 4 && xp + e < g.hx; ++e) dst[e] = src[e];
       }
-    }
   }
 }
 
@@ -610,7 +600,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     a.ra = nz * ny; a.rb = q.hx; a.ro = nz * nx;
     for (int i = 0; i < 2; ++i)
       a.job[i] = SJob{q.xs[i].h, q.xs[i].l, q.fx[i].h, q.fx[i].l, 0, 0, i,
-                      q.ys[0].h, q.ys[0].l, q.ys[1].h, q.ys[1].l, nullptr};
+                      q.ys[0].h, q.ys[0].l, q.ys[1].h, q.ys[1].l, nullptr, 1.f};
     if ((rc = launch<XF>(c, a, 2, s))) return rc;
   }
   // y forward and the z mixing of the coefficients
@@ -618,7 +608,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     a.ntm = (q.hy + kTile - 1) / kTile; a.ntn = (nx + mt - 1) / mt; a.ksteps = q.ry / kStep;
     a.ra = q.hy; a.rb = nz * nx; a.ro = nz * nx;
     for (int i = 0; i < 2; ++i)
-      a.job[i] = SJob{q.fy[i].h, q.fy[i].l, q.ys[i].h, q.ys[i].l, 0, 0, i, q.bb.h, q.bb.l, nullptr, nullptr, nullptr};
+      a.job[i] = SJob{q.fy[i].h, q.fy[i].l, q.ys[i].h, q.ys[i].l, 0, 0, i, q.bb.h, q.bb.l, nullptr, nullptr, nullptr, 1.f};
     if ((rc = launch<YF>(c, a, 2, s))) return rc;
   }
   // y inverse, unfold, z mixing
@@ -629,26 +619,25 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     int nj = 0;
     if (need_pc || need_ps)
       a.job[nj++] = SJob{q.bb.h, q.bb.l, q.gy.h, q.gy.l, 0, 0, 0, need_pc ? q.pc.h : nullptr,
-                         need_pc ? q.pc.l : nullptr, need_ps ? q.ps.h : nullptr, need_ps ? q.ps.l : nullptr, nullptr};
-    if (need_qc) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.hy_s.h, q.hy_s.l, 0, 0, 1, q.qc.h, q.qc.l, nullptr, nullptr, nullptr};
+                         need_pc ? q.pc.l : nullptr, need_ps ? q.ps.h : nullptr, need_ps ? q.ps.l : nullptr, nullptr, 1.f};
+    if (need_qc) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.hy_s.h, q.hy_s.l, 0, 0, 1, q.qc.h, q.qc.l, nullptr, nullptr, nullptr, 1.f};
     if ((rc = launch<YI>(c, a, nj, s))) return rc;
   }
-  // x inverse into even / odd halves
+  // x inverse, even and odd frequency halves into two accumulators, unfolded in the epilogue
   {
-    a.ntm = (nz * ny + kTile - 1) / kTile; a.ntn = (q.hx + kTile - 1) / kTile; a.ksteps = q.rx / kStep;
+    a.ntm = (nz * ny + kTile - 1) / kTile; a.ntn = (q.hx + kTile - 1) / kTile; a.ksteps = 2 * q.rx / kStep;
     a.ra = nz * ny; a.rb = q.hx; a.ro = 0;
-    struct Out { const HL* in; const HL* basis; float* out; };
+    struct Out { const HL* in; const HL* basis; float* out; float sg; };
     Out o[4];
     int no = 0;
-    if (ex) o[no++] = {&q.pc, &q.hx_s, ex};
-    if (ey) o[no++] = {&q.qc, &q.gx, ey};
-    if (ez) o[no++] = {&q.ps, &q.gx, ez};
-    if (phi) o[no++] = {&q.pc, &q.gx, phi};
+    if (ex) o[no++] = {&q.pc, &q.hx_s, ex, -1.f};
+    if (ey) o[no++] = {&q.qc, &q.gx, ey, 1.f};
+    if (ez) o[no++] = {&q.ps, &q.gx, ez, 1.f};
+    if (phi) o[no++] = {&q.pc, &q.gx, phi, 1.f};
     int nj = 0;
     for (int i = 0; i < no; ++i)
-      for (int h = 0; h < 2; ++h)
-        a.job[nj++] = SJob{o[i].in->h, o[i].in->l, o[i].basis->h, o[i].basis->l, h * q.rx, h * q.rx, h,
-                           nullptr, nullptr, nullptr, nullptr, o[i].out};
+      a.job[nj++] = SJob{o[i].in->h, o[i].in->l, o[i].basis->h, o[i].basis->l, 0, 0, 0,
+                         nullptr, nullptr, nullptr, nullptr, o[i].out, o[i].sg};
     if ((rc = launch<XI>(c, a, nj, s))) return rc;
   }
   return PLACE3D_OK;
