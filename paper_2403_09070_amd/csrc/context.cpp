@@ -92,7 +92,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
       hl(q.gy, hy * 2 * ry); hl(q.hy_s, hy * 2 * ry); hl(q.gx, hx * 2 * rx); hl(q.hx_s, hx * 2 * rx);
       for (int i = 0; i < 2; ++i) { hl(q.xs[i], nz * ny * rx); hl(q.ys[i], nz * nx * ry); }
       hl(q.bb, nz * nx * 2 * ry);
-      hl(q.pc, nz * ny * 2 * rx); hl(q.ps, nz * ny * 2 * rx); hl(q.qc, nz * ny * 2 * rx);
+      hl(q.vg, nz * ny * 2 * rx); hl(q.vh, nz * ny * 2 * rx);
     }
   }
   d.inv_w2 = w.take<float>(map);

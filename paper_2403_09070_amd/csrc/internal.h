@@ -77,7 +77,7 @@ struct SplitChain {
   HL xs[2];              // x-folded map (sum, difference): [Nz Ny][rx]
   HL ys[2];              // y-folded x spectra (sum, difference): [Nz Nx][ry], row = (z, x frequency)
   HL bb;                 // potential coefficients: [Nz Nx][2 ry], row = (z frequency, x frequency)
-  HL pc, ps, qc;         // inverse-y results mixed along z: [Nz Ny][2 rx], row = (z, y)
+  HL vg, vh;             // inverse-y results (cosine, sine basis): [Nz Ny][2 rx], row = (z frequency, y)
 };
 
 }  // namespace p3d

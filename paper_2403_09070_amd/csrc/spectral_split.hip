@@ -15,12 +15,13 @@
 //              y-folded planes transposed, [z][x frequency][y]
 //   y forward  A = Fy_even . T_sum, Fy_odd . T_diff per (z, x frequency); epilogue mixes z
 //              (Fz), divides by |omega|^2 and writes the coefficients [l][x frequency][y frequency]
-//   y inverse  V = Gy . b (even and odd frequency halves into two accumulators); epilogue
-//              unfolds y, mixes z (Gz, Hz) and writes Pc, Ps, Qc transposed, [z][y][x frequency]
-//   x inverse  E = P . Gx_even, O = P . Gx_odd (two accumulators); epilogue unfolds x
+//   y inverse  V = Gy . b, Hy . b (even and odd frequency halves into two accumulators);
+//              epilogue unfolds y and writes V transposed, [z frequency][y][x frequency]
+//   x inverse  E = V . Gx_even, O = V . Gx_odd (two accumulators); epilogue unfolds x and mixes
+//              z (Gz or Hz), which commutes with the x contraction
 // Rows of a tile are chosen so that everything an epilogue combines sits in one lane's
 // accumulator registers or in the lane 32 apart: the y fold pairs a row with its mirror across
-// lane halves, the z mixing keeps the layers of a point in one lane (y inverse, layers in the
+// lane halves, the z mixing keeps the layers of a point in one lane (x inverse, layers in the
 // register quads) or in one group of adjacent lanes (y forward, exchanged by DPP).
 #include <cmath>
 
@@ -101,8 +102,12 @@ __device__ __forceinline__ int a_row(const SArgs& g, int tm, int r) {
     kx = kx < g.nx ? kx : g.nx - 1;
     return kx * NZ + l;
   } else {
-    const int m = tm * kTile + r, M = g.nz * g.ny;
-    return m < M ? m : M - 1;
+    // the same layout over (z frequency, y): the layers of a point in one lane's register quads
+    const int t = r >> 5, b = r & 31, q = b >> 3;
+    const int l = q % NZ, y0 = tm * (kTile / NZ) + t * (32 / NZ);
+    int y = y0 + ((b & 7) | ((q / NZ) << 3));
+    y = y < g.ny ? y : g.ny - 1;
+    return l * g.ny + y;
   }
 }
 
@@ -349,11 +354,8 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
   } else if constexpr (KIND == YI) {
     // rows: register quad q -> layer q % NZ and x bits (q / NZ) << 3, register r % 4 and lane
     // half -> x bits 0-2; column = y'.  V(y') = E + O, V(ny-1-y') = E - O (cosine, sel 0) or
-    // O - E (sine, sel 1); then Pc = Gz^T V, Ps = Hz^T V (sel 0) or Qc = Gz^T V (sel 1).
-    // Each (side, plane) is staged in LDS as [z][y'][x frequency] and written out as whole rows
-    // (z, y) of the blocked output.
-    const float* Gz = g.zmat + kMaxNz * kMaxNz;
-    const float* Hz = g.zmat + 2 * kMaxNz * kMaxNz;
+    // O - E (sine, sel 1).  Each side is staged in LDS as [layer][y'][x frequency] and written
+    // out as whole rows (layer, y) of the blocked output.
     const bool cosine = J.sel == 0;
     constexpr int KXT = kTile / NZ;          // x frequencies of the tile
     constexpr int SR = KXT + 8;              // staged row stride (bfloat16), 16-byte multiple
@@ -363,78 +365,62 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
     unsigned short* S = &L[0][0][0][0];
     __syncthreads();
 #pragma unroll
-    for (int side = 0; side < 2; ++side)
+    for (int side = 0; side < 2; ++side) {
 #pragma unroll
-      for (int pl = 0; pl < 2; ++pl) {
-        uint16_t* oh = pl ? J.oh1 : J.oh0;
-        uint16_t* ol = pl ? J.ol1 : J.ol0;
-        if (!oh) continue;
-        const float* zc = pl ? Hz : Gz;
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          const int yl = wn * 64 + b * 32 + (lane & 31);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int yl = wn * 64 + b * 32 + (lane & 31);
+          for (int gq = 0; gq < 4 / NZ; ++gq) {
+            const int kxl = (wm * 2 + a) * (32 / NZ) + (gq << 3) + ((lane >> 5) << 2);
 #pragma unroll
-            for (int gq = 0; gq < 4 / NZ; ++gq) {
-              const int kxl = (wm * 2 + a) * (32 / NZ) + (gq << 3) + ((lane >> 5) << 2);
-              float o[NZ][4];
+            for (int l = 0; l < NZ; ++l) {
+              float o[4];
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
-                float v[NZ];
-#pragma unroll
-                for (int l = 0; l < NZ; ++l) {
-                  const float E = acc[0][a][b][4 * (gq * NZ + l) + e], O = acc[1][a][b][4 * (gq * NZ + l) + e];
-                  v[l] = side == 0 ? E + O : (cosine ? E - O : O - E);
-                }
-#pragma unroll
-                for (int z = 0; z < NZ; ++z) {
-                  float sum = 0.f;
-#pragma unroll
-                  for (int l = 0; l < NZ; ++l) sum += zc[l * kMaxNz + z] * v[l];
-                  o[z][e] = sum;
-                }
+                const float E = acc[0][a][b][4 * (gq * NZ + l) + e], O = acc[1][a][b][4 * (gq * NZ + l) + e];
+                o[e] = side == 0 ? E + O : (cosine ? E - O : O - E);
               }
-#pragma unroll
-              for (int z = 0; z < NZ; ++z) {
-                const u32x2 t0 = split2(o[z][0], o[z][1]), t1 = split2(o[z][2], o[z][3]);
-                const int at = (z * kTile + yl) * SR + kxl;
-                *reinterpret_cast<u32x2*>(S + at) = (u32x2){t0[0], t1[0]};
-                *reinterpret_cast<u32x2*>(S + PL + at) = (u32x2){t0[1], t1[1]};
-              }
-            }
-          }
-        __syncthreads();
-        // copy out: consecutive threads take consecutive 16-byte chunks of consecutive rows
-        for (int idx = tid; idx < 2 * NZ * kTile * CH; idx += 256) {
-          const int hl = idx / (NZ * kTile * CH), rem = idx % (NZ * kTile * CH);
-          const int c = rem % CH, rl = rem / CH, z = rl / kTile, yl = rl % kTile;
-          const int yp = tn * kTile + yl;
-          if (yp >= g.hy) continue;
-          const int y = side ? g.ny - 1 - yp : yp;
-          const size_t grow = (size_t)(z * g.ny + y);
-          uint16_t* dst = hl ? ol : oh;
-          const unsigned short* src = S + hl * PL + rl * SR + 8 * c;
-          const int kx0 = tm * KXT + 8 * c;
-          if (kx0 + 8 <= g.hx || (kx0 >= g.hx && kx0 + 8 <= g.nx && (g.hx & 7) == 0)) {
-            const int col = kx0 < g.hx ? kx0 : g.rx + kx0 - g.hx;
-            *reinterpret_cast<u32x4*>(dst + ((size_t)(col / kStep) * g.ro + grow) * kStep + col % kStep) =
-                *reinterpret_cast<const u32x4*>(src);
-          } else {
-            for (int e = 0; e < 8; ++e) {
-              const int kx = kx0 + e;
-              if (kx >= g.nx) break;
-              const int col = kx < g.hx ? kx : g.rx + kx - g.hx;
-              dst[((size_t)(col / kStep) * g.ro + grow) * kStep + col % kStep] = src[e];
+              const u32x2 t0 = split2(o[0], o[1]), t1 = split2(o[2], o[3]);
+              const int at = (l * kTile + yl) * SR + kxl;
+              *reinterpret_cast<u32x2*>(S + at) = (u32x2){t0[0], t1[0]};
+              *reinterpret_cast<u32x2*>(S + PL + at) = (u32x2){t0[1], t1[1]};
             }
           }
         }
-        __syncthreads();
+      __syncthreads();
+      // copy out: consecutive threads take consecutive 16-byte chunks of consecutive rows
+      for (int idx = tid; idx < 2 * NZ * kTile * CH; idx += 256) {
+        const int hl = idx / (NZ * kTile * CH), rem = idx % (NZ * kTile * CH);
+        const int c = rem % CH, rl = rem / CH, l = rl / kTile, yl = rl % kTile;
+        const int yp = tn * kTile + yl;
+        if (yp >= g.hy) continue;
+        const int y = side ? g.ny - 1 - yp : yp;
+        const size_t grow = (size_t)(l * g.ny + y);
+        uint16_t* dst = hl ? J.ol0 : J.oh0;
+        const unsigned short* src = S + hl * PL + rl * SR + 8 * c;
+        const int kx0 = tm * KXT + 8 * c;
+        if (kx0 + 8 <= g.hx || (kx0 >= g.hx && kx0 + 8 <= g.nx && (g.hx & 7) == 0)) {
+          const int col = kx0 < g.hx ? kx0 : g.rx + kx0 - g.hx;
+          *reinterpret_cast<u32x4*>(dst + ((size_t)(col / kStep) * g.ro + grow) * kStep + col % kStep) =
+              *reinterpret_cast<const u32x4*>(src);
+        } else {
+          for (int e = 0; e < 8; ++e) {
+            const int kx = kx0 + e;
+            if (kx >= g.nx) break;
+            const int col = kx < g.hx ? kx : g.rx + kx - g.hx;
+            dst[((size_t)(col / kStep) * g.ro + grow) * kStep + col % kStep] = src[e];
+          }
+        }
       }
+      __syncthreads();
+    }
   } else {
-    // x inverse: E (even x frequencies) and O (odd) of column x' < nx/2; the output row gets
-    // E + O at x' and sg (E - O) at its mirror nx-1-x'
-    const int M = g.nz * g.ny;
+    // x inverse: E (even x frequencies) and O (odd) of column x' < nx/2 for the layers of a point
+    // (register quads, as in the y inverse); the output rows (z, y) get Z^T (E + O) at x' and
+    // sg Z^T (E - O) at the mirror nx-1-x', Z = Gz or Hz
+    const float* Z = g.zmat + (J.sel ? 2 : 1) * kMaxNz * kMaxNz;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -442,14 +428,31 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
         const int xp = tn * kTile + wn * 64 + b * 32 + (lane & 31);
         if (xp >= g.hx) continue;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = tm * kTile + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          if (m >= M) continue;
-          const float E = acc[0][a][b][r], O = acc[1][a][b][r];
-          float* row = J.of + (size_t)m * g.nx;
-          row[xp] = E + O;
-          row[g.nx - 1 - xp] = J.sg * (E - O);
-        }
+        for (int gq = 0; gq < 4 / NZ; ++gq)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int y = tm * (kTile / NZ) + (wm * 2 + a) * (32 / NZ) + (gq << 3) + ((lane >> 5) << 2) + e;
+            if (y >= g.ny) continue;
+            float u[NZ], v[NZ];
+#pragma unroll
+            for (int l = 0; l < NZ; ++l) {
+              const float E = acc[0][a][b][4 * (gq * NZ + l) + e], O = acc[1][a][b][4 * (gq * NZ + l) + e];
+              u[l] = E + O;
+              v[l] = E - O;
+            }
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) {
+              float pu = 0.f, pv = 0.f;
+#pragma unroll
+              for (int l = 0; l < NZ; ++l) {
+                pu += Z[l * kMaxNz + z] * u[l];
+                pv += Z[l * kMaxNz + z] * v[l];
+              }
+              float* row = J.of + (size_t)(z * g.ny + y) * g.nx;
+              row[xp] = pu;
+              row[g.nx - 1 - xp] = J.sg * pv;
+            }
+          }
       }
   }
 }
@@ -565,7 +568,7 @@ int build_split_chain(place3d_ctx* c, hipStream_t s) {
   P3D_LAUNCH(c, "k_panel");
   // the pad columns of the inverse-y outputs are never written: clear them once
   const size_t px = (size_t)g.nz * ny * 2 * q.rx * sizeof(uint16_t);
-  for (const HL* h : {&q.pc, &q.ps, &q.qc}) {
+  for (const HL* h : {&q.vg, &q.vh}) {
     P3D_HIP(c, hipMemsetAsync(h->h, 0, px, s));
     P3D_HIP(c, hipMemsetAsync(h->l, 0, px, s));
   }
@@ -611,32 +614,31 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
       a.job[i] = SJob{q.fy[i].h, q.fy[i].l, q.ys[i].h, q.ys[i].l, 0, 0, i, q.bb.h, q.bb.l, nullptr, nullptr, nullptr, 1.f};
     if ((rc = launch<YF>(c, a, 2, s))) return rc;
   }
-  // y inverse, unfold, z mixing
-  const bool need_pc = phi || ex, need_ps = ez != nullptr, need_qc = ey != nullptr;
+  // y inverse and unfold
+  const bool need_g = phi || ex || ez, need_h = ey != nullptr;
   {
     a.ntm = (nx + mt - 1) / mt; a.ntn = (q.hy + kTile - 1) / kTile; a.ksteps = 2 * q.ry / kStep;
     a.ra = nz * nx; a.rb = q.hy; a.ro = nz * ny;
     int nj = 0;
-    if (need_pc || need_ps)
-      a.job[nj++] = SJob{q.bb.h, q.bb.l, q.gy.h, q.gy.l, 0, 0, 0, need_pc ? q.pc.h : nullptr,
-                         need_pc ? q.pc.l : nullptr, need_ps ? q.ps.h : nullptr, need_ps ? q.ps.l : nullptr, nullptr, 1.f};
-    if (need_qc) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.hy_s.h, q.hy_s.l, 0, 0, 1, q.qc.h, q.qc.l, nullptr, nullptr, nullptr, 1.f};
+    if (need_g) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.gy.h, q.gy.l, 0, 0, 0, q.vg.h, q.vg.l, nullptr, nullptr, nullptr, 1.f};
+    if (need_h) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.hy_s.h, q.hy_s.l, 0, 0, 1, q.vh.h, q.vh.l, nullptr, nullptr, nullptr, 1.f};
     if ((rc = launch<YI>(c, a, nj, s))) return rc;
   }
-  // x inverse, even and odd frequency halves into two accumulators, unfolded in the epilogue
+  // x inverse, even and odd frequency halves into two accumulators; unfold and z mixing in the
+  // epilogue (Ex = Gz^T Vg Hx, Ey = Gz^T Vh Gx, Ez = Hz^T Vg Gx, phi = Gz^T Vg Gx)
   {
-    a.ntm = (nz * ny + kTile - 1) / kTile; a.ntn = (q.hx + kTile - 1) / kTile; a.ksteps = 2 * q.rx / kStep;
+    a.ntm = (ny + mt - 1) / mt; a.ntn = (q.hx + kTile - 1) / kTile; a.ksteps = 2 * q.rx / kStep;
     a.ra = nz * ny; a.rb = q.hx; a.ro = 0;
-    struct Out { const HL* in; const HL* basis; float* out; float sg; };
+    struct Out { const HL* in; const HL* basis; int zsin; float* out; float sg; };
     Out o[4];
     int no = 0;
-    if (ex) o[no++] = {&q.pc, &q.hx_s, ex, -1.f};
-    if (ey) o[no++] = {&q.qc, &q.gx, ey, 1.f};
-    if (ez) o[no++] = {&q.ps, &q.gx, ez, 1.f};
-    if (phi) o[no++] = {&q.pc, &q.gx, phi, 1.f};
+    if (ex) o[no++] = {&q.vg, &q.hx_s, 0, ex, -1.f};
+    if (ey) o[no++] = {&q.vh, &q.gx, 0, ey, 1.f};
+    if (ez) o[no++] = {&q.vg, &q.gx, 1, ez, 1.f};
+    if (phi) o[no++] = {&q.vg, &q.gx, 0, phi, 1.f};
     int nj = 0;
     for (int i = 0; i < no; ++i)
-      a.job[nj++] = SJob{o[i].in->h, o[i].in->l, o[i].basis->h, o[i].basis->l, 0, 0, 0,
+      a.job[nj++] = SJob{o[i].in->h, o[i].in->l, o[i].basis->h, o[i].basis->l, 0, 0, o[i].zsin,
                          nullptr, nullptr, nullptr, nullptr, o[i].out, o[i].sg};
     if ((rc = launch<XI>(c, a, nj, s))) return rc;
   }
