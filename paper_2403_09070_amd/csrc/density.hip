@@ -278,35 +278,48 @@ __global__ __launch_bounds__(256) void k_bucket_scan_rows(int nblk, int32_t* __r
   if (threadIdx.x == 255) totals[blockIdx.x] = sh[255];
 }
 
-// exclusive scan of the tile totals -> tile_start[0..ntiles]
-__global__ __launch_bounds__(1024) void k_bucket_scan_tiles(int ntiles, const int32_t* __restrict__ totals,
-                                                            int32_t* __restrict__ tile_start) {
-  __shared__ int sh[1024];
-  const int per = (ntiles + 1023) / 1024;
-  const int k0 = threadIdx.x * per, k1 = min(k0 + per, ntiles);
-  int s = 0;
-  for (int k = k0; k < k1; ++k) s += totals[k];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int run = sh[threadIdx.x] - s;
-  for (int k = k0; k < k1; ++k) { tile_start[k] = run; run += totals[k]; }
-  if (threadIdx.x == 1023) tile_start[ntiles] = sh[1023];
-}
-
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                         const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                         const uint8_t* __restrict__ cls, const int32_t* __restrict__ counts,
-                                                        const int32_t* __restrict__ tile_start,
+                                                        const int32_t* __restrict__ totals,
+                                                        int32_t* __restrict__ tile_start,
                                                         float4* __restrict__ entries, int32_t* __restrict__ cell_entry) {
+  // every workgroup scans the tile totals itself (exclusive prefix = tile_start) and workgroup 0
+  // stores the result for the later passes; the cursor of tile k starts at tile_start[k] plus
+  // this workgroup's offset within the tile
   extern __shared__ int cursor[];
-  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x)
-    cursor[k] = tile_start[k] + counts[(size_t)k * t.nblk + blockIdx.x];
+  __shared__ int wsum[kBucketThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int per = (t.ntiles + blockDim.x - 1) / blockDim.x;
+  const int k0 = min((int)threadIdx.x * per, t.ntiles), k1 = min(k0 + per, t.ntiles);
+  int own = 0;
+  for (int k = k0; k < k1; ++k) { const int v = totals[k]; cursor[k] = v; own += v; }
+  int incl = own;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    const int nw = blockDim.x / kWave;
+    const int wv = lane < nw ? wsum[lane] : 0;
+    int wi = wv;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(wi, o);
+      if (lane >= o) wi += u;
+    }
+    if (lane < nw) wsum[lane] = wi - wv;
+  }
+  __syncthreads();
+  int run = wsum[wave] + incl - own;
+  for (int k = k0; k < k1; ++k) {
+    const int v = cursor[k];
+    if (blockIdx.x == 0) tile_start[k] = run;
+    cursor[k] = run + counts[(size_t)k * t.nblk + blockIdx.x];
+    run += v;
+  }
+  if (blockIdx.x == 0 && k0 < k1 && k1 == t.ntiles) tile_start[t.ntiles] = run;
   __syncthreads();
   const int n = g.n;
   const int base = blockIdx.x * t.cpb;
@@ -513,10 +526,17 @@ __global__ void k_zero_f64(double* __restrict__ p, int n) {
 }
 
 // out[q] = sum (or max) over b < nparts of part[(slot0 + q) * stride + b], in a fixed order
-__global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ part, int stride, int slot0, int nparts,
-                                                   int is_max, double* __restrict__ out) {
+// Workgroups [0, nq0) reduce slots slot0.. over nparts0 partials into out0[]; workgroups from nq0
+// on reduce slots slot1.. over nparts1 partials into out1[] (a second group in the same launch).
+__global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ part, int stride, int slot0, int nq0,
+                                                   int nparts0, int is_max, double* __restrict__ out0, int slot1,
+                                                   int nparts1, double* __restrict__ out1) {
   __shared__ double sh[256];
-  const int q = slot0 + blockIdx.x;
+  const bool second = (int)blockIdx.x >= nq0;
+  const int qi = second ? (int)blockIdx.x - nq0 : (int)blockIdx.x;
+  const int q = (second ? slot1 : slot0) + qi;
+  const int nparts = second ? nparts1 : nparts0;
+  double* out = second ? out1 : out0;
   const double* row = part + (size_t)q * stride;
   // four independent accumulators keep four loads in flight per thread
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -534,7 +554,7 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
       sh[threadIdx.x] = is_max ? fmax(sh[threadIdx.x], sh[threadIdx.x + o]) : sh[threadIdx.x] + sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) out[qi] = sh[0];
 }
 
 // ------------------------------------------------------------------ field gather
@@ -927,8 +947,17 @@ int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t 
 
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s) {
   ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
-  hipLaunchKernelGGL(k_red_final, dim3(nq), dim3(256), 0, s, c->part, c->part_stride, slot0, nparts, is_max ? 1 : 0,
-                     out);
+  hipLaunchKernelGGL(k_red_final, dim3(nq), dim3(256), 0, s, c->part, c->part_stride, slot0, nq, nparts,
+                     is_max ? 1 : 0, out, 0, 0, out);
+  P3D_LAUNCH(c, "k_red_final");
+  return PLACE3D_OK;
+}
+
+int reduce_final2(place3d_ctx* c, int slot0, int nq0, int nparts0, double* out0, int slot1, int nq1, int nparts1,
+                  double* out1, hipStream_t s) {
+  ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
+  hipLaunchKernelGGL(k_red_final, dim3(nq0 + nq1), dim3(256), 0, s, c->part, c->part_stride, slot0, nq0, nparts0, 0,
+                     out0, slot1, nparts1, out1);
   P3D_LAUNCH(c, "k_red_final");
   return PLACE3D_OK;
 }
@@ -960,15 +989,13 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part) {
   if (part == 1) return PLACE3D_OK;
   hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_rows");
-  hipLaunchKernelGGL(k_bucket_scan_tiles, dim3(1), dim3(1024), 0, s, t.ntiles, c->bk_totals, c->bk_tile_start);
-  P3D_LAUNCH(c, "k_bucket_scan_tiles");
   hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
-                     c->bk_counts, c->bk_tile_start, c->bk_entries, c->cell_entry);
+                     c->bk_counts, c->bk_totals, c->bk_tile_start, c->bk_entries, c->cell_entry);
   P3D_LAUNCH(c, "k_bucket_scatter");
   return PLACE3D_OK;
 }
 
-int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s) {
+int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s, bool reduce) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
@@ -979,6 +1006,7 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
                        c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
   }
+  if (!reduce) return PLACE3D_OK;
   return reduce_final(c, R_EXCESS_BOT, 2, t.ntiles, false, red + R_EXCESS_BOT, s);
 }
 

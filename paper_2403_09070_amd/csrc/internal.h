@@ -224,11 +224,16 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
 
 // out[0..nq) = sums (max if is_max) of partial slots slot0.. over nparts blocks, fixed order
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);
+// two sum reductions in one launch: slots slot0.. (nq0 of them, nparts0 partials) into out0[] and
+// slots slot1.. (nq1, nparts1) into out1[]
+int reduce_final2(place3d_ctx* c, int slot0, int nq0, int nparts0, double* out0, int slot1, int nq1, int nparts1,
+                  double* out1, hipStream_t s);
 
 int build_fixed_map(place3d_ctx* c, hipStream_t s);
 // part 0: the whole bucketing; 1: only the count pass (which also packs xyzp); 2: the rest
 int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part = 0);
-int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s);
+// reduce: finish the overflow reduction here (else the caller reduces the R_EXCESS slots later)
+int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hipStream_t s, bool reduce = true);
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
                     float* grad, int accumulate, hipStream_t s, bool cells = true,
                     bool xfold = false);

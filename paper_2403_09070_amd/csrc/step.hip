@@ -253,8 +253,9 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
 // wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red.
 // The cells are bucketed once and the buckets serve the density map and its gradient.
 // cells_in_combine: leave the cells' density-gradient shares for k_combine to sum
+// defer_excess: leave the overflow slots' partials for the caller's final reduction
 int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* red, hipStream_t s,
-               bool cells_in_combine = false) {
+               bool cells_in_combine = false, bool defer_excess = false) {
   int rc;
   // every reduction slot read after an evaluation is written by it (the energy slot, read only
   // for the scalars, stays as gp_init zeroed it in the field-gather form)
@@ -266,7 +267,7 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, c->side, true))) return rc;
   P3D_HIP(c, hipEventRecord(c->ev_join, c->side));
   if ((rc = bucket_cells(c, xyz, s, 2))) return rc;
-  if ((rc = density_tiles(c, xyz, c->rho, red, s))) return rc;
+  if ((rc = density_tiles(c, xyz, c->rho, red, s, !defer_excess))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     // the field stays x-folded for the gather, which unfolds it while staging its tiles
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s, large_in_tiles(c)))) return rc;
@@ -358,7 +359,7 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
   const place3d_problem& p = c->prob;
   const unsigned nb = blocks_for(g.n, 256);
   int rc;
-  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s, true))) return rc;
+  if ((rc = eval_parts(c, st->v, c->gw, c->den_grad, c->red, s, true, true))) return rc;
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     const CellShares cs{c->cls, c->cell_entry, c->entry_out, c->cell_scale};
@@ -367,7 +368,10 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
                      c->part, c->part_stride);
     P3D_LAUNCH(c, "k_combine");
   }
-  if ((rc = reduce_final(c, R_DV2, 4, (int)nb, false, c->red + R_DV2, s))) return rc;
+  // the step's partials and the density pass's overflow partials, in one launch
+  if ((rc = reduce_final2(c, R_DV2, 4, (int)nb, c->red + R_DV2, R_EXCESS_BOT, 2, c->tg.ntiles, c->red + R_EXCESS_BOT,
+                          s)))
+    return rc;
   {
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, st->u, st->v,
