@@ -53,6 +53,8 @@ p3d::TileGeom tile_geom(const place3d_problem& p) {
   int T = 32;
   while (T > 4 && (3 * T * T * p.nz * 4 > 60 * 1024 || T > p.nx || T > p.ny)) T >>= 1;
   t.T = T;
+  t.lgT = 0;
+  while ((1 << t.lgT) < T) ++t.lgT;
   t.ntx = (p.nx + T - 1) / T;
   t.nty = (p.ny + T - 1) / T;
   t.ntiles = t.ntx * t.nty;

@@ -206,8 +206,8 @@ constexpr int kBucketThreads = 1024;
 
 // tiles overlapped by a bucketed cell (at most 2 x 2 for the cells this path takes)
 __device__ __forceinline__ void cell_tiles(const Foot& f, const TileGeom& t, int& tx0, int& tx1, int& ty0, int& ty1) {
-  tx0 = f.bx0 / t.T; tx1 = f.bx1 / t.T;
-  ty0 = f.by0 / t.T; ty1 = f.by1 / t.T;
+  tx0 = f.bx0 >> t.lgT; tx1 = f.bx1 >> t.lgT;
+  ty0 = f.by0 >> t.lgT; ty1 = f.by1 >> t.lgT;
 }
 
 // packed tile range of a bucketed cell: tx0 | ty0 << 12 | (tx1 - tx0) << 24 | (ty1 - ty0) << 25
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     S64[k] = (lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)]) : 0ull;
   }
   __syncthreads();
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
   float ex[2] = {0.f, 0.f};
   const int half = g.nz / 2;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     if (lx < tb.wx && ly < tb.wy) {
       const float v = (float)((double)S64[k] * kUnfix);
       rho[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] = v;
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const 
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     float a = 0.f, b = 0.f, d = 0.f;
     if (lx < tb.wx && ly < tb.wy) {
       const int gx = tb.x0 + lx;
@@ -688,8 +688,8 @@ __global__ void k_large_gather_finish(Geom g, TileGeom t, const int32_t* __restr
   const int lane = threadIdx.x & (kWave - 1);
   if (j >= nlarge) return;
   const float4 b = lrec[4 * (size_t)j + 3];
-  const int tx0 = __float_as_int(b.x) / t.T, tx1 = __float_as_int(b.y) / t.T;
-  const int ty0 = __float_as_int(b.z) / t.T, ty1 = __float_as_int(b.w) / t.T;
+  const int tx0 = __float_as_int(b.x) >> t.lgT, tx1 = __float_as_int(b.y) >> t.lgT;
+  const int ty0 = __float_as_int(b.z) >> t.lgT, ty1 = __float_as_int(b.w) >> t.lgT;
   const int ntx = tx1 - tx0 + 1, count = ntx * (ty1 - ty0 + 1);
   float sx = 0.f, sy = 0.f, sz = 0.f;
   for (int q = lane; q < count; q += kWave) {
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k % t.T, ly = (k / t.T) % t.T, bz = k / (t.T * t.T);
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
   }
   __syncthreads();
@@ -858,8 +858,8 @@ __global__ void k_large_adjoint_finish(Geom g, TileGeom t, const int32_t* __rest
   const int lane = threadIdx.x & (kWave - 1);
   if (j >= nlarge) return;
   const float4 b = lrec[4 * (size_t)j + 3];
-  const int tx0 = __float_as_int(b.x) / t.T, tx1 = __float_as_int(b.y) / t.T;
-  const int ty0 = __float_as_int(b.z) / t.T, ty1 = __float_as_int(b.w) / t.T;
+  const int tx0 = __float_as_int(b.x) >> t.lgT, tx1 = __float_as_int(b.y) >> t.lgT;
+  const int ty0 = __float_as_int(b.z) >> t.lgT, ty1 = __float_as_int(b.w) >> t.lgT;
   const int ntx = tx1 - tx0 + 1, count = ntx * (ty1 - ty0 + 1);
   AdjSums a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int q = lane; q < count; q += kWave) {

@@ -39,7 +39,7 @@ constexpr uint8_t kClsLarge = 1;   // movable macro or oversized cell: swept bin
 constexpr uint8_t kClsFixed = 2;   // fixed: part of the constant map
 
 struct TileGeom {       // map tiles owned by one workgroup each, and the bucketing partition
-  int T, ntx, nty, ntiles;
+  int T, lgT, ntx, nty, ntiles;   // T = 2^lgT bins per tile side
   int cpb, nblk;        // cells per bucket block, bucket blocks
 };
 
