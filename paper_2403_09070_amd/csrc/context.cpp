@@ -85,7 +85,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   {
     auto& q = c->sc;
     q = p3d::SplitChain{};
-    q.on = p.precision == PLACE3D_BF16X3 && nx % 2 == 0 && ny % 2 == 0 && (nz == 1 || nz == 2 || nz == 4);
+    q.on = p.precision == PLACE3D_BF16X3 && nx % 2 == 0 && ny % 2 == 0 && (nz == 2 || nz == 4);
     if (q.on) {
       const size_t hx = nx / 2, hy = ny / 2, rx = (hx + 31) / 32 * 32, ry = (hy + 31) / 32 * 32;
       q.hx = (int)hx; q.hy = (int)hy; q.rx = (int)rx; q.ry = (int)ry;
@@ -144,6 +144,7 @@ void fill_geom(place3d_ctx* c) {
   const double dz = p.nz * db;
   g.dx = (float)p.die_x; g.dy = (float)p.die_y; g.dz = (float)dz;
   g.wb = (float)wb; g.hb = (float)hb; g.db = (float)db;
+  g.wbd = wb; g.hbd = hb;
   g.inv_wb = (float)(1.0 / wb); g.inv_hb = (float)(1.0 / hb); g.inv_db = (float)(1.0 / db);
   g.half_dz = (float)(0.5 * dz);
   g.vol_bin = (float)(wb * hb * db);

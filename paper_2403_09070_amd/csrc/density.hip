@@ -44,15 +44,16 @@ __device__ __forceinline__ void foot_local(const Geom& g, Foot& f, int cbx, int 
   f.cbx = cbx;
   f.cby = cby;
   f.rx = rx; f.ry = ry; f.z = z; f.hw = hw; f.hh = hh;
-  const float ox = (float)cbx * g.wb, oy = (float)cby * g.hb;
+  // the region's edges relative to the reference bin's origin
+  const double ox = (double)cbx * g.wbd, oy = (double)cby * g.hbd;
   f.rx0 = rx - hw;
   f.rx1 = rx + hw;
   f.ry0 = ry - hh;
   f.ry1 = ry + hh;
-  f.lx0 = fmaxf(f.rx0, -ox);
-  f.lx1 = fminf(f.rx1, g.dx - ox);
-  f.ly0 = fmaxf(f.ry0, -oy);
-  f.ly1 = fminf(f.ry1, g.dy - oy);
+  f.lx0 = fmaxf(f.rx0, (float)-ox);
+  f.lx1 = fminf(f.rx1, (float)((double)g.dx - ox));
+  f.ly0 = fmaxf(f.ry0, (float)-oy);
+  f.ly1 = fminf(f.ry1, (float)((double)g.dy - oy));
   f.rz0 = z - 0.25f * g.dz;
   f.rz1 = z + 0.25f * g.dz;
   f.z0 = fmaxf(f.rz0, 0.f);
@@ -99,7 +100,8 @@ __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict
   f.omega = fminf(1.f, w / wmin) * fminf(1.f, h / hmin);
   const int cbx = clampi((int)floorf(x * g.inv_wb), 0, g.nx - 1);
   const int cby = clampi((int)floorf(y * g.inv_hb), 0, g.ny - 1);
-  foot_local(g, f, cbx, cby, x - (float)cbx * g.wb, y - (float)cby * g.hb, z, 0.5f * fmaxf(w, wmin),
+  foot_local(g, f, cbx, cby, (float)((double)x - (double)cbx * g.wbd), (float)((double)y - (double)cby * g.hbd), z,
+             0.5f * fmaxf(w, wmin),
              0.5f * fmaxf(h, hmin));
   return f;
 }
@@ -130,18 +132,20 @@ __device__ __forceinline__ Foot foot_record(const Geom& g, const float4* __restr
   return f;
 }
 
-// overlap lengths of the clipped cuboid with bin b along each axis
+// overlap lengths of the clipped cuboid with bin b along each axis, from the edges taken relative
+// to the bin (a bin the cuboid covers gets exactly the bin size, whatever its distance from the
+// footprint's reference bin)
 __device__ __forceinline__ float len_x(const Geom& g, const Foot& f, int b) {
   const float lo = (float)(b - f.cbx) * g.wb;
-  return fmaxf(0.f, fminf(f.lx1, lo + g.wb) - fmaxf(f.lx0, lo));
+  return fmaxf(0.f, fminf(f.lx1 - lo, g.wb) - fmaxf(f.lx0 - lo, 0.f));
 }
 __device__ __forceinline__ float len_y(const Geom& g, const Foot& f, int b) {
   const float lo = (float)(b - f.cby) * g.hb;
-  return fmaxf(0.f, fminf(f.ly1, lo + g.hb) - fmaxf(f.ly0, lo));
+  return fmaxf(0.f, fminf(f.ly1 - lo, g.hb) - fmaxf(f.ly0 - lo, 0.f));
 }
 __device__ __forceinline__ float len_z(const Geom& g, const Foot& f, int b) {
   const float lo = (float)b * g.db;
-  return fmaxf(0.f, fminf(f.z1, lo + g.db) - fmaxf(f.z0, lo));
+  return fmaxf(0.f, fminf(f.z1 - lo, g.db) - fmaxf(f.z0 - lo, 0.f));
 }
 
 // bin holding an unclipped edge (or -1 when the region clips that edge)

@@ -46,6 +46,8 @@ struct TileGeom {       // map tiles owned by one workgroup each, and the bucket
 struct Geom {
   int n, nx, ny, nz;
   float dx, dy, dz, wb, hb, db, inv_wb, inv_hb, inv_db, half_dz, vol_bin;
+  double wbd, hbd;      // bin sizes in float64: bin origins b * size are formed in float64, so
+                        // that a size that float32 cannot hold does not shift far bins' edges
 };
 
 struct DctBases {
@@ -63,7 +65,7 @@ struct DctBases {
 // hi / lo bfloat16 planes of one split operand
 struct HL { uint16_t* h = nullptr; uint16_t* l = nullptr; };
 
-// Split-bfloat16 chain of the folded solve (even x and y, Nz of 1, 2 or 4): every contraction
+// Split-bfloat16 chain of the folded solve (even x and y, Nz of 2 or 4): every contraction
 // operand lives in HBM as hi / lo planes whose rows are k-contiguous, padded with zeros to a
 // multiple of 32, so that the contractions stream both operands straight into LDS.  hx, hy are
 // the axis halves, rx, ry their padded widths.

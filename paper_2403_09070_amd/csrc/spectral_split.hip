@@ -134,9 +134,8 @@ __device__ __forceinline__ float dpp(float v) {
 // value of lane (group base + z) of a group of NZ adjacent lanes
 template <int NZ, int Z>
 __device__ __forceinline__ float group_lane(float v) {
-  if constexpr (NZ == 1) return v;
-  else if constexpr (NZ == 2) return dpp<Z == 0 ? 0xA0 : 0xF5>(v);   // quad_perm (0,0,2,2) / (1,1,3,3)
-  else return dpp<Z * 0x55>(v);                                     // quad_perm (Z,Z,Z,Z)
+  if constexpr (NZ == 2) return dpp<Z == 0 ? 0xA0 : 0xF5>(v);   // quad_perm (0,0,2,2) / (1,1,3,3)
+  else return dpp<Z * 0x55>(v);                                 // quad_perm (Z,Z,Z,Z)
 }
 
 // 16 bytes per lane from global memory into LDS: lane i fills bytes [16 i, 16 i + 16) of the
@@ -534,11 +533,8 @@ int launch(place3d_ctx* c, SArgs& a, int njobs, hipStream_t s) {
   // three stages for the launches of one workgroup per compute unit, two for the x inverse,
   // whose 768 workgroups then run two per compute unit
   constexpr int ST = KIND == XI ? 2 : 3;
-  switch (a.nz) {
-    case 1: hipLaunchKernelGGL((k_sgemm<KIND, 1, ST>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sgemm<KIND, 2, ST>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_sgemm<KIND, 4, ST>), grid, block, 0, s, a); break;
-  }
+  if (a.nz == 2) hipLaunchKernelGGL((k_sgemm<KIND, 2, ST>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_sgemm<KIND, 4, ST>), grid, block, 0, s, a);
   P3D_LAUNCH(c, "k_sgemm");
   return PLACE3D_OK;
 }

@@ -30,11 +30,11 @@ def tiny_case(seed=5, **kw):
     return synth.make_case(config=synth.small_config(**kw), seed=seed)
 
 
-def ragged_case(seed=6, nx=37, ny=29):
+def ragged_case(seed=6, nx=37, ny=29, nz=4):
     """A grid that is not a multiple of any tile size, with macros and a ragged netlist.  Odd
     sides take the dense spectral contractions; even sides (e.g. 38 x 30, halves 19 x 15) the
-    folded ones with ragged halves."""
-    cfg = synth.small_config(n_cells=700, n_nets=800, die=150.0, nx=nx, ny=ny, nz=4,
+    folded ones with ragged halves (the split-bf16 chain when Nz is 2 or 4)."""
+    cfg = synth.small_config(n_cells=700, n_nets=800, die=150.0, nx=nx, ny=ny, nz=nz,
                              macros=("uniform", 4, 0.01, 0.04), degree=("geo", 0.75, 70))
     return synth.make_case(config=cfg, seed=seed)
 

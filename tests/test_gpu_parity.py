@@ -28,6 +28,7 @@ CASES = {
     "tiny": lambda: tiny_case(5),
     "ragged": lambda: ragged_case(6),
     "ragged_even": lambda: ragged_case(7, nx=38, ny=30),
+    "multi_tile": lambda: ragged_case(13, nx=280, ny=264, nz=4),
     "wide_nets": lambda: wide_net_case(8),
     "one_die": lambda: one_die_case(9),
     "no_nets": lambda: no_net_case(10),
