@@ -174,7 +174,7 @@ __device__ __forceinline__ size_t bin_index(const Geom& g, int bz, int by, int b
 template <int NQ>
 __device__ __forceinline__ void block_partials(float (&v)[NQ], double* __restrict__ part, int stride, int slot0,
                                                int idx) {
-  __shared__ double sh[NQ][256 / kWave];
+  __shared__ double sh[NQ][1024 / kWave];
   __syncthreads();
   for (int q = 0; q < NQ; ++q) {
     double x = v[q];
@@ -390,6 +390,10 @@ __device__ __forceinline__ int large_hits(const float4* __restrict__ rec, int nl
 
 struct TileBox { int x0, y0, wx, wy; };
 
+// threads of a tile workgroup (density map, field gather, adjoint): eight wavefronts, so that the
+// gathers of a tile's entries have more loads in flight than the LDS-bound occupancy allows
+constexpr int kTileThreads = 512;
+
 __device__ __forceinline__ TileBox tile_box(const Geom& g, const TileGeom& t, int tile) {
   TileBox b;
   const int tx = tile % t.ntx, ty = tile / t.ntx;
@@ -418,7 +422,7 @@ __device__ __forceinline__ unsigned long long to_fix_unit(float v) {   // 0 <= v
 // x bins of a bucketed entry whose overlap lengths are held in registers
 constexpr int kSpanX = 4;
 
-__global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+__global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
                                                        const float* __restrict__ fixed_map,
                                                        const float4* __restrict__ lrec, int nlarge, float target,
@@ -433,8 +437,8 @@ __global__ __launch_bounds__(256) void k_density_tiles(Geom g, TileGeom t, const
   }
   __syncthreads();
   // large instances: bin-parallel sweep of their part of this tile
-  __shared__ int hits[256];
-  __shared__ int wave_cnt[256 / kWave];
+  __shared__ int hits[kTileThreads];
+  __shared__ int wave_cnt[kTileThreads / kWave];
   const float inv_vol = 1.f / g.vol_bin;
   for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
     const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
@@ -569,16 +573,16 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
 // sign (E - O), with E at column x and O at column hx + x of the stored map.
 struct FoldX { int on, hx; float sx, sy, sz; };
 
-__global__ __launch_bounds__(256) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+__global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                       const int32_t* __restrict__ tile_start,
                                                       const float* __restrict__ mx, const float* __restrict__ my,
                                                       const float* __restrict__ mz, FoldX fx, float4* __restrict__ out,
                                                       const float4* __restrict__ lrec, int nlarge,
                                                       float4* __restrict__ lpart) {
   extern __shared__ float S[];
-  __shared__ int hits[256];
-  __shared__ int wave_cnt[256 / kWave];
-  __shared__ float rsh[3][256 / kWave];
+  __shared__ int hits[kTileThreads];
+  __shared__ int wave_cnt[kTileThreads / kWave];
+  __shared__ float rsh[3][kTileThreads / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
@@ -798,15 +802,15 @@ __device__ __forceinline__ float3 adjoint_finish(const Geom& g, const Foot& f, c
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_adjoint_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+__global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
                                                        const float* __restrict__ m, float4* __restrict__ out,
                                                        const float4* __restrict__ lrec, int nlarge,
                                                        float4* __restrict__ lpart) {
   extern __shared__ float S[];
-  __shared__ int hits[256];
-  __shared__ int wave_cnt[256 / kWave];
-  __shared__ float rsh[6][256 / kWave];
+  __shared__ int hits[kTileThreads];
+  __shared__ int wave_cnt[kTileThreads / kWave];
+  __shared__ float rsh[6][kTileThreads / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
@@ -1005,7 +1009,7 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
   const place3d_problem& p = c->prob;
   {
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
-    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(256), 2 * tile_lds(c, 1), s, g, t, c->bk_entries,
+    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), 2 * tile_lds(c, 1), s, g, t, c->bk_entries,
                        c->bk_tile_start, c->fixed_map, c->large_rec, c->n_large, (float)p.target_density, rho,
                        c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
@@ -1029,7 +1033,7 @@ int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const flo
   if (xfold && !tiled) return set_err(c, PLACE3D_ERR_ARG, "x-folded field maps need the tiled large-instance path");
   // Ex comes from the sine basis (unfold sign -1), Ey and Ez from the cosine basis (+1)
   const FoldX fx{xfold ? 1 : 0, g.nx / 2, -1.f, 1.f, 1.f};
-  hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 3), s, g, t, c->bk_entries,
+  hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(kTileThreads), tile_lds(c, 3), s, g, t, c->bk_entries,
                      c->bk_tile_start, ex, ey, ez, fx, c->entry_out, c->large_rec, c->n_large,
                      tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_gather_tiles");
@@ -1057,7 +1061,7 @@ int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float 
   const place3d_problem& p = c->prob;
   const bool tiled = large_in_tiles(c);
   ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
-  hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles), dim3(256), tile_lds(c, 1), s, g, t, c->bk_entries,
+  hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles), dim3(kTileThreads), tile_lds(c, 1), s, g, t, c->bk_entries,
                      c->bk_tile_start, gmap, c->entry_out, c->large_rec, c->n_large,
                      tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_adjoint_tiles");
