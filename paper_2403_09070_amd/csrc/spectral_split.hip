@@ -144,10 +144,18 @@ __device__ __forceinline__ void lds_load16(const uint16_t* src, unsigned short* 
   __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
 }
 
+// 1 / |omega|^2 by the hardware reciprocal (1 ulp, far below the split products' rounding); the
+// (0,0,0) mode is dropped
 __device__ __forceinline__ float inv_w2(const SArgs& g, int j, int k, int l) {
   const float wx = g.px * (float)j, wy = g.py * (float)k, wz = g.pz * (float)l;
   const float w2 = wx * wx + wy * wy + wz * wz;
-  return w2 > 0.f ? 1.f / w2 : 0.f;
+  return w2 > 0.f ? __builtin_amdgcn_rcpf(w2) : 0.f;
+}
+
+// the value of lane l ^ 32 (the other half of the wavefront), by one lane-half swap
+__device__ __forceinline__ float other_half(float v, bool upper) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(upper ? r[0] : r[1]);
 }
 
 __device__ __forceinline__ int xfreq(int pos, int h) { return pos < h ? 2 * pos : 2 * (pos - h) + 1; }
@@ -283,7 +291,7 @@ __global__ __launch_bounds__(256) void k_sgemm(SArgs g) {
         float v[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float own = acc[0][a][b][r], oth = __shfl_xor(own, 32);
+          const float own = acc[0][a][b][r], oth = other_half(own, upper);
           const float sv = upper ? oth - own : own + oth;
           v[r] = yk + 16 * a + r < g.hy ? sv : 0.f;
         }
