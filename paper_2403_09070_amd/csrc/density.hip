@@ -433,7 +433,9 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   const int tsz = t.T * t.T * g.nz;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    S64[k] = (lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)]) : 0ull;
+    // fixed_map is null when the problem has no fixed instances (the map is then all zero)
+    S64[k] = (fixed_map && lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)])
+                                                      : 0ull;
   }
   __syncthreads();
   // large instances: bin-parallel sweep of their part of this tile
@@ -1010,7 +1012,8 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
   {
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
     hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), 2 * tile_lds(c, 1), s, g, t, c->bk_entries,
-                       c->bk_tile_start, c->fixed_map, c->large_rec, c->n_large, (float)p.target_density, rho,
+                       c->bk_tile_start, c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec, c->n_large,
+                       (float)p.target_density, rho,
                        c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
   }
