@@ -269,7 +269,8 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   if ((rc = bucket_cells(c, xyz, s, 2))) return rc;
   if ((rc = density_tiles(c, xyz, c->rho, red, s, !defer_excess))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
-    // the field stays x-folded for the gather, which unfolds it while staging its tiles
+    // the float32 form's field stays x-folded for the gather, which unfolds it while staging its
+    // tiles (the split-bf16 chain returns it unfolded)
     if ((rc = spectral_field(c, c->rho, nullptr, c->ex, c->ey, c->ez, nullptr, s, large_in_tiles(c)))) return rc;
     if ((rc = gather_bucketed(c, xyz, c->ex, c->ey, c->ez, -1.f, gd, 0, s, !cells_in_combine, c->field_xfold != 0)))
       return rc;
