@@ -78,7 +78,7 @@ struct SplitChain {
   HL gx, hx_s;           // inverse x: [hx][2 rx], row = x, k = even then odd frequencies
   HL xs[2];              // x-folded map (sum, difference): [Nz Ny][rx]
   HL ys[2];              // y-folded x spectra (sum, difference): [Nz Nx][ry], row = (z, x frequency)
-  HL bb;                 // potential coefficients: [Nz Nx][2 ry], row = (z frequency, x frequency)
+  HL bb;                 // potential coefficients: [Nx Nz][2 ry], row = x frequency * Nz + z frequency
   HL vg, vh;             // inverse-y results (cosine, sine basis): [Nz Ny][2 rx], row = (z frequency, y)
 };
 
