@@ -10,6 +10,8 @@ import numpy as np
 
 KIND_MACRO = 1
 KIND_FIXED = 2
+KIND_FILLER = 4     # dummy filler: no pins, left out of the overflow (Sec. III-A)
+KIND_ZFIXED = 8     # z held: the z-gradient is zero (z-fixed fillers, Sec. III-A)
 
 
 def partition(z, dz):
@@ -23,6 +25,14 @@ def is_macro(kind):
 
 def is_fixed(kind):
     return (np.asarray(kind) & KIND_FIXED) != 0
+
+
+def is_filler(kind):
+    return (np.asarray(kind) & KIND_FILLER) != 0
+
+
+def is_zfixed(kind):
+    return (np.asarray(kind) & KIND_ZFIXED) != 0
 
 
 def instance_size(size, kind, z, dz):

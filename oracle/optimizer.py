@@ -18,7 +18,10 @@
   instance, at the size its clamped z gives, stays inside the die.  Fixed instances never move.
 * Overflow per die (reading; the paper prints overflow without defining it): the ePlace form
   sum_{b in die} max(rho_b - rho_t, 0) vol(b) / sum_{movable i on die} q_i, the bottom die being
-  the lower half of the z-bins.
+  the lower half of the z-bins.  Fillers (Sec. III-A) are left out of both: the excess is taken
+  on the map of the other instances and the charge sums over movable non-fillers.
+* z-held instances (the z-fixed fillers of Sec. III-A): their z-gradient is set to zero in both
+  objective parts before anything else uses them (lambda_0, preconditioning, the step).
 """
 from __future__ import annotations
 
@@ -28,7 +31,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import poisson
-from .attributes import charge, instance_size, is_fixed, is_macro, partition
+from .attributes import charge, instance_size, is_filler, is_fixed, is_macro, is_zfixed, partition
 from .density import density_map
 from .density_grad import density_vjp, field_gather
 from .geometry import Geometry, geometry_of, hbt_alpha
@@ -106,14 +109,18 @@ def density_gradient(pb: Problem, xyz, dgrad="field"):
 
 
 def overflow(pb: Problem, rho, xyz):
-    """Per-die overflow (bottom, top)."""
+    """Per-die overflow (bottom, top); with fillers, of the map without them."""
     geo = pb.geo
+    fill = is_filler(pb.kind)
+    if fill.any():
+        real = ~fill
+        rho = density_map(pb.size[:, real], pb.kind[real], np.asarray(xyz)[:, real], geo)
     excess = np.maximum(np.asarray(rho) - pb.target, 0.0) * geo.vol_bin
     half = geo.nz // 2
     w, h = instance_size(pb.size, pb.kind, np.asarray(xyz, dtype=np.float64)[2], geo.dz)
     q = charge(w, h, geo.dz)
     top = partition(np.asarray(xyz, dtype=np.float64)[2], geo.dz)
-    mov = pb.movable
+    mov = pb.movable & ~fill
     q_bot = float(q[mov & ~top].sum())
     q_top = float(q[mov & top].sum())
     o_bot = float(excess[:half].sum()) / q_bot if q_bot > 0 else 0.0
@@ -122,10 +129,18 @@ def overflow(pb: Problem, rho, xyz):
 
 
 def evaluate(pb: Problem, xyz, dgrad="field"):
-    """Wirelength and density parts of the objective gradient at xyz (unscaled by lambda)."""
+    """Wirelength and density parts of the objective gradient at xyz (unscaled by lambda), with
+    the z components of z-held instances set to zero."""
     wl = wirelength(pb.size, pb.kind, xyz, pb.net_start, pb.pin2node, pb.pin_off, pb.geo,
                     pb.gamma, pb.alpha)
     rho, sol, gd = density_gradient(pb, xyz, dgrad)
+    held = is_zfixed(pb.kind)
+    if held.any():
+        wl = dict(wl)
+        wl["grad"] = np.array(wl["grad"], dtype=np.float64)
+        wl["grad"][2, held] = 0.0
+        gd = np.array(gd, dtype=np.float64)
+        gd[2, held] = 0.0
     return wl, rho, sol, gd
 
 

@@ -5,7 +5,7 @@ the initial placement.  It holds none of the placement method's arithmetic, so t
 HIP path can both read its output.  Every array uses the layouts the C ABI takes:
 
 * ``size``    float32 [4][n]  (w_bot, h_bot, w_top, h_top), instance extents on each die
-* ``kind``    uint8   [n]     bit 0 = macro, bit 1 = fixed
+* ``kind``    uint8   [n]     bit 0 = macro, bit 1 = fixed, bit 2 = filler, bit 3 = z held
 * ``net_start`` int32 [m+1]   net -> pin CSR, pins sorted by net
 * ``pin2node``  int32 [P]     owning instance of each pin
 * ``pin_off``   float32 [4][P] (ox_bot, oy_bot, ox_top, oy_top), pin offset from the instance centre
@@ -26,6 +26,8 @@ KIND_CELL = 0
 KIND_MACRO = 1
 KIND_FIXED = 2
 KIND_FIXED_MACRO = KIND_MACRO | KIND_FIXED
+KIND_FILLER = 4          # dummy filler (no pins)
+KIND_ZFIXED = 8          # z held at its start
 
 TOP_SCALE = 0.7          # top-die size and pin-offset scale
 WINDOW = 256             # index half-window of a local net
@@ -245,3 +247,49 @@ def small_config(n_cells=300, n_nets=330, die=100.0, nx=16, ny=16, nz=2, macros=
                  degree=("geo", 0.6, 8), name="tiny") -> Config:
     """A tiny configuration for brute-force and finite-difference tests."""
     return Config(name, n_cells, n_nets, die, nx, ny, nz, degree, macros)
+
+
+def centre_start(case: Case, sigma: float = 0.02, seed: int = 1) -> Case:
+    """The case with its movable instances re-drawn around the centre of the region: x and y
+    normal with standard deviation sigma times the die side, z normal around the mid-plane with
+    standard deviation 0.05 d_z (the usual start of a global placement from scratch)."""
+    import dataclasses
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
+    xyz = case.xyz0.astype(np.float64).copy()
+    mov = (case.kind & KIND_FIXED) == 0
+    k = int(mov.sum())
+    xyz[0, mov] = case.die_x * (0.5 + sigma * rng.standard_normal(k))
+    xyz[1, mov] = case.die_y * (0.5 + sigma * rng.standard_normal(k))
+    xyz[2, mov] = dz * (0.5 + 0.05 * rng.standard_normal(k))
+    return dataclasses.replace(case, xyz0=xyz.astype(np.float32))
+
+
+def with_fillers(case: Case, plan: dict, sigma: float = 0.02, seed: int = 2) -> Case:
+    """The case with fillers appended after its instances, as a filler plan describes them
+    (counts n_top, n_bot, n_free and square sides side_top, side_bot, side_free): z-fixed top
+    fillers at z = 3 d_z/4, z-fixed bottom fillers at z = d_z/4, free fillers around the
+    mid-plane; x and y of all of them normal around the centre (sigma times the die side).
+    Fillers have no pins; the netlist is unchanged."""
+    import dataclasses
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
+    groups = [(int(plan["n_top"]), float(plan["side_top"]), KIND_FILLER | KIND_ZFIXED, 0.75),
+              (int(plan["n_bot"]), float(plan["side_bot"]), KIND_FILLER | KIND_ZFIXED, 0.25),
+              (int(plan["n_free"]), float(plan["side_free"]), KIND_FILLER, None)]
+    sizes, kinds, xyzs = [case.size.astype(np.float64)], [case.kind], [case.xyz0.astype(np.float64)]
+    for k, side, kd, zf in groups:
+        if k <= 0:
+            continue
+        sizes.append(np.full((4, k), side))
+        kinds.append(np.full(k, kd, dtype=np.uint8))
+        xyz = np.empty((3, k))
+        xyz[0] = case.die_x * (0.5 + sigma * rng.standard_normal(k))
+        xyz[1] = case.die_y * (0.5 + sigma * rng.standard_normal(k))
+        xyz[2] = zf * dz if zf is not None else dz * (0.5 + 0.05 * rng.standard_normal(k))
+        xyzs.append(xyz)
+    meta = dict(case.meta)
+    meta.update(n_fillers=sum(max(g[0], 0) for g in groups), filler_plan=dict(plan))
+    return dataclasses.replace(case, size=np.concatenate(sizes, axis=1).astype(np.float32),
+                               kind=np.concatenate(kinds), xyz0=np.concatenate(xyzs, axis=1).astype(np.float32),
+                               meta=meta)

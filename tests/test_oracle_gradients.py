@@ -113,6 +113,28 @@ def test_preconditioner_follows_mixed_size_rule():
         np.testing.assert_allclose(H[~mac], np.maximum(1.0, lam * q[~mac]))
 
 
+def test_preconditioner_forms_against_net_counts():
+    """Eq. general-precond and its two approximations: the ePlace form minus the ePlace3D form is
+    |E_i|, the number of nets incident to instance i (counted here by a plain loop over the nets);
+    the mixed form is max{1, ePlace} on macros and max{1, ePlace3D} elsewhere."""
+    c = _case(2)
+    pb = opt.problem_of(c)
+    v = c.xyz0.astype(np.float64)
+    count = np.zeros(c.n_inst)
+    for e in range(c.n_nets):
+        for i in set(int(x) for x in c.pin2node[c.net_start[e]:c.net_start[e + 1]]):
+            count[i] += 1
+    mac = (c.kind & 1) != 0
+    for lam in (1e-6, 0.3, 10.0):
+        he = opt.preconditioner(pb, v, lam, "eplace")
+        h3 = opt.preconditioner(pb, v, lam, "eplace3d")
+        hm = opt.preconditioner(pb, v, lam, "mixed")
+        np.testing.assert_allclose(he - h3, count, atol=1e-9 * max(1.0, np.abs(he).max()))
+        np.testing.assert_allclose(h3 / lam, opt.preconditioner(pb, v, 1.0, "eplace3d"), rtol=1e-12)
+        np.testing.assert_allclose(hm[mac], np.maximum(1.0, he[mac]))
+        np.testing.assert_allclose(hm[~mac], np.maximum(1.0, h3[~mac]))
+
+
 def test_nesterov_converges_on_a_convex_quadratic():
     """With the objective replaced by 1/2 |v - v*|^2 the iterates converge to v*."""
     rng = np.random.default_rng(0)
