@@ -14,6 +14,10 @@ form's rate, both final D2D HPWLs and their relative difference are reported bes
 The roofline entry is for the kernel with the largest GPU time in the mixed step, from per-launch
 HIP events recorded on the launch stream during a profiled block of steps right after the timed
 block.  The CPU baseline is the FP64 oracle on a bounded sample of the same workload.
+
+``--ablation precond`` runs the preconditioner ablation instead (one JSON line, curves to
+``--ablation-csv``): the mixed-size preconditioner against the ePlace and ePlace3D forms on the
+macro-heavy 200k-cell workload from a clustered start.
 """
 from __future__ import annotations
 
@@ -152,12 +156,106 @@ def cpu_baseline(case, frac=4):
             "seconds_per_iteration": per_iter}
 
 
+def precond_ablation(args, log):
+    """Eq. improved-precond against the ePlace (|E_i| + lambda q_i) and ePlace3D (lambda q_i) forms of
+    Eq. general-precond (Sec. III-C3 and the preconditioner ablation of Sec. V): the same macro-heavy
+    netlist is placed from the same clustered start with each form, recording per iteration the D2D
+    HPWL and per-die overflow, and every --ablation-every iterations the macro density overflow,
+    i.e. the overflow of the map of the macros alone against the target density."""
+    import numpy as np
+    import torch
+    from paper_2403_09070_amd import place3d, synth
+    case = synth.make_case(args.config, args.seed)
+    rng = np.random.default_rng(args.seed + 1)
+    n, nc = case.n_inst, case.meta["n_cells"]
+    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
+    start = case.xyz0.astype(np.float64).copy()
+    mov = (case.kind & place3d.KIND_FIXED) == 0
+    sig = args.ablation_spread
+    start[0, mov] = case.die_x * (0.5 + sig * rng.standard_normal(int(mov.sum())))
+    start[1, mov] = case.die_y * (0.5 + sig * rng.standard_normal(int(mov.sum())))
+    start[2, mov] = dz * (0.5 + 0.05 * rng.standard_normal(int(mov.sum())))
+    start = start.astype(np.float32)
+    mac = np.nonzero((case.kind & place3d.KIND_MACRO) != 0)[0]
+    base = place3d.Problem.from_case(case)
+    mprob = place3d.Problem(size=case.size[:, mac], kind=case.kind[mac], net_start=np.zeros(1, np.int32),
+                            pin2node=np.zeros(0, np.int32), pin_off=np.zeros((4, 0), np.float32),
+                            fixed_xyz=case.xyz0[:, mac], die_x=case.die_x, die_y=case.die_y,
+                            nx=case.nx, ny=case.ny, nz=case.nz, **{k: base.params[k] for k in ("gamma", "alpha")},
+                            target_density=base.params["target_density"])
+    del base
+    mac_t = torch.as_tensor(mac, device="cuda", dtype=torch.long)
+    target = mprob.params["target_density"]
+    half = case.nz // 2
+
+    def macro_overflow(v):
+        rho = mprob.density(v.index_select(1, mac_t))
+        ex = (rho - target).clamp(min=0.0)
+        return [float(x) for x in torch.stack([ex[:half].sum() / rho[:half].sum().clamp(min=1e-30),
+                                               ex[half:].sum() / rho[half:].sum().clamp(min=1e-30),
+                                               ex.sum() / rho.sum()]).cpu()]
+
+    forms = {"mixed": place3d.PRECOND_MIXED, "eplace": place3d.PRECOND_EPLACE,
+             "eplace3d": place3d.PRECOND_EPLACE3D}
+    rows, summary = [], {}
+    for name, code in forms.items():
+        prob = place3d.Problem.from_case(case, precision=place3d.BF16X3, precond=code)
+        st = prob.gp_init(start)
+        h0 = None
+        stop_at, diverged, mo_after = None, False, []
+        t0 = time.perf_counter()
+        for k in range(args.ablation_iters):
+            prob.step(st)
+            s = st.read()
+            mo = macro_overflow(st.v) if (k % args.ablation_every == 0 or k == args.ablation_iters - 1) else None
+            h0 = s["hpwl"] if h0 is None else h0
+            ov = max(s["ovfl_bot"], s["ovfl_top"])
+            rows.append((name, k, s["hpwl"], s["ovfl_bot"], s["ovfl_top"], s["lam"], s["step"], s["ncut"],
+                         *(mo if mo else (float("nan"),) * 3)))
+            if mo and k >= args.ablation_iters // 4:
+                mo_after.append(mo[2])
+            if stop_at is None and ov < args.ablation_stop:
+                stop_at = dict(iteration=k, hpwl=s["hpwl"], ovfl=ov, ncut=s["ncut"],
+                               macro_ovfl=macro_overflow(st.v)[2])
+            if not np.isfinite(s["hpwl"]) or s["hpwl"] > 20.0 * h0:
+                diverged = True
+                break
+            if (k + 1) % 200 == 0:
+                log(f"  {name} it {k + 1}: hpwl {s['hpwl']:.5e} ovfl {s['ovfl_bot']:.3f}/{s['ovfl_top']:.3f} "
+                    f"macro {mo_after[-1] if mo_after else float('nan'):.4f}")
+        torch.cuda.synchronize()
+        s = st.read()
+        mo = macro_overflow(st.v)
+        summary[name] = dict(iterations=k + 1, diverged=diverged, final_hpwl=s["hpwl"],
+                             final_ovfl=[s["ovfl_bot"], s["ovfl_top"]], final_macro_ovfl=mo[2],
+                             reached=stop_at, macro_ovfl_late_max=max(mo_after) if mo_after else None,
+                             macro_ovfl_late_mean=float(np.mean(mo_after)) if mo_after else None,
+                             seconds=round(time.perf_counter() - t0, 2))
+        log(f"[ablation] {name}: {summary[name]}")
+        del prob
+        torch.cuda.empty_cache()
+    if args.ablation_csv:
+        os.makedirs(os.path.dirname(os.path.abspath(args.ablation_csv)), exist_ok=True)
+        with open(args.ablation_csv, "w") as f:
+            f.write("precond,iteration,hpwl,ovfl_bot,ovfl_top,lambda,step,ncut,macro_ovfl_bot,macro_ovfl_top,"
+                    "macro_ovfl\n")
+            for r in rows:
+                f.write(",".join(str(x) for x in r) + "\n")
+    ref = summary["mixed"]
+    for name in ("eplace", "eplace3d"):
+        a, b = summary[name].get("reached"), ref.get("reached")
+        summary[name]["hpwl_vs_mixed_at_stop"] = (a["hpwl"] / b["hpwl"]) if a and b else None
+    print(json.dumps({"ablation": "preconditioner", "workload": f"{args.config} seed {args.seed}, "
+                      f"{nc} cells + {len(mac)} macros, clustered start (sigma {sig} of the die)",
+                      "stop_overflow": args.ablation_stop, "forms": summary}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c4")
+    ap.add_argument("--config", default=None, help="workload (default c4; c2 for --ablation)")
     ap.add_argument("--seed", type=int, default=2403)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -165,6 +263,13 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
+    ap.add_argument("--ablation", choices=["precond"], default=None,
+                    help="run the preconditioner ablation instead of the timing benchmark")
+    ap.add_argument("--ablation-iters", type=int, default=1000)
+    ap.add_argument("--ablation-every", type=int, default=5)
+    ap.add_argument("--ablation-spread", type=float, default=0.02)
+    ap.add_argument("--ablation-stop", type=float, default=0.1)
+    ap.add_argument("--ablation-csv", default=None)
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     if args.gpus != 1:
@@ -175,6 +280,11 @@ def main():
     from paper_2403_09070_amd import place3d, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     place3d.lib()
+    if args.ablation:
+        args.config = args.config or "c2"
+        precond_ablation(args, log)
+        return
+    args.config = args.config or "c4"
     if args.copy_mb > 0:
         src = torch.ones(args.copy_mb * (1 << 18), dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -78,8 +78,14 @@ enum { PLACE3D_PRECOND_MIXED = 0,     /* max{1,|E_i|+lambda q_i} macros, max{1,l
        PLACE3D_PRECOND_EPLACE = 1,    /* |E_i| + lambda q_i                                   */
        PLACE3D_PRECOND_EPLACE3D = 2 };/* lambda q_i                                           */
 
-/* Instance kind bits (uint8 per instance). */
-enum { PLACE3D_KIND_MACRO = 1, PLACE3D_KIND_FIXED = 2 };
+/* Instance kind bits (uint8 per instance).
+ * FILLER: a dummy filler (density model, Sec. III-A): a movable, cell-sized instance with no pins
+ *   that takes part in the density map and moves with the density force, but is left out of the
+ *   overflow (its excess and its charge).  It may not also be a macro or fixed, carry a pin, or
+ *   be wider than a density tile (create returns PLACE3D_ERR_ARG / PLACE3D_ERR_NETLIST).
+ * ZFIXED: the instance's z is held: its z-gradient is zero in both objective parts before
+ *   anything uses them (the z-fixed fillers of Sec. III-A; allowed on any movable instance). */
+enum { PLACE3D_KIND_MACRO = 1, PLACE3D_KIND_FIXED = 2, PLACE3D_KIND_FILLER = 4, PLACE3D_KIND_ZFIXED = 8 };
 
 /* Layout of the float64 wirelength metrics written by place3d_wl_grad (device, 16 slots). */
 enum {
@@ -220,6 +226,28 @@ PLACE3D_API int32_t place3d_gp_init(place3d_ctx* ctx, place3d_state* state, cons
  * step, Nesterov move, clamp, lambda *= lambda_ramp; metrics of the evaluation point go to
  * state->scalars. */
 PLACE3D_API int32_t place3d_step(place3d_ctx* ctx, place3d_state* state, void* stream);
+
+/* Filler plan (density model, Sec. III-A, Eqs. filler-vol and free-filler-vol): how many fillers
+ * of which square footprint fill the region, for the caller to append as instances (kind
+ * FILLER|ZFIXED for the z-fixed ones, at z = 3 d_z/4 on top and d_z/4 below; FILLER for the free
+ * ones).  vol_top = 1/2 d_x d_y d_z (1 - u_top), vol_bot = 1/2 d_x d_y d_z (1 - u_bot),
+ * vol_free = max{d_x d_y d_z - (vol_top + vol_bot + vol_a), 0}, vol_a = the volume of all
+ * instances at the size their z0 gives, d_z = nz (d_x/nx + d_y/ny)/2.  Footprints (the paper
+ * gives none): the z-fixed fillers of a die take the mean footprint area of the movable standard
+ * cells (kind 0) at that die's size, the free fillers the mean of the two areas; a count is the
+ * volume over one filler's volume (area x d_z/2) rounded to nearest, halves up.
+ * Host-only arithmetic on HOST arrays: size float32 [4][n_inst] (the problem's layout), kind uint8
+ * [n_inst], z0 float32 [n_inst].  Errors: PLACE3D_ERR_ARG for a null pointer, u outside [0, 1] or
+ * no movable standard cell; PLACE3D_ERR_SIZE for a bad count or grid. */
+typedef struct place3d_filler_plan {
+  int64_t n_top, n_bot, n_free;            /* z-fixed top, z-fixed bottom and free filler counts */
+  double side_top, side_bot, side_free;    /* square footprint sides                            */
+  double vol_top, vol_bot, vol_free, vol_a;
+} place3d_filler_plan;
+
+PLACE3D_API int32_t place3d_plan_fillers(int32_t n_inst, const float* size, const uint8_t* kind, const float* z0,
+                                         double die_x, double die_y, int32_t nx, int32_t ny, int32_t nz,
+                                         double u_top, double u_bot, place3d_filler_plan* out);
 
 /* Profiling.  With `on` != 0, every later kernel launch of `ctx` is bracketed by a pair of HIP
  * events recorded on the launch stream; place3d_profile_read waits for the recorded events and

@@ -270,17 +270,30 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   // density classes: bucketed cells must span at most two tiles per axis on either die
   std::vector<int32_t> large, fixed;
   std::vector<uint8_t> cls(n);
+  int32_t n_fill = 0;
   {
     const double wb = p.die_x / p.nx, hb = p.die_y / p.ny;
     const double wlim = (c->tg.T - 1) * wb, hlim = (c->tg.T - 1) * hb;
     for (int i = 0; i < n; ++i) {
+      const bool filler = (kind[i] & PLACE3D_KIND_FILLER) != 0;
+      if (filler && (kind[i] & (PLACE3D_KIND_MACRO | PLACE3D_KIND_FIXED)))
+        return set_err(c, PLACE3D_ERR_ARG, "filler " + std::to_string(i) + " is also a macro or fixed");
+      if (filler && nss[i + 1] > nss[i])
+        return set_err(c, PLACE3D_ERR_NETLIST, "filler " + std::to_string(i) + " has a pin");
+      n_fill += filler;
       if (kind[i] & PLACE3D_KIND_FIXED) { cls[i] = p3d::kClsFixed; fixed.push_back(i); continue; }
       const double w = std::max(size[i], size[2 * (size_t)n + i]);
       const double h = std::max(size[(size_t)n + i], size[3 * (size_t)n + i]);
-      if ((kind[i] & PLACE3D_KIND_MACRO) || w > wlim || h > hlim) { cls[i] = p3d::kClsLarge; large.push_back(i); }
-      else cls[i] = p3d::kClsCell;
+      if ((kind[i] & PLACE3D_KIND_MACRO) || w > wlim || h > hlim) {
+        if (filler) return set_err(c, PLACE3D_ERR_ARG, "filler " + std::to_string(i) + " is wider than a density tile");
+        cls[i] = p3d::kClsLarge;
+        large.push_back(i);
+      } else {
+        cls[i] = p3d::kClsCell;
+      }
     }
   }
+  c->n_fillers = n_fill;
   c->n_large = (int32_t)large.size();
   c->n_fixed = (int32_t)fixed.size();
   P3D_HIP(c, hipMemcpyAsync(c->cls, cls.data(), n, hipMemcpyHostToDevice, s));
@@ -484,6 +497,62 @@ int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, dou
   if (metrics && (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned metrics");
   return p3d::wirelength_eval(ctx, xyz, grad_xyz, accumulate != 0, ctx->red, metrics,
                               reinterpret_cast<hipStream_t>(stream));
+}
+
+PLACE3D_API int32_t place3d_plan_fillers(int32_t n_inst, const float* size, const uint8_t* kind, const float* z0,
+                                         double die_x, double die_y, int32_t nx, int32_t ny, int32_t nz,
+                                         double u_top, double u_bot, place3d_filler_plan* out) {
+  if (!size || !kind || !z0 || !out) return PLACE3D_ERR_ARG;
+  if (n_inst < 1 || nx < 2 || ny < 2 || nz < 2 || (nz & 1)) return PLACE3D_ERR_SIZE;
+  if (!(die_x > 0) || !(die_y > 0) || !std::isfinite(die_x) || !std::isfinite(die_y)) return PLACE3D_ERR_ARG;
+  if (!(u_top >= 0 && u_top <= 1) || !(u_bot >= 0 && u_bot <= 1)) return PLACE3D_ERR_ARG;
+  const size_t n = (size_t)n_inst;
+  const double dz = nz * 0.5 * (die_x / nx + die_y / ny);
+  // mean footprint area of the movable standard cells on each die's size
+  double a_bot = 0.0, a_top = 0.0;
+  long long cells = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (kind[i] & (PLACE3D_KIND_MACRO | PLACE3D_KIND_FIXED | PLACE3D_KIND_FILLER)) continue;
+    a_bot += (double)size[i] * (double)size[n + i];
+    a_top += (double)size[2 * n + i] * (double)size[3 * n + i];
+    ++cells;
+  }
+  if (cells == 0) return PLACE3D_ERR_ARG;
+  a_bot /= (double)cells;
+  a_top /= (double)cells;
+  const double a_free = 0.5 * (a_top + a_bot);
+  // vol_a: every instance at the size its initial z gives (cells by partition, macros by the
+  // linear transition over the clamped z)
+  double vol_a = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    const double wb = size[i], hb = size[n + i], wt = size[2 * n + i], ht = size[3 * n + i];
+    const double z = z0[i];
+    double w, h;
+    if (kind[i] & PLACE3D_KIND_MACRO) {
+      const double zc = std::min(std::max(z, 0.25 * dz), 0.75 * dz);
+      const double t = 2.0 * zc / dz;
+      w = (t - 0.5) * wt + (1.5 - t) * wb;
+      h = (t - 0.5) * ht + (1.5 - t) * hb;
+    } else {
+      const bool top = z > 0.5 * dz;
+      w = top ? wt : wb;
+      h = top ? ht : hb;
+    }
+    vol_a += w * h * 0.5 * dz;
+  }
+  const double total = die_x * die_y * dz;
+  out->vol_top = 0.5 * total * (1.0 - u_top);
+  out->vol_bot = 0.5 * total * (1.0 - u_bot);
+  out->vol_free = std::max(total - (out->vol_top + out->vol_bot + vol_a), 0.0);
+  out->vol_a = vol_a;
+  out->side_top = std::sqrt(a_top);
+  out->side_bot = std::sqrt(a_bot);
+  out->side_free = std::sqrt(a_free);
+  auto count = [&](double vol, double area) { return (int64_t)std::floor(vol / (area * 0.5 * dz) + 0.5); };
+  out->n_top = count(out->vol_top, a_top);
+  out->n_bot = count(out->vol_bot, a_bot);
+  out->n_free = count(out->vol_free, a_free);
+  return PLACE3D_OK;
 }
 
 }  // extern "C"

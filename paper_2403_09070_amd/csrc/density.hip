@@ -106,7 +106,7 @@ __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict
   return f;
 }
 
-// bucket entry: (cbx | cby << 16, rx, ry, z), (hw, hh, omega, 0)
+// bucket entry: (cbx | cby << 16, rx, ry, z), (hw, hh, omega, 1 for a filler else 0)
 __device__ __forceinline__ Foot foot_entry(const Geom& g, float4 a, float4 b) {
   Foot f;
   const unsigned packed = __float_as_uint(a.x);
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileG
       const int tx0 = packed & 0xFFF, ty0 = (packed >> 12) & 0xFFF;
       const int tx1 = tx0 + ((packed >> 24) & 1), ty1 = ty0 + ((packed >> 25) & 1);
       const float4 ea = make_float4(__uint_as_float((unsigned)f.cbx | ((unsigned)f.cby << 16)), f.rx, f.ry, f.z);
-      const float4 eb = make_float4(f.hw, f.hh, f.omega, 0.f);
+      const float4 eb = make_float4(f.hw, f.hh, f.omega, (kind[i] & PLACE3D_KIND_FILLER) ? 1.f : 0.f);
       int q = 0;
       for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
@@ -426,16 +426,21 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
                                                        const int32_t* __restrict__ tile_start,
                                                        const float* __restrict__ fixed_map,
                                                        const float4* __restrict__ lrec, int nlarge, float target,
-                                                       float* __restrict__ rho, double* __restrict__ part, int stride) {
+                                                       int fillers, float* __restrict__ rho,
+                                                       double* __restrict__ part, int stride) {
   extern __shared__ unsigned long long S64[];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
+  // with fillers, their share accumulates apart (SF) so that the overflow can leave them out;
+  // the map written is the sum of both (exact: integer fixed point)
+  unsigned long long* SF = fillers ? S64 + tsz : S64;
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     // fixed_map is null when the problem has no fixed instances (the map is then all zero)
     S64[k] = (fixed_map && lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)])
                                                       : 0ull;
+    if (fillers) SF[k] = 0ull;
   }
   __syncthreads();
   // large instances: bin-parallel sweep of their part of this tile
@@ -462,7 +467,9 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   // bucketed cells
   const int e1 = tile_start[tile + 1];
   for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+    const Foot f = foot_entry(g, ea, eb);
+    unsigned long long* acc = eb.w != 0.f ? SF : S64;
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     const float wgt = f.omega * inv_vol;
@@ -475,7 +482,7 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
         const float lz = len_z(g, f, bz) * wgt;
         for (int by = by0; by <= by1; ++by) {
           const float lyz = len_y(g, f, by) * lz;
-          unsigned long long* row = &S64[lds_index(t, bz, by - tb.y0, bx0 - tb.x0)];
+          unsigned long long* row = &acc[lds_index(t, bz, by - tb.y0, bx0 - tb.x0)];
 #pragma unroll
           for (int j = 0; j < kSpanX; ++j)
             if (j < nbx) atomicAdd(row + j, to_fix_unit(lxs[j] * lyz));
@@ -487,7 +494,7 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
         for (int by = by0; by <= by1; ++by) {
           const float lyz = len_y(g, f, by) * lz;
           for (int bx = bx0; bx <= bx1; ++bx)
-            atomicAdd(&S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix_unit(len_x(g, f, bx) * lyz));
+            atomicAdd(&acc[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix_unit(len_x(g, f, bx) * lyz));
         }
       }
     }
@@ -498,9 +505,11 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     if (lx < tb.wx && ly < tb.wy) {
-      const float v = (float)((double)S64[k] * kUnfix);
+      const unsigned long long real = S64[k];
+      const float v = (float)((double)(fillers ? real + SF[k] : real) * kUnfix);
+      const float vr = fillers ? (float)((double)real * kUnfix) : v;
       rho[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] = v;
-      ex[bz < half ? 0 : 1] += fmaxf(v - target, 0.f) * g.vol_bin;
+      ex[bz < half ? 0 : 1] += fmaxf(vr - target, 0.f) * g.vol_bin;
     }
   }
   block_partials<2>(ex, part, stride, R_EXCESS_BOT, tile);
@@ -1011,10 +1020,10 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
   const place3d_problem& p = c->prob;
   {
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
-    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), 2 * tile_lds(c, 1), s, g, t, c->bk_entries,
-                       c->bk_tile_start, c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec, c->n_large,
-                       (float)p.target_density, rho,
-                       c->part, c->part_stride);
+    const int fillers = c->n_fillers > 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), (2 + 2 * fillers) * tile_lds(c, 1), s, g,
+                       t, c->bk_entries, c->bk_tile_start, c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec,
+                       c->n_large, (float)p.target_density, fillers, rho, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
   }
   if (!reduce) return PLACE3D_OK;

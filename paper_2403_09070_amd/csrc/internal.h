@@ -122,6 +122,7 @@ struct place3d_ctx {
   long long lpart_cap = 0;
   int32_t* fixed_list = nullptr;       // fixed instances (their map is built once)
   int32_t n_fixed = 0;
+  int32_t n_fillers = 0;               // instances of kind FILLER (bucketed cells)
   // tiles and per-call buckets
   p3d::TileGeom tg = {};
   int32_t* bk_counts = nullptr;        // [ntiles][nblk] counts, then exclusive offsets

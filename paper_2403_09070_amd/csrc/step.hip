@@ -85,14 +85,16 @@ __global__ void k_clamp_copy(Geom g, const float* __restrict__ size, const uint8
   if (v) { v[i] = x; v[n + i] = y; v[2 * n + i] = z; }
 }
 
-// L1 norms of the wirelength and density gradients over movable instances -> lambda_0
+// L1 norms of the wirelength and density gradients over movable instances -> lambda_0 (the z
+// components of z-held instances count as zero)
 __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float* __restrict__ gw,
                            const float* __restrict__ gd, double* __restrict__ part, int stride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
   double v[2] = {0.0, 0.0};
   if (i < n && !(kind[i] & PLACE3D_KIND_FIXED)) {
-    for (int a = 0; a < 3; ++a) {
+    const int na = (kind[i] & PLACE3D_KIND_ZFIXED) ? 2 : 3;    // a held z has no gradient
+    for (int a = 0; a < na; ++a) {
       v[0] += fabs((double)gw[a * n + i]);
       v[1] += fabs((double)gd[a * n + i]);
     }
@@ -102,7 +104,7 @@ __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float
 
 // g = (gw + lambda gd) / H.  Mode 0 (init): write g to `gout` and track max|g|.  Mode 1 (step):
 // accumulate |v - v_prev|^2 and |g - g_prev|^2, store g over g_prev, and the movable charge
-// per die (overflow denominators).
+// per die without fillers (overflow denominators).  A z-held instance's z-gradient is zero.
 // Cell density gradients held as per-(cell, tile) shares (CellShares.entry != nullptr) are summed
 // here, in the order the separate combine pass uses, instead of being materialised first.
 struct CellShares {
@@ -153,6 +155,7 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
       density_grad_of(cs, gd, n, i, d);
       for (int a = 0; a < 3; ++a)
         gv[a] = (float)(((double)gw[a * n + i] + lam * (double)d[a]) / (double)H);
+      if (k & PLACE3D_KIND_ZFIXED) gv[2] = 0.f;               // z held (z-fixed fillers)
       if (mode == 1) {
         for (int a = 0; a < 3; ++a) {
           const double dv = (double)v[a * n + i] - (double)v_prev[a * n + i];
@@ -162,7 +165,7 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
         }
         float w, h;
         inst_wh(g, size, k, i, z, w, h);
-        const double q = (double)w * (double)h * (double)(0.5f * g.dz);
+        const double q = (k & PLACE3D_KIND_FILLER) ? 0.0 : (double)w * (double)h * (double)(0.5f * g.dz);
         if (z > g.half_dz) acc[3] += q; else acc[2] += q;
       } else {
         acc[0] = fmax(fmax(fabs((double)gv[0]), fabs((double)gv[1])), fabs((double)gv[2]));

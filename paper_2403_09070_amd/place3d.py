@@ -21,7 +21,7 @@ OK = 0
 FP32, BF16X3 = 0, 1
 DGRAD_FIELD, DGRAD_ADJOINT = 0, 1
 PRECOND_MIXED, PRECOND_EPLACE, PRECOND_EPLACE3D = 0, 1, 2
-KIND_MACRO, KIND_FIXED = 1, 2
+KIND_MACRO, KIND_FIXED, KIND_FILLER, KIND_ZFIXED = 1, 2, 4, 8
 NMETRICS, NSCALARS = 16, 32
 M = dict(wa_bi=0, wa_z=1, hpwl=2, hpwl3d=3, ncut=4, norm_x=5, norm_y=6, norm_fda=7, fda_scale=8)
 S = dict(a=0, lam=1, step=2, it=3, ovfl_bot=4, ovfl_top=5, energy=6, wl=8)
@@ -45,6 +45,13 @@ class Problem_(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("size", ctypes.c_void_p), ("kind", ctypes.c_void_p), ("net_start", ctypes.c_void_p),
                 ("pin2node", ctypes.c_void_p), ("pin_off", ctypes.c_void_p), ("fixed_xyz", ctypes.c_void_p)]
+
+
+class FillerPlan_(ctypes.Structure):
+    _fields_ = [("n_top", ctypes.c_int64), ("n_bot", ctypes.c_int64), ("n_free", ctypes.c_int64),
+                ("side_top", ctypes.c_double), ("side_bot", ctypes.c_double), ("side_free", ctypes.c_double),
+                ("vol_top", ctypes.c_double), ("vol_bot", ctypes.c_double), ("vol_free", ctypes.c_double),
+                ("vol_a", ctypes.c_double)]
 
 
 class State_(ctypes.Structure):
@@ -77,6 +84,8 @@ def lib():
             "place3d_gp_init": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
             "place3d_step": (i32, [vp, ctypes.POINTER(State_), vp]),
             "place3d_profile_enable": (i32, [vp, i32]),
+            "place3d_plan_fillers": (i32, [i32, vp, vp, vp, ctypes.c_double, ctypes.c_double, i32, i32, i32,
+                                           ctypes.c_double, ctypes.c_double, ctypes.POINTER(FillerPlan_)]),
             "place3d_profile_read": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64), i32]),
         }
@@ -113,6 +122,21 @@ def hbt_alpha(die_x, dz, hbt_pitch, row_top, row_bot, beta, alpha0=3.5e-3):
     eta = 2 w' / (RH+ + RH-) (experimental setup, Sec. V-A)."""
     eta = 2.0 * hbt_pitch / (row_top + row_bot)
     return alpha0 * (die_x * eta * eta / dz) * math.log(90.0 * beta * eta - 1.0)
+
+
+def plan_fillers(size, kind, z0, die_x, die_y, nx, ny, nz, u_top, u_bot):
+    """place3d_plan_fillers on host arrays: a dict of the counts, sides and volumes."""
+    size = np.ascontiguousarray(size, dtype=np.float32)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    z0 = np.ascontiguousarray(z0, dtype=np.float32)
+    n = int(kind.shape[0])
+    if size.shape != (4, n) or z0.shape != (n,):
+        raise ValueError("size must be [4][n] and z0 [n]")
+    out = FillerPlan_()
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    _check(lib().place3d_plan_fillers(n, vp(size), vp(kind), vp(z0), float(die_x), float(die_y), int(nx), int(ny),
+                                      int(nz), float(u_top), float(u_bot), ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in FillerPlan_._fields_}
 
 
 @dataclass

@@ -39,6 +39,18 @@ def ragged_case(seed=6, nx=37, ny=29, nz=4):
     return synth.make_case(config=cfg, seed=seed)
 
 
+def filler_case(seed=11, n_cells=200, u=0.8, sigma=0.05, config=None):
+    """A small case started around the centre with z-fixed and free fillers appended, as the
+    oracle's filler plan sizes them (Eqs. filler-vol, free-filler-vol)."""
+    from oracle import fillers as fl
+    from oracle.geometry import geometry_of
+    c = synth.make_case(config=config or synth.small_config(n_cells=n_cells, n_nets=int(1.1 * n_cells)), seed=seed)
+    c = synth.centre_start(c, sigma=sigma, seed=seed + 1)
+    geo = geometry_of(c)
+    plan = fl.filler_plan(c.size, c.kind, c.xyz0[2], geo.die_x, geo.die_y, geo.dz, u, u)
+    return synth.with_fillers(c, plan, sigma=sigma, seed=seed + 2)
+
+
 def gpu_problem(case, **kw):
     from paper_2403_09070_amd import place3d
     return place3d.Problem.from_case(case, **kw)

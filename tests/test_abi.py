@@ -76,3 +76,25 @@ def test_calls_reject_a_null_context(L):
     assert L.place3d_density(None, None, None, None) == -1
     assert L.place3d_step(None, None, None) == -1
     assert L.place3d_destroy(None) == 0
+
+
+def test_filler_plan_matches_the_oracle(L):
+    """place3d_plan_fillers (host arithmetic in the library) against the oracle's plan."""
+    import numpy as np
+    from oracle import fillers as fl
+    from oracle.geometry import geometry_of
+    from paper_2403_09070_amd import place3d, synth
+    for name, u in (("c1", (0.8, 0.8)), ("c1", (0.6, 0.95)), ("c1", (0.0, 0.0))):
+        c = synth.make_case(name, 2403)
+        geo = geometry_of(c)
+        mine = place3d.plan_fillers(c.size, c.kind, c.xyz0[2], c.die_x, c.die_y, c.nx, c.ny, c.nz, *u)
+        ref = fl.filler_plan(c.size, c.kind, c.xyz0[2], geo.die_x, geo.die_y, geo.dz, *u)
+        for k in ("n_top", "n_bot", "n_free"):
+            assert mine[k] == ref[k], k
+        for k in ("side_top", "side_bot", "side_free", "vol_top", "vol_bot", "vol_free", "vol_a"):
+            assert abs(mine[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), k
+    c = synth.make_case("c1", 2403)
+    with pytest.raises(place3d.Place3dError):
+        place3d.plan_fillers(c.size, c.kind, c.xyz0[2], c.die_x, c.die_y, c.nx, c.ny, c.nz, 1.5, 0.8)
+    with pytest.raises(place3d.Place3dError):
+        place3d.plan_fillers(c.size, np.full_like(c.kind, 1), c.xyz0[2], c.die_x, c.die_y, c.nx, c.ny, c.nz, 0.8, 0.8)

@@ -6,6 +6,9 @@
   |g_k - g_{k-1}|, which amplifies the float32 rounding of the gradient by |g| / |g_k - g_{k-1}|,
   so the displacement is compared at 1e-3 relative (measured well below).
 * A short trajectory: the D2D HPWL of GPU and oracle stay within 1e-3 of each other.
+* The ePlace and ePlace3D preconditioners of Eq. general-precond: init and one step, as above.
+* Fillers (z-fixed and free): init, one step and a 20-step trajectory with the overflow measured
+  without them; z-fixed fillers keep their z exactly.
 """
 import numpy as np
 import pytest
@@ -21,11 +24,22 @@ FORMS = {
     "field-fp32": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.FP32),
     "field-bf16x3": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.BF16X3),
     "adjoint-bf16x3": dict(dgrad=place3d.DGRAD_ADJOINT, precision=place3d.BF16X3),
+    # the two earlier preconditioners of Eq. general-precond (ePlace and ePlace3D forms)
+    "field-bf16x3-eplace": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.BF16X3,
+                                precond=place3d.PRECOND_EPLACE),
+    "field-bf16x3-eplace3d": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.BF16X3,
+                                  precond=place3d.PRECOND_EPLACE3D),
 }
+PRECOND_NAMES = {place3d.PRECOND_MIXED: "mixed", place3d.PRECOND_EPLACE: "eplace",
+                 place3d.PRECOND_EPLACE3D: "eplace3d"}
 
 
 def _oracle_form(form):
     return "field" if FORMS[form]["dgrad"] == place3d.DGRAD_FIELD else "adjoint"
+
+
+def _oracle_precond(form):
+    return PRECOND_NAMES[FORMS[form].get("precond", place3d.PRECOND_MIXED)]
 
 
 @pytest.mark.parametrize("form", list(FORMS))
@@ -37,7 +51,7 @@ def test_gp_init(which, form):
     prob = gpu_problem(case, **FORMS[form])
     pb = oracle_problem(case)
     st = prob.gp_init(case.xyz0)
-    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form))
+    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form), precond=_oracle_precond(form))
     s = st.read()
     log(f"[step] lambda0 gpu={s['lam']:.9g} ref={ref.lam:.9g}")
     assert abs(s["lam"] - ref.lam) <= 1e-5 * ref.lam
@@ -72,14 +86,14 @@ def test_one_step_from_the_same_state(form):
     case = synth.make_case("c1", 2403)
     prob = gpu_problem(case, **FORMS[form])
     pb = oracle_problem(case)
-    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form))
+    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form), precond=_oracle_precond(form))
     for _ in range(3):                                   # move away from the bootstrap point
-        opt.gp_step(pb, ref, dgrad=_oracle_form(form))
+        opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
     ref = _round_state(ref)
     st = _load_state(prob, ref)
     v0 = ref.v.copy()
     prob.step(st)
-    m = opt.gp_step(pb, ref, dgrad=_oracle_form(form))
+    m = opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
     s = st.read()
     for key, rkey in (("hpwl", "hpwl_d2d"), ("wa_bi", "wa_bi"), ("wa_z", "wa_z")):
         assert abs(s[key] - m[rkey]) <= 1e-5 * abs(m[rkey]), key
@@ -112,3 +126,68 @@ def test_short_trajectory_tracks_the_oracle():
         log(f"[step] it {k} hpwl gpu={s['hpwl']:.7g} ref={m['hpwl_d2d']:.7g} rel={d:.2e} "
             f"ovfl gpu={s['ovfl_bot']:.4f}/{s['ovfl_top']:.4f} ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
     assert worst <= 1e-3
+
+
+def test_fillers_init_step_and_trajectory():
+    """z-fixed and free fillers (density model, Sec. III-A) on a centre start: lambda_0 and the
+    bootstrap agree with the oracle, the per-die overflow (fillers left out) and the D2D HPWL track
+    it for 20 steps, z-fixed fillers keep their z bit for bit and free fillers move in z."""
+    from gpu_common import filler_case
+    need_gpu()
+    log("[step] fillers: init + 20 steps")
+    case = filler_case(11)
+    held = (case.kind & place3d.KIND_ZFIXED) != 0
+    free = ((case.kind & place3d.KIND_FILLER) != 0) & ~held
+    assert held.any() and free.any()
+    prob = gpu_problem(case, precision=place3d.BF16X3)
+    pb = oracle_problem(case)
+    st = prob.gp_init(case.xyz0)
+    ref = opt.gp_init(pb, case.xyz0)
+    s = st.read()
+    assert abs(s["lam"] - ref.lam) <= 1e-5 * ref.lam
+    assert rel_l2(st.g_prev.cpu().numpy(), ref.g_prev) <= 1e-4
+    assert np.all(st.g_prev.cpu().numpy()[2, held] == 0.0)
+    z_held = case.xyz0[2, held].copy()
+    z_free = st.v.cpu().numpy()[2, free].copy()
+    worst_h = worst_o = 0.0
+    saw_overflow = False
+    for k in range(20):
+        prob.step(st)
+        m = opt.gp_step(pb, ref)
+        s = st.read()
+        dh = abs(s["hpwl"] - m["hpwl_d2d"]) / m["hpwl_d2d"]
+        do = max(abs(s["ovfl_bot"] - m["ovfl_bot"]), abs(s["ovfl_top"] - m["ovfl_top"]))
+        worst_h, worst_o = max(worst_h, dh), max(worst_o, do)
+        saw_overflow |= max(m["ovfl_bot"], m["ovfl_top"]) > 0.05
+        log(f"[step] fillers it {k} hpwl rel={dh:.2e} ovfl gpu={s['ovfl_bot']:.4f}/{s['ovfl_top']:.4f} "
+            f"ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
+    v = st.v.cpu().numpy()
+    assert np.array_equal(v[2, held], z_held) and np.array_equal(st.u.cpu().numpy()[2, held], z_held)
+    assert np.abs(v[2, free] - z_free).max() > 0.0
+    assert saw_overflow
+    assert worst_h <= 1e-3 and worst_o <= 1e-3
+
+
+def test_fillers_one_step_from_the_same_state():
+    from gpu_common import filler_case
+    need_gpu()
+    log("[step] fillers: one step c1-sized")
+    case = filler_case(12, config=synth.CONFIGS["c1"], u=0.9, sigma=0.08)
+    prob = gpu_problem(case, precision=place3d.BF16X3)
+    pb = oracle_problem(case)
+    ref = opt.gp_init(pb, case.xyz0)
+    for _ in range(3):
+        opt.gp_step(pb, ref)
+    ref = _round_state(ref)
+    st = _load_state(prob, ref)
+    v0 = ref.v.copy()
+    prob.step(st)
+    m = opt.gp_step(pb, ref)
+    s = st.read()
+    assert abs(s["hpwl"] - m["hpwl_d2d"]) <= 1e-5 * m["hpwl_d2d"]
+    assert abs(s["ovfl_bot"] - m["ovfl_bot"]) <= 1e-6 and abs(s["ovfl_top"] - m["ovfl_top"]) <= 1e-6
+    step_err = abs(s["step"] - m["step"]) / m["step"]
+    disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
+    log(f"[step] fillers step rel={step_err:.3e} displacement rel_l2={disp:.3e} "
+        f"ovfl={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
+    assert step_err <= 1e-3 and disp <= 1e-3
