@@ -158,32 +158,32 @@ def cpu_baseline(case, frac=4):
 
 def precond_ablation(args, log):
     """Eq. improved-precond against the ePlace (|E_i| + lambda q_i) and ePlace3D (lambda q_i) forms of
-    Eq. general-precond (Sec. III-C3 and the preconditioner ablation of Sec. V): the same macro-heavy
+    Eq. general-precond (Sec. III-A, and the preconditioner ablation of Sec. V): the same macro-heavy
     netlist is placed from the same clustered start with each form, recording per iteration the D2D
-    HPWL and per-die overflow, and every --ablation-every iterations the macro density overflow,
-    i.e. the overflow of the map of the macros alone against the target density."""
+    HPWL and per-die overflow (fillers left out), and every --ablation-every iterations the macro
+    density overflow, i.e. the overflow of the map of the macros alone against the target density.
+    Fillers (z-fixed and free, Eqs. filler-vol and free-filler-vol) fill the region unless
+    --ablation-util is 0."""
     import numpy as np
     import torch
     from paper_2403_09070_amd import place3d, synth
-    case = synth.make_case(args.config, args.seed)
-    rng = np.random.default_rng(args.seed + 1)
-    n, nc = case.n_inst, case.meta["n_cells"]
-    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
-    start = case.xyz0.astype(np.float64).copy()
-    mov = (case.kind & place3d.KIND_FIXED) == 0
+    case = synth.centre_start(synth.make_case(args.config, args.seed), sigma=args.ablation_spread, seed=args.seed + 1)
+    nc = case.meta["n_cells"]
+    plan = None
+    if args.ablation_util > 0:
+        plan = place3d.plan_fillers(case.size, case.kind, case.xyz0[2], case.die_x, case.die_y, case.nx, case.ny,
+                                    case.nz, args.ablation_util, args.ablation_util)
+        case = synth.with_fillers(case, plan, sigma=args.ablation_spread, seed=args.seed + 2)
+        log(f"[ablation] fillers: {plan['n_top']} + {plan['n_bot']} z-fixed, {plan['n_free']} free")
+    start = case.xyz0
     sig = args.ablation_spread
-    start[0, mov] = case.die_x * (0.5 + sig * rng.standard_normal(int(mov.sum())))
-    start[1, mov] = case.die_y * (0.5 + sig * rng.standard_normal(int(mov.sum())))
-    start[2, mov] = dz * (0.5 + 0.05 * rng.standard_normal(int(mov.sum())))
-    start = start.astype(np.float32)
     mac = np.nonzero((case.kind & place3d.KIND_MACRO) != 0)[0]
-    base = place3d.Problem.from_case(case)
+    params = place3d.Problem.case_params(case)
     mprob = place3d.Problem(size=case.size[:, mac], kind=case.kind[mac], net_start=np.zeros(1, np.int32),
                             pin2node=np.zeros(0, np.int32), pin_off=np.zeros((4, 0), np.float32),
                             fixed_xyz=case.xyz0[:, mac], die_x=case.die_x, die_y=case.die_y,
-                            nx=case.nx, ny=case.ny, nz=case.nz, **{k: base.params[k] for k in ("gamma", "alpha")},
-                            target_density=base.params["target_density"])
-    del base
+                            nx=case.nx, ny=case.ny, nz=case.nz, gamma=params["gamma"], alpha=params["alpha"],
+                            target_density=params["target_density"])
     mac_t = torch.as_tensor(mac, device="cuda", dtype=torch.long)
     target = mprob.params["target_density"]
     half = case.nz // 2
@@ -245,8 +245,10 @@ def precond_ablation(args, log):
     for name in ("eplace", "eplace3d"):
         a, b = summary[name].get("reached"), ref.get("reached")
         summary[name]["hpwl_vs_mixed_at_stop"] = (a["hpwl"] / b["hpwl"]) if a and b else None
+    fill = (f", fillers for utilisation {args.ablation_util}: {plan['n_top']} + {plan['n_bot']} z-fixed, "
+            f"{plan['n_free']} free") if plan else ", no fillers"
     print(json.dumps({"ablation": "preconditioner", "workload": f"{args.config} seed {args.seed}, "
-                      f"{nc} cells + {len(mac)} macros, clustered start (sigma {sig} of the die)",
+                      f"{nc} cells + {len(mac)} macros, clustered start (sigma {sig} of the die){fill}",
                       "stop_overflow": args.ablation_stop, "forms": summary}), flush=True)
 
 
@@ -269,6 +271,8 @@ def main():
     ap.add_argument("--ablation-every", type=int, default=5)
     ap.add_argument("--ablation-spread", type=float, default=0.02)
     ap.add_argument("--ablation-stop", type=float, default=0.1)
+    ap.add_argument("--ablation-util", type=float, default=0.8,
+                    help="maximum utilisation u of both dies for the fillers (0: no fillers)")
     ap.add_argument("--ablation-csv", default=None)
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731

@@ -201,14 +201,19 @@ class Problem:
         _check(L.place3d_create(ctypes.byref(self._p), ctypes.c_void_p(aligned), nbytes.value, _stream(),
                                 ctypes.byref(self._ctx)))
 
-    @classmethod
-    def from_case(cls, case, **kw):
+    @staticmethod
+    def case_params(case):
+        """gamma, alpha, target density and lambda ramp of a synthetic case's configuration."""
         cfg = case.config
         wb = case.die_x / case.nx
         dz = case.nz * 0.5 * (wb + case.die_y / case.ny)
-        params = dict(gamma=cfg.gamma_bins * wb,
-                      alpha=hbt_alpha(case.die_x, dz, cfg.hbt_pitch, cfg.row_top, cfg.row_bot, cfg.beta, cfg.alpha0),
-                      target_density=cfg.target_density, lambda_ramp=cfg.lambda_ramp)
+        return dict(gamma=cfg.gamma_bins * wb,
+                    alpha=hbt_alpha(case.die_x, dz, cfg.hbt_pitch, cfg.row_top, cfg.row_bot, cfg.beta, cfg.alpha0),
+                    target_density=cfg.target_density, lambda_ramp=cfg.lambda_ramp)
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        params = cls.case_params(case)
         params.update(kw)
         return cls(size=case.size, kind=case.kind, net_start=case.net_start, pin2node=case.pin2node,
                    pin_off=case.pin_off, fixed_xyz=case.xyz0, die_x=case.die_x, die_y=case.die_y,
