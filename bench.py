@@ -17,7 +17,9 @@ block.  The CPU baseline is the FP64 oracle on a bounded sample of the same work
 
 ``--ablation precond`` runs the preconditioner ablation instead (one JSON line, curves to
 ``--ablation-csv``): the mixed-size preconditioner against the ePlace and ePlace3D forms on the
-macro-heavy 200k-cell workload from a clustered start.
+macro-heavy 200k-cell workload from a clustered start.  ``--ablation algo`` times the density map
+and the wirelength call with the paper's baseline algorithms (instance-parallel macro scatter,
+O(|P_e|^2) FDA) against the default ones on the 1.2M-cell workload.
 """
 from __future__ import annotations
 
@@ -252,6 +254,47 @@ def precond_ablation(args, log):
                       "stop_overflow": args.ablation_stop, "forms": summary}), flush=True)
 
 
+def algo_ablation(args, log):
+    """The paper's algorithm ablation (Sec. IV; its Fig. acc-density) on this hardware: the density
+    map with large instances scattered instance-parallel (one thread per instance, global atomics)
+    against the tile-resident bin-parallel sweep, and the wirelength call with the O(|P_e|^2)
+    vanilla FDA against the incremental one.  Each call is timed alone (HIP events on the launch
+    stream, mean over --ablation-iters calls after 5 warm-up calls) at the workload's start."""
+    import torch
+    from paper_2403_09070_amd import place3d, synth
+    case = synth.make_case(args.config, args.seed)
+    forms = {"default": 0, "macro_instance": place3d.OPT_MACRO_INSTANCE, "fda_vanilla": place3d.OPT_FDA_VANILLA}
+    out = {}
+    for name, opt in forms.items():
+        prob = place3d.Problem.from_case(case, precision=place3d.BF16X3, options=opt)
+        xyz = prob.xyz(case.xyz0)
+        rho = prob.new_map()
+        g = torch.empty((3, prob.n), dtype=torch.float32, device="cuda")
+        res = {}
+        for call, fn in (("density", lambda: prob.density(xyz, out=rho)), ("wl_grad", lambda: prob.wl_grad(xyz, out=g))):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(args.ablation_iters):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            res[call + "_ms"] = t0.elapsed_time(t1) / args.ablation_iters
+        out[name] = res
+        log(f"[ablation] {name}: {res}")
+        del prob
+        torch.cuda.empty_cache()
+    d, m, v = out["default"], out["macro_instance"], out["fda_vanilla"]
+    print(json.dumps({"ablation": "algorithms", "workload": f"{args.config} seed {args.seed}: {case.meta['n_cells']} "
+                      f"cells + {case.meta['n_macros']} macros, {case.n_nets} nets, {case.n_pins} pins, grid "
+                      f"{case.nx}x{case.ny}x{case.nz}", "calls": args.ablation_iters, "forms": out,
+                      "density_speedup_tiles_over_instance": m["density_ms"] / d["density_ms"],
+                      "wl_speedup_incremental_over_vanilla": v["wl_grad_ms"] / d["wl_grad_ms"],
+                      "paper_context": {"density": 4.7, "fda": 1.7}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,7 +308,7 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
-    ap.add_argument("--ablation", choices=["precond"], default=None,
+    ap.add_argument("--ablation", choices=["precond", "algo"], default=None,
                     help="run the preconditioner ablation instead of the timing benchmark")
     ap.add_argument("--ablation-iters", type=int, default=1000)
     ap.add_argument("--ablation-every", type=int, default=5)
@@ -284,9 +327,13 @@ def main():
     from paper_2403_09070_amd import place3d, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     place3d.lib()
-    if args.ablation:
+    if args.ablation == "precond":
         args.config = args.config or "c2"
         precond_ablation(args, log)
+        return
+    if args.ablation == "algo":
+        args.config = args.config or "c4"
+        algo_ablation(args, log)
         return
     args.config = args.config or "c4"
     if args.copy_mb > 0:

@@ -78,6 +78,18 @@ enum { PLACE3D_PRECOND_MIXED = 0,     /* max{1,|E_i|+lambda q_i} macros, max{1,l
        PLACE3D_PRECOND_EPLACE = 1,    /* |E_i| + lambda q_i                                   */
        PLACE3D_PRECOND_EPLACE3D = 2 };/* lambda q_i                                           */
 
+/* Algorithm options (place3d_problem.options bits): the baselines that the paper's adaptive
+ * density accumulation and incremental FDA are measured against (Sec. IV), kept to repeat that
+ * comparison on this hardware.  Results agree with the default algorithms within rounding.
+ * MACRO_INSTANCE: large instances (movable macros, oversized cells) are scattered into the map
+ *   instance-parallel, one thread per instance walking all its bins with global float atomics,
+ *   instead of the tile-resident bin-parallel sweep (Sec. IV-A); the map's last bits then depend
+ *   on atomic order.  Not available with fillers (create returns PLACE3D_ERR_UNSUPPORTED).
+ * FDA_VANILLA: every pin's FDA difference comes from a full re-evaluation of its net's exact
+ *   bistratal wirelength with the owner on each die, O(|P_e|^2) per net, instead of the
+ *   incremental O(|P_e|) evaluation of Sec. IV-B. */
+enum { PLACE3D_OPT_MACRO_INSTANCE = 1, PLACE3D_OPT_FDA_VANILLA = 2 };
+
 /* Instance kind bits (uint8 per instance).
  * FILLER: a dummy filler (density model, Sec. III-A): a movable, cell-sized instance with no pins
  *   that takes part in the density map and moves with the density force, but is left out of the
@@ -140,7 +152,7 @@ typedef struct place3d_problem {
   int32_t precision;       /* PLACE3D_FP32 or PLACE3D_BF16X3                                 */
   int32_t dgrad;           /* PLACE3D_DGRAD_FIELD or PLACE3D_DGRAD_ADJOINT                   */
   int32_t precond;         /* PLACE3D_PRECOND_*                                              */
-  int32_t reserved;
+  int32_t options;         /* PLACE3D_OPT_* bits; 0 for the default algorithms                */
   /* device arrays, caller-owned, read-only, must outlive the context */
   const float* size;       /* float32 [4][n_inst]: w_bot, h_bot, w_top, h_top (Eq. std-size-tech) */
   const uint8_t* kind;     /* uint8 [n_inst], PLACE3D_KIND_* bits                             */

@@ -40,6 +40,7 @@ int check_problem(const place3d_problem* p, std::string& why) {
   if (p->precision != PLACE3D_FP32 && p->precision != PLACE3D_BF16X3) { why = "bad precision"; return PLACE3D_ERR_ARG; }
   if (p->dgrad != PLACE3D_DGRAD_FIELD && p->dgrad != PLACE3D_DGRAD_ADJOINT) { why = "bad dgrad"; return PLACE3D_ERR_ARG; }
   if (p->precond < PLACE3D_PRECOND_MIXED || p->precond > PLACE3D_PRECOND_EPLACE3D) { why = "bad precond"; return PLACE3D_ERR_ARG; }
+  if (p->options & ~(PLACE3D_OPT_MACRO_INSTANCE | PLACE3D_OPT_FDA_VANILLA)) { why = "unknown option bits"; return PLACE3D_ERR_ARG; }
   if (!p->size || !p->kind || !p->net_start || !p->fixed_xyz) { why = "null device array in problem"; return PLACE3D_ERR_ARG; }
   if (p->n_pins > 0 && (!p->pin2node || !p->pin_off)) { why = "null pin arrays"; return PLACE3D_ERR_ARG; }
   if ((reinterpret_cast<uintptr_t>(p->size) | reinterpret_cast<uintptr_t>(p->pin_off) |
@@ -294,6 +295,8 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     }
   }
   c->n_fillers = n_fill;
+  if (n_fill > 0 && (p.options & PLACE3D_OPT_MACRO_INSTANCE))
+    return set_err(c, PLACE3D_ERR_UNSUPPORTED, "the instance-parallel macro scatter cannot leave fillers out of the overflow");
   c->n_large = (int32_t)large.size();
   c->n_fixed = (int32_t)fixed.size();
   P3D_HIP(c, hipMemcpyAsync(c->cls, cls.data(), n, hipMemcpyHostToDevice, s));

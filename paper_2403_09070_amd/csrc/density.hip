@@ -534,6 +534,46 @@ __global__ void k_density_large(Geom g, const float* __restrict__ xyz, const flo
   }
 }
 
+// Instance-parallel scatter of the large instances (the baseline of Sec. IV-A, selected by
+// PLACE3D_OPT_MACRO_INSTANCE): one thread per instance walks all its bins and adds its overlap
+// with a global float atomic.  The tile kernel then runs without the large-instance sweep.
+__global__ __launch_bounds__(64) void k_density_large_thread(Geom g, const float* __restrict__ xyz,
+                                                             const float* __restrict__ size,
+                                                             const uint8_t* __restrict__ kind,
+                                                             const int32_t* __restrict__ list, int nlist,
+                                                             float* __restrict__ rho) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nlist) return;
+  const int i = list[j];
+  const Foot f = footprint(g, xyz, size, kind[i], i);
+  const float wgt = f.omega / g.vol_bin;
+  for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+    const float lz = len_z(g, f, bz) * wgt;
+    for (int by = f.by0; by <= f.by1; ++by) {
+      const float lyz = len_y(g, f, by) * lz;
+      for (int bx = f.bx0; bx <= f.bx1; ++bx) {
+        const float v = len_x(g, f, bx) * lyz;
+        if (v != 0.f) atomicAdd(rho + bin_index(g, bz, by, bx), v);
+      }
+    }
+  }
+}
+
+// per-die overflow excess of a finished map, one partial per workgroup (the tile kernel's slots
+// and partial count, so the same final reduction applies)
+__global__ __launch_bounds__(256) void k_map_excess(Geom g, const float* __restrict__ rho, float target,
+                                                    double* __restrict__ part, int stride) {
+  const long long plane = (long long)g.nx * g.ny, total = plane * g.nz;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long q0 = (long long)blockIdx.x * per, q1 = q0 + per < total ? q0 + per : total;
+  const long long half = plane * (g.nz / 2);
+  float ex[2] = {0.f, 0.f};
+  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) ex[q < half ? 0 : 1] += fmaxf(rho[q] - target, 0.f);
+  ex[0] *= g.vol_bin;
+  ex[1] *= g.vol_bin;
+  block_partials<2>(ex, part, stride, R_EXCESS_BOT, blockIdx.x);
+}
+
 __global__ void k_fill(float* __restrict__ p, long long n, float v) {
   for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
     p[q] = v;
@@ -1021,10 +1061,19 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
   {
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
     const int fillers = c->n_fillers > 0 ? 1 : 0;
+    const bool inst = (p.options & PLACE3D_OPT_MACRO_INSTANCE) != 0;
     hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), (2 + 2 * fillers) * tile_lds(c, 1), s, g,
                        t, c->bk_entries, c->bk_tile_start, c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec,
-                       c->n_large, (float)p.target_density, fillers, rho, c->part, c->part_stride);
+                       inst ? 0 : c->n_large, (float)p.target_density, fillers, rho, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
+    if (inst && c->n_large > 0) {
+      hipLaunchKernelGGL(k_density_large_thread, dim3(blocks_for(c->n_large, 64)), dim3(64), 0, s, g, xyz, p.size,
+                         p.kind, c->large_list, c->n_large, rho);
+      P3D_LAUNCH(c, "k_density_large_thread");
+      hipLaunchKernelGGL(k_map_excess, dim3(t.ntiles), dim3(256), 0, s, g, rho, (float)p.target_density, c->part,
+                         c->part_stride);
+      P3D_LAUNCH(c, "k_map_excess");
+    }
   }
   if (!reduce) return PLACE3D_OK;
   return reduce_final(c, R_EXCESS_BOT, 2, t.ntiles, false, red + R_EXCESS_BOT, s);

@@ -492,6 +492,52 @@ __global__ void k_wl_finish_z(int n, const float* __restrict__ gz_wa, const floa
   }
 }
 
+// Vanilla FDA (the O(|P_e|^2) baseline of Sec. IV-B, selected by PLACE3D_OPT_FDA_VANILLA): one
+// thread per pin slot re-evaluates its net's exact bistratal wirelength with the owner on the top
+// die and on the bottom die from all |P_e| pins, and overwrites the FDA difference k_wl_nets
+// stored for the slot.  Coordinates are relative to the net's first owner, as in k_wl_nets.
+__device__ __forceinline__ void set_put(float& mx, float& mn, int& cnt, float u) {
+  mx = fmaxf(mx, u);
+  mn = fminf(mn, u);
+  ++cnt;
+}
+
+__global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, float half_dz, float four_over_dz,
+                                                     const float4* __restrict__ xyzp,
+                                                     const int32_t* __restrict__ s_net_start,
+                                                     const int32_t* __restrict__ pin_node,
+                                                     const float4* __restrict__ off,
+                                                     const int32_t* __restrict__ slot_pos,
+                                                     float4* __restrict__ pin_out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  int lo = 0, hi = nnets - 1;                    // the net holding slot s: last e with start <= s
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_net_start[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  const int b = s_net_start[lo], e = s_net_start[lo + 1];
+  const float4 q0 = xyzp[pin_node[b]];
+  const float xa = q0.x, ya = q0.y;
+  float txM = kNegInf, txm = kPosInf, tyM = kNegInf, tym = kPosInf;
+  float bxM = kNegInf, bxm = kPosInf, byM = kNegInf, bym = kPosInf;
+  int ct = 0, cb = 0, cdummy = 0;
+  for (int q = b; q < e; ++q) {                  // every other pin, on its own die
+    if (q == s) continue;
+    const PinRel p = load_pin(xyzp, pin_node, off, q, half_dz, xa, ya);
+    if (p.top) { set_put(txM, txm, ct, p.ux); set_put(tyM, tym, cdummy, p.uy); }
+    else       { set_put(bxM, bxm, cb, p.ux); set_put(byM, bym, cdummy, p.uy); }
+  }
+  const PinRel me = load_pin(xyzp, pin_node, off, s, half_dz, xa, ya);
+  const float xt = me.top ? me.ux : me.fx, yt = me.top ? me.uy : me.fy;   // the owner's pin on top
+  const float xb = me.top ? me.fx : me.ux, yb = me.top ? me.fy : me.uy;   // and on the bottom
+  const float wx_top = w_exact(fmaxf(txM, xt), fminf(txm, xt), ct + 1, bxM, bxm, cb);
+  const float wy_top = w_exact(fmaxf(tyM, yt), fminf(tym, yt), ct + 1, byM, bym, cb);
+  const float wx_bot = w_exact(txM, txm, ct, fmaxf(bxM, xb), fminf(bxm, xb), cb + 1);
+  const float wy_bot = w_exact(tyM, tym, ct, fmaxf(byM, yb), fminf(bym, yb), cb + 1);
+  pin_out[slot_pos[s]].w = four_over_dz * ((wx_top - wx_bot) + (wy_top - wy_bot));
+}
+
 }  // namespace
 
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
@@ -510,6 +556,12 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
                        (float)p.gamma, (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
                        c->pin_out, c->classes, c->wa_block_order, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
+    if (p.options & PLACE3D_OPT_FDA_VANILLA) {
+      const int nslots = p.n_pins, nnets = c->classes.net_begin[kNumClasses];
+      hipLaunchKernelGGL(k_fda_vanilla, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nslots, nnets, g.half_dz,
+                         4.f / g.dz, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out);
+      P3D_LAUNCH(c, "k_fda_vanilla");
+    }
   }
   if ((rc = reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, red + R_WA_BI, s))) return rc;
   const unsigned nlight = blocks_for(g.n, 256);

@@ -21,6 +21,7 @@ OK = 0
 FP32, BF16X3 = 0, 1
 DGRAD_FIELD, DGRAD_ADJOINT = 0, 1
 PRECOND_MIXED, PRECOND_EPLACE, PRECOND_EPLACE3D = 0, 1, 2
+OPT_MACRO_INSTANCE, OPT_FDA_VANILLA = 1, 2
 KIND_MACRO, KIND_FIXED, KIND_FILLER, KIND_ZFIXED = 1, 2, 4, 8
 NMETRICS, NSCALARS = 16, 32
 M = dict(wa_bi=0, wa_z=1, hpwl=2, hpwl3d=3, ncut=4, norm_x=5, norm_y=6, norm_fda=7, fda_scale=8)
@@ -42,7 +43,7 @@ class Problem_(ctypes.Structure):
                 ("die_x", ctypes.c_double), ("die_y", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("target_density", ctypes.c_double),
                 ("lambda_ramp", ctypes.c_double), ("precision", ctypes.c_int32), ("dgrad", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("options", ctypes.c_int32),
                 ("size", ctypes.c_void_p), ("kind", ctypes.c_void_p), ("net_start", ctypes.c_void_p),
                 ("pin2node", ctypes.c_void_p), ("pin_off", ctypes.c_void_p), ("fixed_xyz", ctypes.c_void_p)]
 
@@ -168,7 +169,7 @@ class Problem:
 
     def __init__(self, *, size, kind, net_start, pin2node, pin_off, fixed_xyz, die_x, die_y, nx, ny, nz,
                  gamma, alpha, target_density=1.0, lambda_ramp=1.05, precision=FP32, dgrad=DGRAD_FIELD,
-                 precond=PRECOND_MIXED, device="cuda"):
+                 precond=PRECOND_MIXED, options=0, device="cuda"):
         L = lib()
         dev = torch.device(device)
         self.device = dev
@@ -186,10 +187,10 @@ class Problem:
         self.fixed_xyz = t(fixed_xyz, torch.float32)
         self.params = dict(gamma=float(gamma), alpha=float(alpha), target_density=float(target_density),
                            lambda_ramp=float(lambda_ramp), precision=int(precision), dgrad=int(dgrad),
-                           precond=int(precond))
+                           precond=int(precond), options=int(options))
         self._p = Problem_(self.n, self.P, self.m, self.nx, self.ny, self.nz, self.die_x, self.die_y,
                            float(gamma), float(alpha), float(target_density), float(lambda_ramp),
-                           int(precision), int(dgrad), int(precond), 0,
+                           int(precision), int(dgrad), int(precond), int(options),
                            self.size.data_ptr(), self.kind.data_ptr(), self.net_start.data_ptr(),
                            self.pin2node.data_ptr(), self.pin_off.data_ptr(), self.fixed_xyz.data_ptr())
         nbytes = ctypes.c_size_t()

@@ -89,8 +89,10 @@ def test_field(setup, precision):
     assert abs(float(out["energy"].cpu()[0]) - e_ref) <= 1e-4 * abs(e_ref)
 
 
-def test_wirelength(setup):
+def test_wirelength(setup, options=0):
     name, case, prob = setup
+    if options:
+        prob = gpu_problem(case, options=options)
     geo = geometry_of(case)
     pb = oracle_problem(case)
     g, met = prob.wl_grad(case.xyz0)
@@ -145,3 +147,25 @@ def test_density_vjp(setup):
     err = rel_l2(g, ref)
     log(f"[parity] {name} density-vjp rel_l2={err:.3e}")
     assert err <= 1e-5
+
+
+def test_baseline_algorithms(setup):
+    """The paper's baselines (Sec. IV) behind the option bits: the instance-parallel scatter of
+    large instances gives the same map as the tile-resident sweep (atomic order aside), and the
+    O(|P_e|^2) FDA the same z-gradient as the incremental one, both to the default bars."""
+    name, case, _ = setup
+    from paper_2403_09070_amd import place3d
+    geo = geometry_of(case)
+    if (case.kind & place3d.KIND_FILLER).any():
+        with pytest.raises(place3d.Place3dError):
+            gpu_problem(case, options=place3d.OPT_MACRO_INSTANCE)
+        opts = place3d.OPT_FDA_VANILLA
+    else:
+        opts = place3d.OPT_MACRO_INSTANCE | place3d.OPT_FDA_VANILLA
+        prob = gpu_problem(case, options=opts)
+        rho = prob.density(case.xyz0).cpu().numpy()
+        ref = oden.density_map(case.size, case.kind, case.xyz0, geo)
+        err = rel_l2(rho, ref)
+        log(f"[parity] {name} instance-parallel density rel_l2={err:.3e}")
+        assert err <= 1e-6
+    test_wirelength(setup, options=opts)

@@ -191,3 +191,23 @@ def test_fillers_one_step_from_the_same_state():
     log(f"[step] fillers step rel={step_err:.3e} displacement rel_l2={disp:.3e} "
         f"ovfl={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
     assert step_err <= 1e-3 and disp <= 1e-3
+
+
+def test_baseline_algorithms_in_the_step():
+    """The option bits of the paper's baselines (instance-parallel macro scatter, vanilla FDA)
+    leave a 10-step trajectory where the default algorithms take it (atomic order aside)."""
+    need_gpu()
+    log("[step] baseline algorithm options: 10 steps")
+    case = tiny_case(5)
+    assert ((case.kind & place3d.KIND_MACRO) != 0).any()
+    a = gpu_problem(case, precision=place3d.BF16X3)
+    b = gpu_problem(case, precision=place3d.BF16X3, options=place3d.OPT_MACRO_INSTANCE | place3d.OPT_FDA_VANILLA)
+    sa, sb = a.gp_init(case.xyz0), b.gp_init(case.xyz0)
+    for k in range(10):
+        a.step(sa)
+        b.step(sb)
+        ra, rb = sa.read(), sb.read()
+        dh = abs(ra["hpwl"] - rb["hpwl"]) / ra["hpwl"]
+        do = max(abs(ra["ovfl_bot"] - rb["ovfl_bot"]), abs(ra["ovfl_top"] - rb["ovfl_top"]))
+        log(f"[step] options it {k} hpwl rel={dh:.2e} ovfl diff={do:.2e}")
+        assert dh <= 1e-4 and do <= 1e-4
