@@ -261,11 +261,14 @@ PLACE3D_API int32_t place3d_plan_fillers(int32_t n_inst, const float* size, cons
                                          double die_x, double die_y, int32_t nx, int32_t ny, int32_t nz,
                                          double u_top, double u_bot, place3d_filler_plan* out);
 
-/* Profiling.  With `on` != 0, every later kernel launch of `ctx` is bracketed by a pair of HIP
- * events recorded on the launch stream; place3d_profile_read waits for the recorded events and
- * returns, for `stage`, the summed GPU milliseconds and the number of launches since the last
- * reset (`reset` != 0 clears all stages after reading).  Event objects are host-runtime objects;
- * no device memory is allocated.  Profiling adds a small per-launch overhead. */
+/* Profiling.  `on` is a bit mask of stages (bit k = PLACE3D_STAGE_* k; PLACE3D_PROFILE_ALL for
+ * every stage, 0 to stop): every later kernel launch of `ctx` in a selected stage is bracketed by
+ * a pair of HIP events recorded on the launch stream; place3d_profile_read waits for the recorded
+ * events and returns, for `stage`, the summed GPU milliseconds and the number of launches since
+ * the last reset (`reset` != 0 clears all stages after reading).  Event objects are host-runtime
+ * objects; no device memory is allocated.  Each bracketed launch pays a small overhead, and the
+ * events change how launches on the two streams overlap, so a narrow mask perturbs least. */
+#define PLACE3D_PROFILE_ALL 0xFF
 PLACE3D_API int32_t place3d_profile_enable(place3d_ctx* ctx, int32_t on);
 PLACE3D_API int32_t place3d_profile_read(place3d_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
                                          int32_t reset);

@@ -340,11 +340,12 @@ int prof_begin(place3d_ctx* c, int stage, hipStream_t s) {
     if (hipEventCreate(&ev.first) != hipSuccess) return PLACE3D_ERR_HIP;
     if (hipEventCreate(&ev.second) != hipSuccess) { hipEventDestroy(ev.first); return PLACE3D_ERR_HIP; }
   }
-  c->prof_pending.push_back({stage, ev.first, ev.second});
+  c->prof_pending.push_back({stage, ev.first, ev.second, 1});
   return hipEventRecord(ev.first, s) == hipSuccess ? PLACE3D_OK : PLACE3D_ERR_HIP;
 }
-int prof_end(place3d_ctx* c, hipStream_t s) {
+int prof_end(place3d_ctx* c, hipStream_t s, int launches) {
   if (c->prof_pending.empty()) return PLACE3D_OK;
+  c->prof_pending.back().launches = launches;
   return hipEventRecord(c->prof_pending.back().b, s) == hipSuccess ? PLACE3D_OK : PLACE3D_ERR_HIP;
 }
 int hip_fail(place3d_ctx* c, hipError_t e, const char* where) {
@@ -430,7 +431,7 @@ int32_t place3d_destroy(place3d_ctx* ctx) {
 
 int32_t place3d_profile_enable(place3d_ctx* ctx, int32_t on) {
   if (!ctx) return PLACE3D_ERR_ARG;
-  ctx->prof_on = on != 0;
+  ctx->prof_mask = (uint32_t)on & ((1u << PLACE3D_NSTAGES) - 1u);
   return PLACE3D_OK;
 }
 
@@ -442,7 +443,7 @@ int32_t place3d_profile_read(place3d_ctx* ctx, int32_t stage, double* ms, int64_
     float t = 0.f;
     P3D_HIP(ctx, hipEventElapsedTime(&t, r.a, r.b));
     ctx->prof_ms[r.stage] += t;
-    ctx->prof_count[r.stage] += 1;
+    ctx->prof_count[r.stage] += r.launches;
     ctx->prof_free.push_back({r.a, r.b});
   }
   ctx->prof_pending.clear();

@@ -85,13 +85,13 @@ struct SplitChain {
 }  // namespace p3d
 
 namespace p3d {
-struct ProfRec { int stage; hipEvent_t a, b; };
+struct ProfRec { int stage; hipEvent_t a, b; int launches; };
 }
 
 struct place3d_ctx {
   place3d_problem prob;
   // optional per-stage event profiler
-  bool prof_on = false;
+  uint32_t prof_mask = 0;              // stages whose launches are bracketed by events
   std::vector<p3d::ProfRec> prof_pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
   double prof_ms[PLACE3D_NSTAGES] = {0};
@@ -199,16 +199,19 @@ __host__ __device__ inline int xcd_swizzle(int b, int nb) {
 
 // Profiler brackets (no-ops unless profiling is on).  prof_end records on the same stream.
 int prof_begin(place3d_ctx* c, int stage, hipStream_t s);
-int prof_end(place3d_ctx* c, hipStream_t s);
+int prof_end(place3d_ctx* c, hipStream_t s, int launches);
 
+// One event pair per scope; `launches` is how many kernel launches the scope holds (a scope
+// around several consecutive launches of one stage perturbs the stream less than one per launch)
 struct ProfScope {
   place3d_ctx* c;
   hipStream_t s;
   bool on;
-  ProfScope(place3d_ctx* c_, int stage, hipStream_t s_) : c(c_), s(s_), on(c_->prof_on) {
+  int launches = 1;
+  ProfScope(place3d_ctx* c_, int stage, hipStream_t s_) : c(c_), s(s_), on((c_->prof_mask >> stage) & 1u) {
     if (on) prof_begin(c, stage, s);
   }
-  ~ProfScope() { if (on) prof_end(c, s); }
+  ~ProfScope() { if (on) prof_end(c, s, launches); }
 };
 
 // ---- launchers implemented in the .hip sources (all enqueue only) ----

@@ -530,13 +530,14 @@ __global__ void k_panel(const float* __restrict__ src, int ld, int trans, int ro
   lo[t] = rne16(v - __uint_as_float((unsigned)hv << 16));
 }
 
+// the caller brackets its consecutive launches with one profiler scope and counts them in `made`
 template <int KIND>
-int launch(place3d_ctx* c, SArgs& a, int njobs, hipStream_t s) {
+int launch(place3d_ctx* c, SArgs& a, int njobs, hipStream_t s, int& made) {
   const long long tiles = (long long)a.ntm * a.ntn * njobs;
   if (tiles <= 0) return PLACE3D_OK;
   if (tiles > 0x7fffffffLL) return set_err(c, PLACE3D_ERR_SIZE, "contraction grid too large");
   for (int i = njobs; i < kMaxJobs; ++i) a.job[i] = a.job[0];
-  ProfScope prof_(c, PLACE3D_STAGE_GEMM, s);
+  ++made;
   const dim3 grid((unsigned)tiles), block(256);
   // three stages for the launches of one workgroup per compute unit, two for the x inverse,
   // whose 768 workgroups then run two per compute unit
@@ -601,6 +602,9 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
                        q.xs[0].h, q.xs[0].l, q.xs[1].h, q.xs[1].l);
     P3D_LAUNCH(c, "k_fold_split_x");
   }
+  // the four contractions run back to back on s: one profiler scope for all of them
+  ProfScope gemm_(c, PLACE3D_STAGE_GEMM, s);
+  gemm_.launches = 0;
   // x forward
   {
     a.ntm = nz * ((q.hy + 63) / 64); a.ntn = (q.hx + kTile - 1) / kTile; a.ksteps = q.rx / kStep;
@@ -608,7 +612,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     for (int i = 0; i < 2; ++i)
       a.job[i] = SJob{q.xs[i].h, q.xs[i].l, q.fx[i].h, q.fx[i].l, 0, 0, i,
                       q.ys[0].h, q.ys[0].l, q.ys[1].h, q.ys[1].l, nullptr, 1.f};
-    if ((rc = launch<XF>(c, a, 2, s))) return rc;
+    if ((rc = launch<XF>(c, a, 2, s, gemm_.launches))) return rc;
   }
   // y forward and the z mixing of the coefficients
   {
@@ -616,7 +620,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     a.ra = q.hy; a.rb = nz * nx; a.ro = nz * nx;
     for (int i = 0; i < 2; ++i)
       a.job[i] = SJob{q.fy[i].h, q.fy[i].l, q.ys[i].h, q.ys[i].l, 0, 0, i, q.bb.h, q.bb.l, nullptr, nullptr, nullptr, 1.f};
-    if ((rc = launch<YF>(c, a, 2, s))) return rc;
+    if ((rc = launch<YF>(c, a, 2, s, gemm_.launches))) return rc;
   }
   // y inverse and unfold
   const bool need_g = phi || ex || ez, need_h = ey != nullptr;
@@ -626,7 +630,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     int nj = 0;
     if (need_g) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.gy.h, q.gy.l, 0, 0, 0, q.vg.h, q.vg.l, nullptr, nullptr, nullptr, 1.f};
     if (need_h) a.job[nj++] = SJob{q.bb.h, q.bb.l, q.hy_s.h, q.hy_s.l, 0, 0, 1, q.vh.h, q.vh.l, nullptr, nullptr, nullptr, 1.f};
-    if ((rc = launch<YI>(c, a, nj, s))) return rc;
+    if ((rc = launch<YI>(c, a, nj, s, gemm_.launches))) return rc;
   }
   // x inverse, even and odd frequency halves into two accumulators; unfold and z mixing in the
   // epilogue (Ex = Gz^T Vg Hx, Ey = Gz^T Vh Gx, Ez = Hz^T Vg Gx, phi = Gz^T Vg Gx)
@@ -644,7 +648,7 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
     for (int i = 0; i < no; ++i)
       a.job[nj++] = SJob{o[i].in->h, o[i].in->l, o[i].basis->h, o[i].basis->l, 0, 0, o[i].zsin,
                          nullptr, nullptr, nullptr, nullptr, o[i].out, o[i].sg};
-    if ((rc = launch<XI>(c, a, nj, s))) return rc;
+    if ((rc = launch<XI>(c, a, nj, s, gemm_.launches))) return rc;
   }
   return PLACE3D_OK;
 }

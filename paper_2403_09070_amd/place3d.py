@@ -294,8 +294,12 @@ class Problem:
         _check(lib().place3d_gp_init(self._ctx, ctypes.byref(cs), _ptr(xyz0), _stream()), self._ctx)
         return st
 
-    def profile(self, on=True):
-        _check(lib().place3d_profile_enable(self._ctx, int(on)), self._ctx)
+    def profile(self, on=True, stages=None):
+        """Bracket the launches of the named stages (all stages by default) with HIP events."""
+        mask = 0
+        if on:
+            mask = 0xFF if stages is None else sum(1 << STAGES.index(k) for k in stages)
+        _check(lib().place3d_profile_enable(self._ctx, int(mask)), self._ctx)
 
     def profile_read(self, reset=True):
         """{stage: (gpu milliseconds, launches)} since the last reset (waits for the events)."""
