@@ -20,7 +20,9 @@ timed steps.  The CPU baseline is the FP64 oracle on a bounded sample of the sam
 ``--ablation-csv``): the mixed-size preconditioner against the ePlace and ePlace3D forms on the
 macro-heavy 200k-cell workload from a clustered start.  ``--ablation algo`` times the density map
 and the wirelength call with the paper's baseline algorithms (instance-parallel macro scatter,
-O(|P_e|^2) FDA) against the default ones on the 1.2M-cell workload.
+O(|P_e|^2) FDA) against the default ones on the 1.2M-cell workload.  ``--ablation converge`` runs
+global placement on the 4M-cell workload from a clustered start until the overflow is below 0.1,
+for the plain, mixed and autograd forms.
 """
 from __future__ import annotations
 
@@ -70,10 +72,11 @@ def density_bytes(n, bins):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
 
 
-def recorded_traffic(stage, form):
+def recorded_traffic(stage, form, workload):
     """HBM bytes per launch of a stage, from the rocprofv3 FETCH_SIZE / WRITE_SIZE counts recorded in
     profiles/hbm_traffic.txt (already scaled by the copy-kernel factors noted there), or None when
-    nothing is recorded for this stage and form or the stage's kernel source has changed since."""
+    nothing is recorded for this stage, form and workload or the stage's kernel source has changed
+    since."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -81,7 +84,7 @@ def recorded_traffic(stage, form):
         if not line.startswith("stage="):
             continue
         rec = dict(kv.split("=", 1) for kv in line.split())
-        if rec.get("stage") != stage or rec.get("form") != form:
+        if rec.get("stage") != stage or rec.get("form") != form or rec.get("workload") != workload:
             continue
         src = os.path.join(ROOT, rec["source"])
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
@@ -310,6 +313,51 @@ def algo_ablation(args, log):
                       "paper_context": {"density": 4.7, "fda": 1.7}}), flush=True)
 
 
+def converge_run(args, log):
+    """Global placement from a clustered start until the larger per-die overflow falls below
+    --converge-overflow (or --converge-max iterations), for the plain (float32, field gather),
+    mixed (split-bf16, field gather) and autograd (split-bf16, exact adjoint) forms from the same
+    start; the host reads the overflow and HPWL back every 10 iterations, inside the timed loop,
+    as a placer's convergence check does."""
+    import torch
+    from paper_2403_09070_amd import place3d, synth
+    case = synth.centre_start(synth.make_case(args.config, args.seed), sigma=args.ablation_spread, seed=args.seed + 1)
+    forms = {"plain": (place3d.FP32, place3d.DGRAD_FIELD), "mixed": (place3d.BF16X3, place3d.DGRAD_FIELD),
+             "autograd": (place3d.BF16X3, place3d.DGRAD_ADJOINT)}
+    out = {}
+    for name in args.forms.split(","):
+        precision, dgrad = forms[name]
+        prob = place3d.Problem.from_case(case, precision=precision, dgrad=dgrad)
+        st = prob.gp_init(case.xyz0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, s = 0, None
+        while it < args.converge_max:
+            for _ in range(10):
+                prob.step(st)
+            it += 10
+            s = st.read()
+            if max(s["ovfl_bot"], s["ovfl_top"]) < args.converge_overflow:
+                break
+            if it % 200 == 0:
+                log(f"  {name} it {it}: hpwl {s['hpwl']:.5e} ovfl {s['ovfl_bot']:.3f}/{s['ovfl_top']:.3f}")
+        dt = time.perf_counter() - t0
+        out[name] = dict(iterations=it, seconds=round(dt, 3), iters_per_s=round(it / dt, 1), hpwl=s["hpwl"],
+                         ovfl=[s["ovfl_bot"], s["ovfl_top"]], ncut=s["ncut"],
+                         reached=max(s["ovfl_bot"], s["ovfl_top"]) < args.converge_overflow)
+        log(f"[converge] {name}: {out[name]}")
+        del prob
+        torch.cuda.empty_cache()
+    if "plain" in out:
+        for name in out:
+            out[name]["hpwl_vs_plain"] = out[name]["hpwl"] / out["plain"]["hpwl"]
+            out[name]["time_vs_plain"] = out["plain"]["seconds"] / out[name]["seconds"]
+    print(json.dumps({"run": "to overflow", "workload": f"{args.config} seed {args.seed}: {case.meta['n_cells']} "
+                      f"cells + {case.meta['n_macros']} macros, {case.n_nets} nets, {case.n_pins} pins, grid "
+                      f"{case.nx}x{case.ny}x{case.nz}, clustered start (sigma {args.ablation_spread} of the die), "
+                      f"no fillers", "target_overflow": args.converge_overflow, "forms": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,12 +371,14 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
-    ap.add_argument("--ablation", choices=["precond", "algo"], default=None,
+    ap.add_argument("--ablation", choices=["precond", "algo", "converge"], default=None,
                     help="run the preconditioner ablation instead of the timing benchmark")
     ap.add_argument("--ablation-iters", type=int, default=1000)
     ap.add_argument("--ablation-every", type=int, default=5)
     ap.add_argument("--ablation-spread", type=float, default=0.02)
     ap.add_argument("--ablation-stop", type=float, default=0.1)
+    ap.add_argument("--converge-overflow", type=float, default=0.1)
+    ap.add_argument("--converge-max", type=int, default=3000)
     ap.add_argument("--ablation-util", type=float, default=0.8,
                     help="maximum utilisation u of both dies for the fillers (0: no fillers)")
     ap.add_argument("--ablation-csv", default=None)
@@ -349,6 +399,12 @@ def main():
     if args.ablation == "algo":
         args.config = args.config or "c4"
         algo_ablation(args, log)
+        return
+    if args.ablation == "converge":
+        args.config = args.config or "c5"
+        if args.forms == "plain,mixed":
+            args.forms = "plain,mixed,autograd"
+        converge_run(args, log)
         return
     args.config = args.config or "c4"
     if args.copy_mb > 0:
@@ -396,7 +452,7 @@ def main():
         lps = launches / (args.steps if key == head["timed"][0] else ps)
         avg_ms = ms / launches
         achieved = (work / lps) / (avg_ms / 1e3)        # per launch / average launch duration
-        traffic = recorded_traffic(key, head_name)
+        traffic = recorded_traffic(key, head_name, args.config)
         roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": key,
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_step": lps,

@@ -18,6 +18,7 @@ instance counts, net-degree laws, macro mixes and grid sizes of the five workloa
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -31,7 +32,6 @@ KIND_ZFIXED = 8          # z held at its start
 
 TOP_SCALE = 0.7          # top-die size and pin-offset scale
 WINDOW = 256             # index half-window of a local net
-LOCAL_FRACTION = 0.9     # share of nets drawn from an index window
 MACRO_PIN_PROB = 0.02    # chance that a net swaps one member for a macro
 
 
@@ -55,6 +55,7 @@ class Config:
     row_top: float = 0.7
     beta: float = 10.0
     alpha0: float = 3.5e-3
+    local_fraction: float = 0.9  # share of nets drawn from an index window (0: every net uniform)
 
 
 CONFIGS = {
@@ -66,6 +67,9 @@ CONFIGS = {
     "c5": Config("c5", 4_000_000, 4_400_000, 8000.0, 2048, 2048, 4, ("mix", 0.0346, 100),
                  ("zipf", 200, 0.05, 1.3528)),
 }
+# the 1.2M-cell netlist with every net drawn uniformly: no index locality, the worst case for the
+# position gathers
+CONFIGS["c4u"] = dataclasses.replace(CONFIGS["c4"], name="c4u", local_fraction=0.0)
 
 
 @dataclass
@@ -198,7 +202,7 @@ def make_case(name: str = "c1", seed: int = 2403, config: Config | None = None) 
     m = cfg.n_nets
     deg = _degree_law(rng, cfg.degree, m).astype(np.int64)
     anchors = rng.integers(0, nc, size=m)
-    local = rng.random(m) < LOCAL_FRACTION
+    local = rng.random(m) < cfg.local_fraction
     members = [None] * m
     by_deg = {}
     for d in np.unique(deg):
