@@ -8,8 +8,11 @@ Workload: the 1.2M-cell synthetic netlist (150 macros, 1.3M nets, ~4.5M pins, gr
   autograd (optional, --forms) -- split-bf16 contractions with the exact-adjoint density gradient
 A step is one full GP iteration (place3d_step): density map, spectral solve, density gradient,
 bistratal WA wirelength with the FDA z-gradient, preconditioned Nesterov move.  `value` is the
-mixed form's iterations/s over exactly --steps timed steps after --warmup untimed ones; the plain
-form's rate, both final D2D HPWLs and their relative difference are reported beside it.
+mixed form's iterations/s over exactly --steps timed steps after --warmup warm-up and
+--profile-steps untimed ones, with the metrics read back to the host every --readback-every
+steps inside the timed loop (a placer's convergence check); the plain form's rate, both final
+D2D HPWLs and their relative difference are reported beside it.  With --repeats R the forms
+alternate R times, each repeat from the same start, and the median rate is reported.
 
 The roofline entry is for the stage with the largest GPU time in the mixed step (found in an
 untimed block of steps with every stage's launches bracketed by HIP events); its average launch
@@ -93,47 +96,66 @@ def recorded_traffic(stage, form, workload):
     return None
 
 
-def run_form(case, precision, dgrad, steps, warmup, profile_steps, log, events=True):
-    """Warm-up steps, then (untimed) profile_steps steps with every stage's launches bracketed by
-    HIP events, which give the per-stage breakdown and the dominant stage; then the timed steps,
-    with events around the dominant stage's launches only (one pair per step for the contractions,
-    which run back to back), which give its average launch time under the timed conditions.
-    With events=False the profile steps run without events and the timed steps are untouched."""
+def run_forms(case, names, forms, args, log):
+    """Time the forms in alternation, args.repeats times each, every repeat from a fresh
+    gp_init at the same start: warm-up steps, args.profile_steps untimed steps, then args.steps
+    timed steps with the host reading the metrics back every args.readback_every steps (a placer's
+    convergence check).  In the first repeat the reported form's untimed steps carry HIP events
+    around every stage's launches, which give the per-stage breakdown and the dominant stage; its
+    timed steps then carry events around that stage's launches only (one pair per step for the
+    four back-to-back contractions), which give its average launch time under the timed
+    conditions.  The other forms run without events.  Rates are medians over the repeats."""
+    import statistics
     import torch
     from paper_2403_09070_amd import place3d
-    prob = place3d.Problem.from_case(case, precision=precision, dgrad=dgrad)
-    st = prob.gp_init(case.xyz0)
-    for _ in range(warmup):
-        prob.step(st)
-    prof, dominant = None, None
-    if profile_steps > 0 and not events:
-        for _ in range(profile_steps):
-            prob.step(st)
-    elif profile_steps > 0:
-        prob.profile(True)
-        for _ in range(profile_steps):
-            prob.step(st)
-        torch.cuda.synchronize()
-        prof = prob.profile_read(reset=True)
-        prob.profile(False)
-        dominant = max(prof, key=lambda k: prof[k][0])
-        prob.profile(True, stages=(dominant,))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        prob.step(st)
-        if (k + 1) % 100 == 0:
-            log(f"  step {k + 1}/{steps}")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    timed = None
+    head = "mixed" if "mixed" in names else names[0]
+    probs = {nm: place3d.Problem.from_case(case, precision=forms[nm][0], dgrad=forms[nm][1]) for nm in names}
+    out = {nm: dict(runs=[], state=None, prof=None, timed=None) for nm in names}
+    dominant, ev_ms, ev_n = None, 0.0, 0
+    for r in range(args.repeats):
+        for nm in names:
+            prob = probs[nm]
+            st = prob.gp_init(case.xyz0)
+            for _ in range(args.warmup):
+                prob.step(st)
+            events = nm == head
+            if events and r == 0 and args.profile_steps > 0:
+                prob.profile(True)
+                for _ in range(args.profile_steps):
+                    prob.step(st)
+                torch.cuda.synchronize()
+                prof = prob.profile_read(reset=True)
+                prob.profile(False)
+                out[nm]["prof"] = prof
+                dominant = max(prof, key=lambda k: prof[k][0])
+            else:
+                for _ in range(args.profile_steps):
+                    prob.step(st)
+            if events and dominant is not None:
+                prob.profile(True, stages=(dominant,))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                prob.step(st)
+                if args.readback_every and (k + 1) % args.readback_every == 0:
+                    st.read()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if events and dominant is not None:
+                ms, cnt = prob.profile_read(reset=True)[dominant]
+                prob.profile(False)
+                ev_ms, ev_n = ev_ms + ms, ev_n + cnt
+            out[nm]["runs"].append(args.steps / dt)
+            out[nm]["state"] = st.read()
+            log(f"[bench] repeat {r} form {nm}: {args.steps / dt:.1f} it/s, hpwl {out[nm]['state']['hpwl']:.6e}")
+    for nm in names:
+        ips = statistics.median(out[nm]["runs"])
+        out[nm].update(ips=ips, ms=1e3 / ips)
     if dominant is not None:
-        timed = (dominant, prob.profile_read(reset=True)[dominant])
-        prob.profile(False)
-    res = st.read()
-    del prob
+        out[head]["timed"] = (dominant, (ev_ms, ev_n))
+    del probs
     torch.cuda.empty_cache()
-    return dict(seconds=dt, ips=steps / dt, ms=1e3 * dt / steps, state=res, prof=prof, timed=timed)
+    return out
 
 
 def cpu_baseline(case, frac=4):
@@ -366,6 +388,9 @@ def main():
     ap.add_argument("--config", default=None, help="workload (default c4; c2 for --ablation)")
     ap.add_argument("--seed", type=int, default=2403)
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=1, help="timed repeats per form (median reported)")
+    ap.add_argument("--readback-every", type=int, default=10,
+                    help="read the metrics back to the host every this many timed steps (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,mixed")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -419,14 +444,10 @@ def main():
     case = synth.make_case(args.config, args.seed)
     forms = {"plain": (place3d.FP32, place3d.DGRAD_FIELD), "mixed": (place3d.BF16X3, place3d.DGRAD_FIELD),
              "autograd": (place3d.BF16X3, place3d.DGRAD_ADJOINT)}
-    res = {}
-    for name in args.forms.split(","):
-        log(f"[bench] form {name}: warmup {args.warmup}, timed {args.steps}")
-        # only the reported form's steps carry profiling events; the others run untouched
-        head_form = "mixed" if "mixed" in args.forms.split(",") else args.forms.split(",")[0]
-        res[name] = run_form(case, *forms[name], args.steps, args.warmup, args.profile_steps, log,
-                             events=name == head_form)
-        log(f"[bench] form {name}: {res[name]['ips']:.1f} it/s, hpwl {res[name]['state']['hpwl']:.6e}")
+    names = args.forms.split(",")
+    log(f"[bench] forms {names}: {args.repeats} repeats of warmup {args.warmup} + {args.profile_steps} untimed + "
+        f"{args.steps} timed steps")
+    res = run_forms(case, names, forms, args, log)
     head = res.get("mixed") or res[list(res)[0]]
     head_name = "mixed" if "mixed" in res else list(res)[0]
     bf16x3 = head_name in ("mixed", "autograd")
@@ -449,7 +470,7 @@ def main():
         if key not in cands:
             key, (ms, launches) = "gemm", prof["gemm"]
         bound, work, peak, unit = cands[key]
-        lps = launches / (args.steps if key == head["timed"][0] else ps)
+        lps = launches / (args.steps * args.repeats if key == head["timed"][0] else ps)
         avg_ms = ms / launches
         achieved = (work / lps) / (avg_ms / 1e3)        # per launch / average launch duration
         traffic = recorded_traffic(key, head_name, args.config)
@@ -462,6 +483,8 @@ def main():
     line = {
         "metric": METRIC, "value": round(head["ips"], 2), "unit": "iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms"], 4),
+        "repeats": args.repeats, "readback_every": args.readback_every,
+        "runs_iters_per_s": [round(v, 1) for v in head["runs"]],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16x3/f32" if bf16x3 else "f32", "data": "synthetic",
         "config": {"workload": f"{args.config}: {n - case.meta['n_macros']} cells + {case.meta['n_macros']} macros, "
