@@ -152,6 +152,24 @@ def test_nesterov_converges_on_a_convex_quadratic():
     assert np.abs(st.u - target).max() < 1e-8 * err0
 
 
+def test_lipschitz_step_is_exact_on_a_uniform_quadratic():
+    """Closed form: for the gradient c (v - v*) the estimate |dv| / |dg| is 1/c whatever the two
+    points, so the first move lands on v* exactly; with a_0 = 1 the momentum coefficient
+    (a_0 - 1)/a_1 is zero, so v_1 = u_1, and a_1 = (1 + sqrt(5))/2."""
+    rng = np.random.default_rng(1)
+    c = 2.5
+    target = rng.uniform(10, 90, size=(3, 40))
+    v0 = rng.uniform(10, 90, size=(3, 40))
+    grad = lambda v: c * (v - target)  # noqa: E731
+    vp = v0 + rng.normal(scale=3.0, size=v0.shape)
+    st = opt.GPState(u=v0.copy(), v=v0.copy(), v_prev=vp, g_prev=grad(vp), a=1.0, lam=0.0)
+    u, v, a, step = opt.nesterov_update(st, grad(v0), lambda p: p, np.ones(40, dtype=bool))
+    assert abs(step - 1.0 / c) < 1e-14
+    np.testing.assert_allclose(u, target, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(v, u)
+    assert abs(a - (1.0 + 5.0 ** 0.5) / 2.0) < 1e-15
+
+
 def test_clamp_keeps_instances_inside_region():
     c = _case(3)
     pb = opt.problem_of(c)
