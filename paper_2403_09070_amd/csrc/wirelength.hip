@@ -496,10 +496,9 @@ __global__ void k_wl_finish_z(int n, const float* __restrict__ gz_wa, const floa
 // thread per pin slot re-evaluates its net's exact bistratal wirelength with the owner on the top
 // die and on the bottom die from all |P_e| pins, and overwrites the FDA difference k_wl_nets
 // stored for the slot.  Coordinates are relative to the net's first owner, as in k_wl_nets.
-__device__ __forceinline__ void set_put(float& mx, float& mn, int& cnt, float u) {
+__device__ __forceinline__ void set_put(float& mx, float& mn, float u) {
   mx = fmaxf(mx, u);
   mn = fminf(mn, u);
-  ++cnt;
 }
 
 __global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, float half_dz, float four_over_dz,
@@ -521,12 +520,12 @@ __global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, floa
   const float xa = q0.x, ya = q0.y;
   float txM = kNegInf, txm = kPosInf, tyM = kNegInf, tym = kPosInf;
   float bxM = kNegInf, bxm = kPosInf, byM = kNegInf, bym = kPosInf;
-  int ct = 0, cb = 0, cdummy = 0;
+  int ct = 0, cb = 0;                            // pins per die set
   for (int q = b; q < e; ++q) {                  // every other pin, on its own die
     if (q == s) continue;
     const PinRel p = load_pin(xyzp, pin_node, off, q, half_dz, xa, ya);
-    if (p.top) { set_put(txM, txm, ct, p.ux); set_put(tyM, tym, cdummy, p.uy); }
-    else       { set_put(bxM, bxm, cb, p.ux); set_put(byM, bym, cdummy, p.uy); }
+    if (p.top) { set_put(txM, txm, p.ux); set_put(tyM, tym, p.uy); ++ct; }
+    else       { set_put(bxM, bxm, p.ux); set_put(byM, bym, p.uy); ++cb; }
   }
   const PinRel me = load_pin(xyzp, pin_node, off, s, half_dz, xa, ya);
   const float xt = me.top ? me.ux : me.fx, yt = me.top ? me.uy : me.fy;   // the owner's pin on top
