@@ -119,3 +119,17 @@ def test_energy_gradient_with_respect_to_density_is_potential_times_bin_volume()
         dn = poisson.energy(rho - e, poisson.solve(rho - e, geo, want=("phi",))["phi"], geo)
         fd = (up - dn) / 2e-3
         assert abs(fd - phi[idx] * geo.vol_bin) < 1e-9 * max(1.0, abs(fd))
+
+
+def test_potential_map_is_symmetric():
+    """<phi(a), b> = <a, phi(b)>: the forward coefficients and the inverse sum share the cosine
+    basis and the 1/|omega|^2 weights sit on the diagonal, so rho -> phi is a symmetric operator
+    (what lets the autograd form reuse the solve as its own adjoint)."""
+    rng = np.random.default_rng(3)
+    geo = Geometry(30.0, 20.0, 12, 10, 4)
+    a = rng.normal(size=(geo.nz, geo.ny, geo.nx))
+    b = rng.normal(size=(geo.nz, geo.ny, geo.nx))
+    pa = poisson.solve(a, geo, want=("phi",))["phi"]
+    pb = poisson.solve(b, geo, want=("phi",))["phi"]
+    lhs, rhs = float(np.sum(pa * b)), float(np.sum(a * pb))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
