@@ -630,14 +630,32 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
                                                       const float* __restrict__ mz, FoldX fx, float4* __restrict__ out,
                                                       const float4* __restrict__ lrec, int nlarge,
                                                       float4* __restrict__ lpart) {
-  extern __shared__ float S[];
+  extern __shared__ __align__(16) float S[];
   __shared__ int hits[kTileThreads];
   __shared__ int wave_cnt[kTileThreads / kWave];
   __shared__ float rsh[3][kTileThreads / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
-  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+  // natural-order maps whose rows and tile width are multiples of 4 bins: stage 4 bins per load
+  // (the row start tb.x0 + lx is then a multiple of 4, so the 16-byte loads are aligned)
+  const bool vec = !fx.on && (g.nx & 3) == 0 && (tb.wx & 3) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(mx) | reinterpret_cast<uintptr_t>(my) |
+                     reinterpret_cast<uintptr_t>(mz)) & 15) == 0;
+  for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, d = a;
+    if (lx < tb.wx && ly < tb.wy) {
+      const size_t q = bin_index(g, bz, tb.y0 + ly, tb.x0 + lx);
+      a = *reinterpret_cast<const float4*>(mx + q);
+      b = *reinterpret_cast<const float4*>(my + q);
+      d = *reinterpret_cast<const float4*>(mz + q);
+    }
+    *reinterpret_cast<float4*>(S + k) = a;
+    *reinterpret_cast<float4*>(S + tsz + k) = b;
+    *reinterpret_cast<float4*>(S + 2 * tsz + k) = d;
+  }
+  for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     float a = 0.f, b = 0.f, d = 0.f;
     if (lx < tb.wx && ly < tb.wy) {
