@@ -502,7 +502,23 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   __syncthreads();
   float ex[2] = {0.f, 0.f};
   const int half = g.nz / 2;
-  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+  // rows and tile width multiples of 4 bins: write 4 bins per store (aligned, as in the gather)
+  const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(rho) & 15) == 0;
+  for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+    if (lx < tb.wx && ly < tb.wy) {
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned long long real = S64[k + j];
+        v[j] = (float)((double)(fillers ? real + SF[k + j] : real) * kUnfix);
+        const float vr = fillers ? (float)((double)real * kUnfix) : v[j];
+        ex[bz < half ? 0 : 1] += fmaxf(vr - target, 0.f) * g.vol_bin;
+      }
+      *reinterpret_cast<float4*>(rho + bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     if (lx < tb.wx && ly < tb.wy) {
       const unsigned long long real = S64[k];
