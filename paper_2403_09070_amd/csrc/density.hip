@@ -892,14 +892,22 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
                                                        const float* __restrict__ m, float4* __restrict__ out,
                                                        const float4* __restrict__ lrec, int nlarge,
                                                        float4* __restrict__ lpart) {
-  extern __shared__ float S[];
+  extern __shared__ __align__(16) float S[];
   __shared__ int hits[kTileThreads];
   __shared__ int wave_cnt[kTileThreads / kWave];
   __shared__ float rsh[6][kTileThreads / kWave];
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
-  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+  // rows and tile width multiples of 4 bins: stage 4 bins per load (aligned, as in the gather)
+  const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0;
+  for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
+    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+    *reinterpret_cast<float4*>(S + k) =
+        (lx < tb.wx && ly < tb.wy) ? *reinterpret_cast<const float4*>(m + bin_index(g, bz, tb.y0 + ly, tb.x0 + lx))
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
   }
