@@ -17,15 +17,21 @@
  *                                                              Sec. IV-B)
  *   place3d_step        one GP iteration: all of the above, the mixed-size preconditioner
  *                       (Eq. improved-precond) and a Nesterov move
+ *   place3d_plan_fillers host-side sizing of z-fixed and free fillers (Eqs. filler-vol,
+ *                       free-filler-vol), appended by the caller as instances of kind FILLER
+ *
+ * Instance kinds (PLACE3D_KIND_*) mark macros, fixed instances, fillers and z-held instances;
+ * place3d_problem.options selects the paper's baseline algorithms for comparison (Sec. IV).
  *
  * Conventions (all calls):
- *   - Device pointers unless stated.  Coordinates are instance centres in length units,
+ *   - Device pointers unless stated (place3d_plan_fillers takes host arrays).  Coordinates are instance centres in length units,
  *     structure-of-arrays float32 [3][n] (x row, y row, z row).  Maps are float32
  *     [Nz][Ny][Nx], x fastest.  CSR arrays are int32, pins sorted by net,
  *     net_start[n_nets] == n_pins.
  *   - The die depth is derived, d_z = N_z (w_b + h_b)/2 with w_b = d_x/N_x, h_b = d_y/N_y
  *     (Sec. V-A); an instance's centre z decides its die: top iff z > d_z/2.
- *   - Gradients are d(objective)/d(coordinate), not forces.  Fixed instances get 0.
+ *   - Gradients are d(objective)/d(coordinate), not forces.  Fixed instances get 0; z-held
+ *     instances get 0 in z inside place3d_step and place3d_gp_init.
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream) and
  *     never synchronises, except place3d_create, which reads the netlist back to the host once.
  *   - The caller owns all device memory (inputs, outputs and the workspace).  The library never
