@@ -38,6 +38,16 @@ struct Foot {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// A z within 2^-20 d_z of a bound of the movable range [d_z/4, 3 d_z/4] is on that bound (the
+// clamp rounds the bounds to float32): -1 lower, +1 upper, 0 neither.
+constexpr float kClampBand = 9.5367431640625e-07f;   // 2^-20
+__device__ __forceinline__ int z_bound(const Geom& g, float z) {
+  const float tol = kClampBand * g.dz;
+  if (fabsf(z - 0.25f * g.dz) <= tol) return -1;
+  if (fabsf(z - 0.75f * g.dz) <= tol) return 1;
+  return 0;
+}
+
 // footprint from the centre in local coordinates (rx = x - cbx w_b) and the stretched half extents
 __device__ __forceinline__ void foot_local(const Geom& g, Foot& f, int cbx, int cby, float rx, float ry, float z,
                                            float hw, float hh) {
@@ -84,7 +94,9 @@ __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict
     const float t = 2.f * zc / g.dz;
     w = (t - 0.5f) * wtop + (1.5f - t) * wbot;
     h = (t - 0.5f) * htop + (1.5f - t) * hbot;
-    if (z >= zl && z <= zh) {
+    // the size transition's slope, inside the movable range with its bounds (where the adjoint
+    // takes the derivative into the range)
+    if ((z > zl && z < zh) || z_bound(g, z) != 0) {
       f.dw = 2.f / g.dz * (wtop - wbot);
       f.dh = 2.f / g.dz * (htop - hbot);
     }
@@ -148,23 +160,50 @@ __device__ __forceinline__ float len_z(const Geom& g, const Foot& f, int b) {
   return fmaxf(0.f, fminf(f.z1 - lo, g.db) - fmaxf(f.z0 - lo, 0.f));
 }
 
-// bin holding an unclipped edge (or -1 when the region clips that edge)
-__device__ __forceinline__ int edge_bin_x(const Geom& g, const Foot& f, float redge) {
-  const float ox = (float)f.cbx * g.wb;
-  if (!(redge > -ox && redge < g.dx - ox)) return -1;
-  const int b = f.cbx + (int)floorf(redge * g.inv_wb);
-  return (b >= f.bx0 && b <= f.bx1) ? b : -1;
+// One-sided derivatives of the overlap lengths (the adjoint).  The map is piecewise linear in each
+// coordinate, with kinks where an edge meets a bin face or a face of the region.  Per axis the
+// derivative is taken from above (the coordinate growing), or from below when the unclipped
+// upper edge lies on or beyond the region's upper face; at the bounds of the movable range that
+// is the direction the clamp allows (into the range).  Moving that way an edge at e changes the
+// overlap of one bin: floor(e/s) from above if 0 <= e < L, ceil(e/s) - 1 from below if
+// 0 < e <= L, none otherwise (the region holds the edge).
+__device__ __forceinline__ int edge_bin(float e, float lo, float hi, float inv_step, bool down, int q0, int n) {
+  if (down ? !(e > lo && e <= hi) : !(e >= lo && e < hi)) return -1;
+  const float q = e * inv_step;
+  return clampi(q0 + (down ? (int)ceilf(q) - 1 : (int)floorf(q)), 0, n - 1);
 }
-__device__ __forceinline__ int edge_bin_y(const Geom& g, const Foot& f, float redge) {
-  const float oy = (float)f.cby * g.hb;
-  if (!(redge > -oy && redge < g.dy - oy)) return -1;
-  const int b = f.cby + (int)floorf(redge * g.inv_hb);
-  return (b >= f.by0 && b <= f.by1) ? b : -1;
+
+struct EdgeBins {
+  int xl, xh, yl, yh, zl, zh;   // bins whose overlap each edge changes, -1 for none
+  bool down_x, down_y, down_z;  // derivative from below along that axis
+};
+
+// the region's faces in the footprint's local planar coordinates (as foot_local clips them)
+__device__ __forceinline__ float2 local_faces(float die, int cb, double step) {
+  const double o = (double)cb * step;
+  return make_float2((float)-o, (float)((double)die - o));
 }
-__device__ __forceinline__ int edge_bin_z(const Geom& g, const Foot& f, float zedge) {
-  if (!(zedge > 0.f && zedge < g.dz)) return -1;
-  const int b = (int)floorf(zedge * g.inv_db);
-  return (b >= f.bz0 && b <= f.bz1) ? b : -1;
+
+__device__ __forceinline__ EdgeBins edge_bins(const Geom& g, const Foot& f) {
+  EdgeBins e;
+  const float2 fx = local_faces(g.dx, f.cbx, g.wbd), fy = local_faces(g.dy, f.cby, g.hbd);
+  e.down_x = f.rx1 >= fx.y;
+  e.down_y = f.ry1 >= fy.y;
+  e.xl = edge_bin(f.rx0, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
+  e.xh = edge_bin(f.rx1, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
+  e.yl = edge_bin(f.ry0, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
+  e.yh = edge_bin(f.ry1, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
+  const int zb = z_bound(g, f.z);
+  if (zb < 0) {            // on the lower bound: edges on the floor and the mid-plane, moving up
+    e.down_z = false; e.zl = 0; e.zh = g.nz / 2;
+  } else if (zb > 0) {     // on the upper bound: edges on the mid-plane and the ceiling, moving down
+    e.down_z = true; e.zl = g.nz / 2 - 1; e.zh = g.nz - 1;
+  } else {
+    e.down_z = f.rz1 >= g.dz;
+    e.zl = edge_bin(f.rz0, 0.f, g.dz, g.inv_db, e.down_z, 0, g.nz);
+    e.zh = edge_bin(f.rz1, 0.f, g.dz, g.inv_db, e.down_z, 0, g.nz);
+  }
+  return e;
 }
 
 __device__ __forceinline__ size_t bin_index(const Geom& g, int bz, int by, int bx) {
@@ -845,28 +884,54 @@ __global__ void k_gather_large(Geom g, const float* __restrict__ xyz, const floa
 // [bx0..bx1] x [by0..by1] x [bz0..bz1] (a sub-box of the footprint).
 struct AdjSums { float gx, gy, gz, xs, ys, all; };
 
+// widen [lo, hi] to an edge bin b (>= 0) lying inside the limits [l0, l1]
+__device__ __forceinline__ void widen(int& lo, int& hi, int b, int l0, int l1) {
+  if (b >= l0 && b <= l1) { lo = min(lo, b); hi = max(hi, b); }
+}
+
+// [bx0, bx1] x [by0, by1]: the footprint's bins inside the limits [xl0, xl1] x [yl0, yl1] (a
+// tile, or the grid); the loop also visits the edge bins inside the limits that lie just off
+// the footprint (an edge on a bin face).
 template <class MapAt>
 __device__ __forceinline__ AdjSums adjoint_sums(const Geom& g, const Foot& f, MapAt map_at, int bx0, int bx1,
-                                                int by0, int by1, int t0, int tstep, bool with_size_terms) {
-  const int ebx_lo = edge_bin_x(g, f, f.rx0), ebx_hi = edge_bin_x(g, f, f.rx1);
-  const int eby_lo = edge_bin_y(g, f, f.ry0), eby_hi = edge_bin_y(g, f, f.ry1);
-  const int ebz_lo = edge_bin_z(g, f, f.rz0), ebz_hi = edge_bin_z(g, f, f.rz1);
-  const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = f.bz1 - f.bz0 + 1;
+                                                int by0, int by1, int xl0, int xl1, int yl0, int yl1, int t0,
+                                                int tstep, bool with_size_terms) {
+  const EdgeBins e = edge_bins(g, f);
+  // the size transition moves the planar edges as z moves: an upper edge the way of dw/dz, a
+  // lower edge the other way, each with its own one-sided bin
+  int sxl = -1, sxh = -1, syl = -1, syh = -1;
+  if (with_size_terms) {
+    const float2 fx = local_faces(g.dx, f.cbx, g.wbd), fy = local_faces(g.dy, f.cby, g.hbd);
+    const bool hx = e.down_z != (f.dw < 0.f), hy = e.down_z != (f.dh < 0.f);   // upper edge moving down
+    sxl = edge_bin(f.rx0, fx.x, fx.y, g.inv_wb, !hx, f.cbx, g.nx);
+    sxh = edge_bin(f.rx1, fx.x, fx.y, g.inv_wb, hx, f.cbx, g.nx);
+    syl = edge_bin(f.ry0, fy.x, fy.y, g.inv_hb, !hy, f.cby, g.ny);
+    syh = edge_bin(f.ry1, fy.x, fy.y, g.inv_hb, hy, f.cby, g.ny);
+  }
+  int x0 = bx0, x1 = bx1, y0 = by0, y1 = by1, z0 = f.bz0, z1 = f.bz1;
+  widen(x0, x1, e.xl, xl0, xl1); widen(x0, x1, e.xh, xl0, xl1);
+  widen(x0, x1, sxl, xl0, xl1); widen(x0, x1, sxh, xl0, xl1);
+  widen(y0, y1, e.yl, yl0, yl1); widen(y0, y1, e.yh, yl0, yl1);
+  widen(y0, y1, syl, yl0, yl1); widen(y0, y1, syh, yl0, yl1);
+  widen(z0, z1, e.zl, 0, g.nz - 1); widen(z0, z1, e.zh, 0, g.nz - 1);
+  const int nbx = x1 - x0 + 1, nby = y1 - y0 + 1, nbz = z1 - z0 + 1;
   const int total = nbx * nby * nbz;
   AdjSums a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int q = t0; q < total; q += tstep) {
-    const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = f.bz0 + q / (nbx * nby);
+    const int bx = x0 + q % nbx, by = y0 + (q / nbx) % nby, bz = z0 + q / (nbx * nby);
     const float mv = map_at(bz, by, bx);
     const float lx = len_x(g, f, bx), ly = len_y(g, f, by), lz = len_z(g, f, bz);
-    const float fxh = (bx == ebx_hi) ? 1.f : 0.f, fxl = (bx == ebx_lo) ? 1.f : 0.f;
-    const float fyh = (by == eby_hi) ? 1.f : 0.f, fyl = (by == eby_lo) ? 1.f : 0.f;
-    const float fzh = (bz == ebz_hi) ? 1.f : 0.f, fzl = (bz == ebz_lo) ? 1.f : 0.f;
+    const float fxh = (bx == e.xh) ? 1.f : 0.f, fxl = (bx == e.xl) ? 1.f : 0.f;
+    const float fyh = (by == e.yh) ? 1.f : 0.f, fyl = (by == e.yl) ? 1.f : 0.f;
+    const float fzh = (bz == e.zh) ? 1.f : 0.f, fzl = (bz == e.zl) ? 1.f : 0.f;
     a.gx += (fxh - fxl) * ly * lz * mv;
     a.gy += lx * (fyh - fyl) * lz * mv;
     a.gz += lx * ly * (fzh - fzl) * mv;
     if (with_size_terms) {
-      a.xs += (fxh + fxl) * ly * lz * mv;
-      a.ys += lx * (fyh + fyl) * lz * mv;
+      const float sx = (bx == sxh ? 1.f : 0.f) + (bx == sxl ? 1.f : 0.f);
+      const float sy = (by == syh ? 1.f : 0.f) + (by == syl ? 1.f : 0.f);
+      a.xs += sx * ly * lz * mv;
+      a.ys += lx * sy * lz * mv;
       a.all += lx * ly * lz * mv;
     }
   }
@@ -920,7 +985,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     float3 r = make_float3(0.f, 0.f, 0.f);
     if (bx0 <= bx1 && by0 <= by1) {
-      const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, 0, 1, false);
+      const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0,
+                                     tb.y0 + tb.wy - 1, 0, 1, false);
       r = adjoint_finish(g, f, a);
     }
     out[e] = make_float4(r.x, r.y, r.z, 0.f);
@@ -933,7 +999,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
       const Foot h = foot_record(g, lrec, j);
       const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
       const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
-      AdjSums a = adjoint_sums(g, h, at, bx0, bx1, by0, by1, threadIdx.x, blockDim.x, true);
+      AdjSums a = adjoint_sums(g, h, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1,
+                               threadIdx.x, blockDim.x, true);
       float v[6] = {a.gx, a.gy, a.gz, a.xs, a.ys, a.all};
       for (int q = 0; q < 6; ++q) {
         for (int o = kWave / 2; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
@@ -990,7 +1057,8 @@ __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const flo
   const int i = list[blockIdx.x];
   const Foot f = footprint(g, xyz, size, kind[i], i);
   auto at = [&](int bz, int by, int bx) { return m[bin_index(g, bz, by, bx)]; };
-  AdjSums a = adjoint_sums(g, f, at, f.bx0, f.bx1, f.by0, f.by1, threadIdx.x, blockDim.x, true);
+  AdjSums a = adjoint_sums(g, f, at, f.bx0, f.bx1, f.by0, f.by1, 0, g.nx - 1, 0, g.ny - 1, threadIdx.x, blockDim.x,
+                           true);
   a.gx = block_sum<256>(a.gx, sh);
   a.gy = block_sum<256>(a.gy, sh);
   a.gz = block_sum<256>(a.gz, sh);

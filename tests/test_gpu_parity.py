@@ -149,6 +149,50 @@ def test_density_vjp(setup):
     assert err <= 1e-5
 
 
+def _clamped(case, seed):
+    """The case's start with a third of the movable instances on the lower z bound, a third on the
+    upper (the float32 bounds the step's clamp produces) and every movable macro against a die side
+    in x (even index) or y (odd index), at the size its z gives."""
+    geo = geometry_of(case)
+    f32 = np.float32
+    dz = f32(geo.dz)
+    xyz = case.xyz0.astype(np.float32).copy()
+    mov = np.nonzero((case.kind & 2) == 0)[0]
+    rng = np.random.default_rng(seed)
+    pick = rng.permutation(mov)
+    lo, hi = pick[: len(pick) // 3], pick[len(pick) // 3: 2 * len(pick) // 3]
+    xyz[2, lo] = f32(0.25) * dz
+    xyz[2, hi] = f32(0.75) * dz
+    macros = [i for i in mov if case.kind[i] & 1]
+    for k, i in enumerate(macros):
+        top = xyz[2, i] > f32(0.5) * dz
+        xyz[2, i] = f32(0.75) * dz if top else f32(0.25) * dz
+        w, h = (case.size[2, i], case.size[3, i]) if top else (case.size[0, i], case.size[1, i])
+        if k % 2 == 0:
+            xyz[0, i] = f32(0.5) * f32(w) if k % 4 == 0 else f32(geo.die_x) - f32(0.5) * f32(w)
+        else:
+            xyz[1, i] = f32(0.5) * f32(h) if k % 4 == 1 else f32(geo.die_y) - f32(0.5) * f32(h)
+    return xyz, np.concatenate([lo, hi])
+
+
+def test_density_vjp_at_the_clamp_bounds(setup):
+    """The exact adjoint where GP leaves most instances: on the bounds of the movable z range (every
+    z-edge on a bin face or the region's floor or ceiling) and macros against the die sides.  The
+    one-sided derivative into the range must match the oracle's, instance by instance."""
+    name, case, prob = setup
+    import torch
+    geo = geometry_of(case)
+    xyz, on_bound = _clamped(case, 1)
+    rng = np.random.default_rng(2)
+    gmap = rng.normal(size=(case.nz, case.ny, case.nx)).astype(np.float32)
+    g = prob.density_vjp(xyz, torch.from_numpy(gmap).cuda()).cpu().numpy()
+    ref = odg.density_vjp(case.size, case.kind, xyz.astype(np.float64), gmap.astype(np.float64), geo)
+    err = rel_l2(g, ref)
+    zerr = rel_l2(g[2, on_bound], ref[2, on_bound])
+    log(f"[parity] {name} density-vjp at the clamp bounds rel_l2={err:.3e} z on the bounds {zerr:.3e}")
+    assert err <= 1e-5 and zerr <= 1e-5
+
+
 def test_baseline_algorithms(setup):
     """The paper's baselines (Sec. IV) behind the option bits: the instance-parallel scatter of
     large instances gives the same map as the tile-resident sweep (atomic order aside), and the
