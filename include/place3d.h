@@ -11,6 +11,8 @@
  *                                                              to possion-sol-force)
  *   place3d_field_force density-penalty gradient by field gather (Sec. III-A, Sec. IV-A backward)
  *   place3d_density_vjp exact adjoint of the density map      (differentiation form)
+ *   place3d_wl_value / place3d_wl_vjp  forward value and recomputing backward of the wirelength
+ *                       model                                  (differentiation form)
  *   place3d_wl_grad     bistratal WA wirelength, its gradient and the FDA z-gradient
  *                                                             (Eqs. wa-model-approx, wl-obj,
  *                                                              wl-model, fda-grad, fda-normalize;
@@ -33,7 +35,8 @@
  *   - Gradients are d(objective)/d(coordinate), not forces.  Fixed instances get 0; z-held
  *     instances get 0 in z inside place3d_step and place3d_gp_init.
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream) and
- *     never synchronises, except place3d_create, which reads the netlist back to the host once.
+ *     never synchronises, except place3d_create, which reads the netlist back to the host once,
+ *     and place3d_read_scalars, which waits for the stream to read the optimiser's scalars.
  *   - The caller owns all device memory (inputs, outputs and the workspace).  The library never
  *     allocates device memory.  Arrays named in place3d_problem must outlive the context.
  *   - Return value: PLACE3D_OK (0) or a negative place3d_status.  Argument checks are
@@ -52,7 +55,7 @@
 extern "C" {
 #endif
 
-#define PLACE3D_ABI_VERSION 1
+#define PLACE3D_ABI_VERSION 2
 
 #if defined(__GNUC__) || defined(__clang__)
 #define PLACE3D_API __attribute__((visibility("default")))
@@ -65,7 +68,7 @@ typedef enum place3d_status {
   PLACE3D_ERR_ARG = -1,         /* null or misaligned pointer, bad enum value                */
   PLACE3D_ERR_SIZE = -2,        /* sizes out of range or inconsistent (grid, CSR, workspace) */
   PLACE3D_ERR_HIP = -3,         /* a HIP runtime call failed; the HIP code is in last_error  */
-  PLACE3D_ERR_NONFINITE = -4,   /* reserved: a non-finite value seen by a host-visible check */
+  PLACE3D_ERR_NONFINITE = -4,   /* place3d_read_scalars: a GP iteration met a NaN or infinity  */
   PLACE3D_ERR_UNSUPPORTED = -5, /* valid request this build does not implement               */
   PLACE3D_ERR_NETLIST = -6      /* CSR not monotone, pin owner out of range, or an instance
                                    with two pins on one net (the FDA flips whole instances)  */
@@ -105,6 +108,12 @@ enum { PLACE3D_OPT_MACRO_INSTANCE = 1, PLACE3D_OPT_FDA_VANILLA = 2 };
  *   anything uses them (the z-fixed fillers of Sec. III-A; allowed on any movable instance). */
 enum { PLACE3D_KIND_MACRO = 1, PLACE3D_KIND_FIXED = 2, PLACE3D_KIND_FILLER = 4, PLACE3D_KIND_ZFIXED = 8 };
 
+/* z-gradient of place3d_wl_vjp. */
+enum { PLACE3D_WLZ_FDA = 0,     /* the paper's z-gradient: normalised FDA (Eqs. fda-grad,
+                                   fda-normalize) plus alpha d p^_e(z)/dz, as place3d_wl_grad      */
+       PLACE3D_WLZ_VALUE = 1 }; /* the derivative of the model's value in z: alpha d p^_e(z)/dz only
+                                   (the bistratal part changes with z only by steps)               */
+
 /* Layout of the float64 wirelength metrics written by place3d_wl_grad (device, 16 slots). */
 enum {
   PLACE3D_M_WA_BI = 0,     /* sum_e of the smoothed bistratal wirelength (x + y)            */
@@ -128,6 +137,10 @@ enum {
   PLACE3D_S_OVFL_BOT = 4,  /* per-die overflow at the last evaluation point                 */
   PLACE3D_S_OVFL_TOP = 5,
   PLACE3D_S_ENERGY = 6,    /* 1/2 sum_b rho_b phi_b vol(b) (adjoint form only, else 0)      */
+  PLACE3D_S_NONFINITE = 7, /* 0, or 1 + the index of the first iteration (0 = place3d_gp_init's
+                              evaluation) whose float64 reductions held a NaN or infinity: step
+                              and gradient-change norms, lambda, wirelength totals and norms,
+                              overflow excess, energy.  Sticky; place3d_read_scalars checks it */
   PLACE3D_S_WL = 8,        /* slots 8..23: the PLACE3D_M_* metrics at the evaluation point  */
   PLACE3D_NSCALARS = 32
 };
@@ -149,7 +162,9 @@ typedef struct place3d_problem {
   int32_t n_inst;          /* instances: movable cells and macros, fixed instances           */
   int32_t n_pins;
   int32_t n_nets;
-  int32_t nx, ny, nz;      /* bin grid; nx, ny in [2, 8192]; nz even, in [2, 16]             */
+  int32_t nx, ny, nz;      /* bin grid; nx, ny in [2, 8192]; nz even, in [2, 16]; and at most
+                              40,704 density tiles (32 x 32 bins for nz <= 4; 16 x 16 for
+                              nz = 16): e.g. 6400 x 6400 at nz = 4 (else PLACE3D_ERR_SIZE)       */
   double die_x, die_y;     /* die extent d_x, d_y (> 0)                                      */
   double gamma;            /* WA smoothing, length units (> 0)                               */
   double alpha;            /* weight of the cut term alpha p_e(z) (>= 0)                     */
@@ -223,10 +238,17 @@ PLACE3D_API int32_t place3d_field_force(place3d_ctx* ctx, const float* xyz, cons
                             const float* ez, float lambda, float* grad_xyz, int32_t accumulate,
                             void* stream);
 
-/* Exact adjoint of place3d_density: grad[a][i] (+)= sum_b g_rho[b] d rho_b / d v_{a,i},
- * including the z-dependence of the macro size transition. */
-PLACE3D_API int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho,
-                            float* grad_xyz, int32_t accumulate, void* stream);
+/* Exact adjoint of place3d_density: grad[a][i] (+)= s sum_b g_rho[b] d rho_b / d v_{a,i},
+ * s = scale * (d_scale ? d_scale[0] : 1), including the z-dependence of the macro size
+ * transition.  `d_scale` (device float64, one value, may be NULL) carries a factor that lives on
+ * the device, such as the incoming gradient of a backward pass; with g_rho = phi, scale = vol(b)
+ * it gives the gradient of the energy 1/2 sum_b rho_b phi_b vol(b) (the map rho -> phi is
+ * symmetric).  The density is piecewise linear in each coordinate; at a kink the derivative is
+ * one-sided: from above, or from below along an axis whose upper edge reaches the region's upper
+ * face, which at the bounds of the movable range (z = d_z/4 and 3 d_z/4, a macro against a die
+ * side) is the direction the clamp allows.  A z within 2^-20 d_z of a bound counts as on it. */
+PLACE3D_API int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho, float scale,
+                                        const double* d_scale, float* grad_xyz, int32_t accumulate, void* stream);
 
 /* Wirelength model at `xyz`: grad[x], grad[y] (+)= gradient of the smoothed bistratal
  * wirelength; grad[z] (+)= normalised FDA gradient (Eqs. fda-grad, fda-normalize) plus
@@ -234,6 +256,22 @@ PLACE3D_API int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, cons
  * the PLACE3D_M_* values. */
 PLACE3D_API int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, double* metrics,
                         int32_t accumulate, void* stream);
+
+/* The wirelength model's value at `xyz` without its gradient (the forward pass of the
+ * differentiation form; nothing per pin is stored): metrics (device float64 [PLACE3D_NMETRICS])
+ * receives PLACE3D_M_WA_BI .. PLACE3D_M_NCUT, the other slots 0.  In the precision form
+ * (precision == PLACE3D_BF16X3) the exponential sums are compensated float32 sums, as in every
+ * wirelength call of that form. */
+PLACE3D_API int32_t place3d_wl_value(place3d_ctx* ctx, const float* xyz, double* metrics, void* stream);
+
+/* Backward pass of the wirelength model: every net's extremes and shifted exponential sums are
+ * recomputed from `xyz` (none is kept from the forward pass), and grad (+)= s * dW/dxyz with
+ * s = d_scale ? d_scale[0] : 1 (device float64, the incoming gradient) and W = sum_e (W^_e(x) +
+ * W^_e(y) + alpha p^_e(z)).  `z_mode` picks the z part: PLACE3D_WLZ_FDA (the paper's surrogate,
+ * as place3d_wl_grad) or PLACE3D_WLZ_VALUE (the derivative of W itself).  The workspace holds
+ * 16 bytes per pin while the call runs, to sum each instance's pin shares in a fixed order. */
+PLACE3D_API int32_t place3d_wl_vjp(place3d_ctx* ctx, const float* xyz, const double* d_scale, int32_t z_mode,
+                                   float* grad_xyz, int32_t accumulate, void* stream);
 
 /* Start a GP run from `xyz0` (float32 [3][n_inst]): u = v = clamp(xyz0), lambda_0 =
  * |grad W|_1 / |grad U|_1, the bootstrap point v_prev and its preconditioned gradient g_prev;
@@ -244,6 +282,13 @@ PLACE3D_API int32_t place3d_gp_init(place3d_ctx* ctx, place3d_state* state, cons
  * step, Nesterov move, clamp, lambda *= lambda_ramp; metrics of the evaluation point go to
  * state->scalars. */
 PLACE3D_API int32_t place3d_step(place3d_ctx* ctx, place3d_state* state, void* stream);
+
+/* Copy state->scalars (PLACE3D_NSCALARS float64) to the HOST array `host_scalars`, waiting for
+ * `stream`: the convergence check of a GP loop.  Returns PLACE3D_ERR_NONFINITE (with the
+ * iteration in place3d_last_error) when PLACE3D_S_NONFINITE is set; the scalars are copied
+ * either way. */
+PLACE3D_API int32_t place3d_read_scalars(place3d_ctx* ctx, const place3d_state* state, double* host_scalars,
+                                         void* stream);
 
 /* Filler plan (density model, Sec. III-A, Eqs. filler-vol and free-filler-vol): how many fillers
  * of which square footprint fill the region, for the caller to append as instances (kind

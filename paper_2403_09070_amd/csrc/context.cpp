@@ -28,6 +28,8 @@ struct Carver {
   }
 };
 
+int check_grid_fits(const place3d_problem& p, std::string& why);
+
 int check_problem(const place3d_problem* p, std::string& why) {
   if (!p) { why = "problem is NULL"; return PLACE3D_ERR_ARG; }
   if (p->n_inst < 1 || p->n_pins < 0 || p->n_nets < 0) { why = "n_inst < 1 or negative pin/net count"; return PLACE3D_ERR_SIZE; }
@@ -46,6 +48,22 @@ int check_problem(const place3d_problem* p, std::string& why) {
   if ((reinterpret_cast<uintptr_t>(p->size) | reinterpret_cast<uintptr_t>(p->pin_off) |
        reinterpret_cast<uintptr_t>(p->fixed_xyz) | reinterpret_cast<uintptr_t>(p->net_start) |
        reinterpret_cast<uintptr_t>(p->pin2node)) & 3) { why = "misaligned device array"; return PLACE3D_ERR_ARG; }
+  return check_grid_fits(*p, why);
+}
+
+p3d::TileGeom tile_geom(const place3d_problem& p);
+
+// the bucketing passes keep one int per density tile in LDS (a workgroup may use up to 160 KiB on
+// gfx950; 1 KiB is left for the passes' other LDS)
+constexpr size_t kBucketLdsBudget = 159 * 1024;
+
+int check_grid_fits(const place3d_problem& p, std::string& why) {
+  const p3d::TileGeom t = tile_geom(p);
+  if (sizeof(int32_t) * (size_t)t.ntiles > kBucketLdsBudget) {
+    why = "grid too large: " + std::to_string(t.ntiles) + " density tiles of " + std::to_string(t.T) + "x" +
+          std::to_string(t.T) + " bins exceed the bucketing pass's LDS histogram";
+    return PLACE3D_ERR_SIZE;
+  }
   return PLACE3D_OK;
 }
 
@@ -487,11 +505,14 @@ int32_t place3d_field_force(place3d_ctx* ctx, const float* xyz, const float* ex,
                                    reinterpret_cast<hipStream_t>(stream));
 }
 
-int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho, float* grad_xyz,
-                            int32_t accumulate, void* stream) {
+int32_t place3d_density_vjp(place3d_ctx* ctx, const float* xyz, const float* g_rho, float scale,
+                            const double* d_scale, float* grad_xyz, int32_t accumulate, void* stream) {
   if (int rc = check_ctx(ctx)) return rc;
   if (bad_ptr(xyz) || bad_ptr(g_rho) || bad_ptr(grad_xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "NULL or misaligned array");
-  return p3d::density_adjoint(ctx, xyz, g_rho, 1.0f, grad_xyz, accumulate != 0, reinterpret_cast<hipStream_t>(stream));
+  if (d_scale && (reinterpret_cast<uintptr_t>(d_scale) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned d_scale");
+  if (!std::isfinite(scale)) return set_err(ctx, PLACE3D_ERR_ARG, "scale not finite");
+  return p3d::density_adjoint(ctx, xyz, g_rho, scale, grad_xyz, accumulate != 0, reinterpret_cast<hipStream_t>(stream),
+                              d_scale);
 }
 
 int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, double* metrics,
@@ -501,6 +522,37 @@ int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* grad_xyz, dou
   if (metrics && (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned metrics");
   return p3d::wirelength_eval(ctx, xyz, grad_xyz, accumulate != 0, ctx->red, metrics,
                               reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_wl_value(place3d_ctx* ctx, const float* xyz, double* metrics, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "xyz NULL or misaligned");
+  if (!metrics || (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "metrics NULL or misaligned");
+  return p3d::wirelength_value(ctx, xyz, metrics, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_wl_vjp(place3d_ctx* ctx, const float* xyz, const double* d_scale, int32_t z_mode, float* grad_xyz,
+                       int32_t accumulate, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz) || bad_ptr(grad_xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "NULL or misaligned array");
+  if (d_scale && (reinterpret_cast<uintptr_t>(d_scale) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "misaligned d_scale");
+  if (z_mode != PLACE3D_WLZ_FDA && z_mode != PLACE3D_WLZ_VALUE) return set_err(ctx, PLACE3D_ERR_ARG, "bad z_mode");
+  return p3d::wirelength_eval(ctx, xyz, grad_xyz, accumulate != 0, ctx->red, nullptr,
+                              reinterpret_cast<hipStream_t>(stream), false, d_scale, z_mode == PLACE3D_WLZ_FDA);
+}
+
+int32_t place3d_read_scalars(place3d_ctx* ctx, const place3d_state* state, double* host_scalars, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (!state || !state->scalars || !host_scalars) return set_err(ctx, PLACE3D_ERR_ARG, "NULL state or output");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  P3D_HIP(ctx, hipMemcpyAsync(host_scalars, state->scalars, sizeof(double) * PLACE3D_NSCALARS, hipMemcpyDeviceToHost, s));
+  P3D_HIP(ctx, hipStreamSynchronize(s));
+  const double flag = host_scalars[PLACE3D_S_NONFINITE];
+  if (flag != 0.0)
+    return set_err(ctx, PLACE3D_ERR_NONFINITE,
+                   "a non-finite value at GP iteration " + std::to_string((long long)flag - 1) +
+                       " (step size, gradient change, wirelength, overflow, norm or lambda)");
+  return PLACE3D_OK;
 }
 
 PLACE3D_API int32_t place3d_plan_fillers(int32_t n_inst, const float* size, const uint8_t* kind, const float* z0,

@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
 
 __global__ void k_large_adjoint_finish(Geom g, TileGeom t, const int32_t* __restrict__ large, int nlarge,
                                        const float4* __restrict__ lrec, const float4* __restrict__ lpart, float scale,
-                                       float* __restrict__ grad, int accumulate) {
+                                       const double* __restrict__ dscale, float* __restrict__ grad, int accumulate) {
   const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (j >= nlarge) return;
@@ -1042,7 +1042,7 @@ __global__ void k_large_adjoint_finish(Geom g, TileGeom t, const int32_t* __rest
   if (lane == 0) {
     const Foot f = foot_record(g, lrec, j);
     const float3 r = adjoint_finish(g, f, a);
-    const float s = scale / g.vol_bin;
+    const float s = scale / g.vol_bin * (dscale ? (float)dscale[0] : 1.f);
     const int i = large[j], n = g.n;
     if (accumulate) { grad[i] += s * r.x; grad[n + i] += s * r.y; grad[2 * n + i] += s * r.z; }
     else { grad[i] = s * r.x; grad[n + i] = s * r.y; grad[2 * n + i] = s * r.z; }
@@ -1051,8 +1051,8 @@ __global__ void k_large_adjoint_finish(Geom g, TileGeom t, const int32_t* __rest
 
 __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const float* __restrict__ size,
                                 const uint8_t* __restrict__ kind, const int32_t* __restrict__ list,
-                                const float* __restrict__ m, float scale, float* __restrict__ grad,
-                                int accumulate) {
+                                const float* __restrict__ m, float scale, const double* __restrict__ dscale,
+                                float* __restrict__ grad, int accumulate) {
   __shared__ float sh[256 / kWave];
   const int i = list[blockIdx.x];
   const Foot f = footprint(g, xyz, size, kind[i], i);
@@ -1067,7 +1067,7 @@ __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const flo
   a.all = block_sum<256>(a.all, sh);
   if (threadIdx.x == 0) {
     const float3 r = adjoint_finish(g, f, a);
-    const float s = scale / g.vol_bin;
+    const float s = scale / g.vol_bin * (dscale ? (float)dscale[0] : 1.f);
     const int n = g.n;
     if (accumulate) { grad[i] += s * r.x; grad[n + i] += s * r.y; grad[2 * n + i] += s * r.z; }
     else { grad[i] = s * r.x; grad[n + i] = s * r.y; grad[2 * n + i] = s * r.z; }
@@ -1077,11 +1077,13 @@ __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const flo
 // per instance: the sum of its (<= 4) entry results for bucketed cells, zero for fixed
 // instances; large instances are written by their own kernel
 __global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ cell_entry,
-                                const float4* __restrict__ res, float scale, float* __restrict__ grad, int accumulate) {
+                                const float4* __restrict__ res, float scale, const double* __restrict__ dscale,
+                                float* __restrict__ grad, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint8_t c = cls[i];
   if (c == kClsLarge) return;
+  if (dscale) scale *= (float)dscale[0];
   float sx = 0.f, sy = 0.f, sz = 0.f;
   if (c == kClsCell) {
     for (int q = 0; q < 4; ++q) {
@@ -1220,13 +1222,13 @@ int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const flo
   c->cell_scale = scale;
   if (!cells) return PLACE3D_OK;
   hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
-                     c->entry_out, scale, grad, accumulate);
+                     c->entry_out, scale, (const double*)nullptr, grad, accumulate);
   P3D_LAUNCH(c, "k_cells_combine");
   return PLACE3D_OK;
 }
 
 int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
-                     hipStream_t s, bool cells) {
+                     hipStream_t s, bool cells, const double* dscale) {
   const Geom& g = c->g;
   const TileGeom& t = c->tg;
   const place3d_problem& p = c->prob;
@@ -1238,17 +1240,17 @@ int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float 
   P3D_LAUNCH(c, "k_adjoint_tiles");
   if (c->n_large > 0 && tiled) {
     hipLaunchKernelGGL(k_large_adjoint_finish, dim3(blocks_for(c->n_large, 256 / kWave)), dim3(256), 0, s, g, t,
-                       c->large_list, c->n_large, c->large_rec, c->lpart, scale, grad, accumulate);
+                       c->large_list, c->n_large, c->large_rec, c->lpart, scale, dscale, grad, accumulate);
     P3D_LAUNCH(c, "k_large_adjoint_finish");
   } else if (c->n_large > 0) {
     hipLaunchKernelGGL(k_adjoint_large, dim3(c->n_large), dim3(256), 0, s, g, xyz, p.size, p.kind, c->large_list, gmap,
-                       scale, grad, accumulate);
+                       scale, dscale, grad, accumulate);
     P3D_LAUNCH(c, "k_adjoint_large");
   }
   c->cell_scale = scale / g.vol_bin;
   if (!cells) return PLACE3D_OK;
   hipLaunchKernelGGL(k_cells_combine, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, c->cls, c->cell_entry,
-                     c->entry_out, scale / g.vol_bin, grad, accumulate);
+                     c->entry_out, scale / g.vol_bin, dscale, grad, accumulate);
   P3D_LAUNCH(c, "k_cells_combine");
   return PLACE3D_OK;
 }
@@ -1260,9 +1262,9 @@ int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, cons
 }
 
 int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
-                    hipStream_t s) {
+                    hipStream_t s, const double* dscale) {
   if (int rc = bucket_cells(c, xyz, s)) return rc;
-  return adjoint_bucketed(c, xyz, gmap, scale, grad, accumulate, s);
+  return adjoint_bucketed(c, xyz, gmap, scale, grad, accumulate, s, true, dscale);
 }
 
 }  // namespace p3d

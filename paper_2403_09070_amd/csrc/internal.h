@@ -243,16 +243,22 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
 int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const float* ey, const float* ez, float scale,
                     float* grad, int accumulate, hipStream_t s, bool cells = true,
                     bool xfold = false);
+// dscale: a device float64 factor multiplying scale (NULL: 1)
 int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad, int accumulate,
-                     hipStream_t s, bool cells = true);
+                     hipStream_t s, bool cells = true, const double* dscale = nullptr);
 int density_forward(place3d_ctx* c, const float* xyz, float* rho, hipStream_t s);
 int density_field_gather(place3d_ctx* c, const float* xyz, const float* ex, const float* ey,
                          const float* ez, float scale, float* grad, int accumulate, hipStream_t s);
 int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float scale, float* grad,
-                    int accumulate, hipStream_t s);
+                    int accumulate, hipStream_t s, const double* dscale = nullptr);
 
-// packed: c->xyzp already holds xyz (the bucket pass of the same positions wrote it)
+// packed: c->xyzp already holds xyz (the bucket pass of the same positions wrote it); dscale: a
+// device float64 factor of the gradient (NULL: 1); with_fda: the z-gradient carries the normalised
+// FDA term, else only the derivative of alpha p^(z)
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
-                    double* metrics, hipStream_t s, bool packed = false);
+                    double* metrics, hipStream_t s, bool packed = false, const double* dscale = nullptr,
+                    bool with_fda = true);
+// the model's net totals only (no gradient, nothing per pin) into metrics[PLACE3D_NMETRICS]
+int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s);
 
 }  // namespace p3d

@@ -211,6 +211,9 @@ __global__ void k_init_scalars(double* __restrict__ sc, const double* __restrict
   for (int q = 0; q < PLACE3D_NSCALARS; ++q) sc[q] = 0.0;
   sc[PLACE3D_S_A] = 1.0;
   sc[PLACE3D_S_LAMBDA] = red[R_L1_DEN] > 0.0 ? red[R_L1_WL] / red[R_L1_DEN] : 0.0;
+  // the start's norms non-finite: flagged as iteration 0
+  if (!isfinite(red[R_L1_WL]) || !isfinite(red[R_L1_DEN]) || !isfinite(sc[PLACE3D_S_LAMBDA]))
+    sc[PLACE3D_S_NONFINITE] = 1.0;
 }
 
 // the Nesterov move; g (the new preconditioned gradient) sits in g_prev
@@ -251,6 +254,12 @@ __global__ void k_step_finish(double* __restrict__ sc, const double* __restrict_
   for (int q = 0; q <= PLACE3D_M_NORM_FDA; ++q) sc[PLACE3D_S_WL + q] = red[R_WA_BI + q];
   const double nf = red[R_NORM_FDA];
   sc[PLACE3D_S_WL + PLACE3D_M_FDA_SCALE] = nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
+  // the step's float64 reductions: any NaN or infinity in a position, a gradient or a map shows in
+  // one of them; the first iteration that saw one is kept (1 + its index)
+  bool finite = isfinite(dv2) && isfinite(dg2) && isfinite(sc[PLACE3D_S_LAMBDA]) && isfinite(red[R_EXCESS_BOT]) &&
+                isfinite(red[R_EXCESS_TOP]) && isfinite(red[R_ENERGY]);
+  for (int q = R_WA_BI; q <= R_NORM_FDA; ++q) finite = finite && isfinite(red[q]);
+  if (!finite && sc[PLACE3D_S_NONFINITE] == 0.0) sc[PLACE3D_S_NONFINITE] = sc[PLACE3D_S_ITER];
 }
 
 // wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red.

@@ -130,24 +130,65 @@ __device__ __forceinline__ void ext_merge(Ext2& e) {
   e.min1 = fminf(e.min1, b1);
 }
 
-struct Sums4 { float sp, tp, sm, tm; };
+// A float32 sum, compensated when C (Neumaier's variant of Kahan summation: the rounding error of
+// every addition is kept in c and added back at the end), plain otherwise.  merge<M> adds the
+// partner lane's sum; it is commutative, so both partners of a butterfly hold the same sum.
+template <bool C>
+struct Acc {
+  float s, c;
+  __device__ __forceinline__ void add(float x) {
+    if constexpr (C) {
+      const float t = s + x;
+      c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    } else {
+      s += x;
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ void merge() {
+    const float o = xchg<M>(s);
+    if constexpr (C) {
+      const float oc = xchg<M>(c);
+      const float t = s + o;
+      const float e = fabsf(s) >= fabsf(o) ? (s - t) + o : (o - t) + s;
+      c = (c + oc) + e;
+      s = t;
+    } else {
+      s += o;
+    }
+  }
+  __device__ __forceinline__ float value() const { return C ? s + c : s; }
+};
 
-template <int M>
-__device__ __forceinline__ void sums_merge(Sums4& s) {
-  s.sp += xchg<M>(s.sp); s.tp += xchg<M>(s.tp);
-  s.sm += xchg<M>(s.sm); s.tm += xchg<M>(s.tm);
+// shifted exponential sums of one set along one axis: s+ = sum e^{(u-M)/g}, t+ = sum (u-M) e^{(u-M)/g},
+// s- = sum e^{-(u-m)/g}, t- = sum (u-m) e^{-(u-m)/g}
+template <bool C>
+struct Sums4 { Acc<C> sp, tp, sm, tm; };
+struct Sums4v { float sp, tp, sm, tm; };
+
+template <bool C>
+__device__ __forceinline__ Sums4v val(const Sums4<C>& s) { return {s.sp.value(), s.tp.value(), s.sm.value(), s.tm.value()}; }
+
+template <int M, bool C>
+__device__ __forceinline__ void sums_merge(Sums4<C>& s) {
+  s.sp.template merge<M>(); s.tp.template merge<M>();
+  s.sm.template merge<M>(); s.tm.template merge<M>();
 }
 
-struct NetSums { Sums4 xt, xb, yt, yb, z; };
+template <bool C>
+struct NetSums { Sums4<C> xt, xb, yt, yb, z; };
 
-__device__ __forceinline__ void sums_add(Sums4& s, bool in, float du, float dl, float ep, float em) {
-  s.sp += in ? ep : 0.f;
-  s.tp += in ? du * ep : 0.f;
-  s.sm += in ? em : 0.f;
-  s.tm += in ? dl * em : 0.f;
+template <bool C>
+__device__ __forceinline__ void sums_add(Sums4<C>& s, bool in, float du, float dl, float ep, float em) {
+  s.sp.add(in ? ep : 0.f);
+  s.tp.add(in ? du * ep : 0.f);
+  s.sm.add(in ? em : 0.f);
+  s.tm.add(in ? dl * em : 0.f);
 }
 
-__device__ __forceinline__ void sums_pin(NetSums& S, const NetExt& a, const PinRel& p, float ig) {
+template <bool C>
+__device__ __forceinline__ void sums_pin(NetSums<C>& S, const NetExt& a, const PinRel& p, float ig) {
   const float Mx = p.top ? a.tx.max1 : a.bx.max1, mx = p.top ? a.tx.min1 : a.bx.min1;
   const float My = p.top ? a.ty.max1 : a.by.max1, my = p.top ? a.ty.min1 : a.by.min1;
   const float dux = p.ux - Mx, dlx = p.ux - mx, duy = p.uy - My, dly = p.uy - my;
@@ -174,7 +215,7 @@ struct AxisCoef {
 // set's extreme term e^0) or are not used
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ AxisCoef axis_coef(const Ext2& T, const Sums4& st, int ct, const Ext2& B, const Sums4& sb,
+__device__ __forceinline__ AxisCoef axis_coef(const Ext2& T, const Sums4v& st, int ct, const Ext2& B, const Sums4v& sb,
                                               int cb, float ig) {
   const float Mt = T.max1, mt = T.min1, Mb = B.max1, mb = B.min1;
   const float rt_p = ct > 0 ? rcp(st.sp) : 0.f, rt_m = ct > 0 ? rcp(st.sm) : 0.f;
@@ -268,8 +309,8 @@ __device__ __forceinline__ void merge_step(NetExt& a) {
   a.ct += xchg<M>(a.ct);
   a.cb += xchg<M>(a.cb);
 }
-template <int M>
-__device__ __forceinline__ void merge_step(NetSums& S) {
+template <int M, bool C>
+__device__ __forceinline__ void merge_step(NetSums<C>& S) {
   sums_merge<M>(S.xt); sums_merge<M>(S.xb); sums_merge<M>(S.yt); sums_merge<M>(S.yb); sums_merge<M>(S.z);
 }
 // reduce over a group of G lanes, widest step first
@@ -286,17 +327,29 @@ __device__ __forceinline__ void group_merge(T& v) {
 struct NetTotals { float wa_bi, wa_z, hpwl, hpwl3d, ncut; };
 
 // Sum over the wavefront in a fixed order: quad, half-row and row sums by DPP exchanges
-// (xor 1, xor 2, mirror 8, mirror 16), then the four row sums.
+// (xor 1, xor 2, mirror 8, mirror 16), then the four row sums; compensated when C.
+template <bool C>
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp<0xB1>(v);     // quad_perm(1, 0, 3, 2)
-  v += dpp<0x4E>(v);     // quad_perm(2, 3, 0, 1)
-  v += dpp<0x141>(v);    // row_half_mirror
-  v += dpp<0x140>(v);    // row_mirror
-  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+  Acc<C> a{v, 0.f};
+  a.template merge<1>();     // quad_perm(1, 0, 3, 2)
+  a.template merge<2>();     // quad_perm(2, 3, 0, 1)
+  a.template merge<4>();     // row_half_mirror
+  a.template merge<8>();     // row_mirror
+  if constexpr (!C) {
+    return (lane_value(a.s, 0) + lane_value(a.s, 16)) + (lane_value(a.s, 32) + lane_value(a.s, 48));
+  } else {
+    Acc<C> r{lane_value(a.s, 0), lane_value(a.c, 0)};
+    for (int l = 16; l < kWave; l += 16) {
+      r.add(lane_value(a.s, l));
+      r.add(lane_value(a.c, l));
+    }
+    return r.value();
+  }
 }
 
-// one net per group of G lanes; lane lg of the group holds pins lg + G j
-template <int G>
+// one net per group of G lanes; lane lg of the group holds pins lg + G j.  kGrad: also write the
+// per-pin results (phase C); else only the net totals.  C: compensated exponential sums.
+template <int G, bool kGrad, bool C>
 __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, float four_over_dz, float ig,
                                               float alpha, const float4* __restrict__ xyzp,
                                               const int32_t* __restrict__ s_net_start,
@@ -319,7 +372,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   group_merge<G>(a);
 
   // ---- phase B: shifted exponential sums
-  NetSums S = {};
+  NetSums<C> S = {};
 #pragma unroll
   for (int j = 0; j < kPinsPerLane; ++j)
     if (lg + G * j < d) sums_pin(S, a, pc[j], ig);
@@ -328,21 +381,24 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   group_merge<G>(S);
 
   NetCoef c;
-  c.x = axis_coef(a.tx, S.xt, a.ct, a.bx, S.xb, a.cb, ig);
-  c.y = axis_coef(a.ty, S.yt, a.ct, a.by, S.yb, a.cb, ig);
+  c.x = axis_coef(a.tx, val(S.xt), a.ct, a.bx, val(S.xb), a.cb, ig);
+  c.y = axis_coef(a.ty, val(S.yt), a.ct, a.by, val(S.yb), a.cb, ig);
   c.zmax = a.zmax; c.zmin = a.zmin;
-  c.az_p = rcp(S.z.sp); c.Az_p = S.z.tp * c.az_p;
-  c.az_m = rcp(S.z.sm); c.Az_m = S.z.tm * c.az_m;
+  const Sums4v sz = val(S.z);
+  c.az_p = rcp(sz.sp); c.Az_p = sz.tp * c.az_p;
+  c.az_m = rcp(sz.sm); c.Az_m = sz.tm * c.az_m;
   c.Wx = w_exact(a.tx.max1, a.tx.min1, a.ct, a.bx.max1, a.bx.min1, a.cb);
   c.Wy = w_exact(a.ty.max1, a.ty.min1, a.ct, a.by.max1, a.by.min1, a.cb);
 
   // ---- phase C: per-pin results, written at the pin's node-ordered position
+  if constexpr (kGrad) {
 #pragma unroll
-  for (int j = 0; j < kPinsPerLane; ++j)
-    if (lg + G * j < d) pin_out[slot_pos[s + lg + G * j]] = pin_result(pc[j], a, c, ig, alpha, four_over_dz);
-  for (int k = lg + G * kPinsPerLane; k < d; k += G)
-    pin_out[slot_pos[s + k]] =
-        pin_result(load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
+    for (int j = 0; j < kPinsPerLane; ++j)
+      if (lg + G * j < d) pin_out[slot_pos[s + lg + G * j]] = pin_result(pc[j], a, c, ig, alpha, four_over_dz);
+    for (int k = lg + G * kPinsPerLane; k < d; k += G)
+      pin_out[slot_pos[s + k]] =
+          pin_result(load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), a, c, ig, alpha, four_over_dz);
+  }
 
   // ---- net totals, from the group's first lane
   NetTotals t = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -357,6 +413,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   return t;
 }
 
+template <bool kGrad, bool C>
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     float half_dz, float four_over_dz, float gamma, float alpha, const float4* __restrict__ xyzp,
     const int32_t* __restrict__ s_net_start, const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
@@ -374,7 +431,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   NetTotals t = {0.f, 0.f, 0.f, 0.f, 0.f};
   if (net < tab.net_begin[pos + 1]) {
 #define P3D_GROUP(G) \
-  wl_group<G>(net, lg, half_dz, four_over_dz, ig, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
+  wl_group<G, kGrad, C>(net, lg, half_dz, four_over_dz, ig, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
     switch (lg2) {
       case 0: t = P3D_GROUP(1); break;
       case 1: t = P3D_GROUP(2); break;
@@ -390,7 +447,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const float v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    const float x = wave_sum(v[q]);
+    const float x = wave_sum<C>(v[q]);
     if ((threadIdx.x & (kWave - 1)) == 0) shred[q][threadIdx.x / kWave] = (double)x;
   }
   __syncthreads();
@@ -414,7 +471,8 @@ constexpr int kHeavyPins = 32;
 __global__ void k_wl_gather(int n, int nlight, const int32_t* __restrict__ heavy, int nheavy,
                             const uint8_t* __restrict__ kind, const int32_t* __restrict__ node_slot_start,
                             const float4* __restrict__ pin_out, float* __restrict__ grad, int accumulate,
-                            float* __restrict__ gz_wa, float* __restrict__ fda, double* __restrict__ part, int stride) {
+                            const double* __restrict__ dscale, float* __restrict__ gz_wa, float* __restrict__ fda,
+                            double* __restrict__ part, int stride) {
   __shared__ double sh[3][256 / kWave];
   float gx = 0.f, gy = 0.f, gz = 0.f, gf = 0.f;
   int i = -1;
@@ -448,8 +506,9 @@ __global__ void k_wl_gather(int n, int nlight, const int32_t* __restrict__ heavy
     }
   }
   if (writer) {
-    if (accumulate) { grad[i] += gx; grad[n + i] += gy; }
-    else { grad[i] = gx; grad[n + i] = gy; }
+    const float sc = dscale ? (float)dscale[0] : 1.f;     // the caller's factor (a vjp's incoming gradient)
+    if (accumulate) { grad[i] += sc * gx; grad[n + i] += sc * gy; }
+    else { grad[i] = sc * gx; grad[n + i] = sc * gy; }
     gz_wa[i] = gz;
     fda[i] = gf;
   } else {
@@ -474,14 +533,16 @@ __device__ __forceinline__ double fda_scale(const double* red) {
   return nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
 }
 
-// grad_z (+)= scale * fda + gz_wa, scale = (|g_x|_1 + |g_y|_1) / (2 |fda|_1)
+// grad_z (+)= sc (scale * fda + gz_wa), scale = (|g_x|_1 + |g_y|_1) / (2 |fda|_1); without the FDA
+// term (with_fda == 0) grad_z (+)= sc gz_wa, the derivative of the model's value
 __global__ void k_wl_finish_z(int n, const float* __restrict__ gz_wa, const float* __restrict__ fda,
-                              const double* __restrict__ red, float* __restrict__ grad, int accumulate,
-                              double* __restrict__ metrics) {
+                              const double* __restrict__ red, int with_fda, const double* __restrict__ dscale,
+                              float* __restrict__ grad, int accumulate, double* __restrict__ metrics) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const float scale = (float)fda_scale(red);
   if (i < n) {
-    const float v = scale * fda[i] + gz_wa[i];
+    const float sc = dscale ? (float)dscale[0] : 1.f;
+    const float v = sc * (with_fda ? scale * fda[i] + gz_wa[i] : gz_wa[i]);
     if (accumulate) grad[2 * n + i] += v; else grad[2 * n + i] = v;
   }
   if (metrics && i < PLACE3D_NMETRICS) {
@@ -540,9 +601,10 @@ __global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, floa
 }  // namespace
 
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
-                    double* metrics, hipStream_t s, bool packed) {
+                    double* metrics, hipStream_t s, bool packed, const double* dscale, bool with_fda) {
   const Geom& g = c->g;
   const place3d_problem& p = c->prob;
+  const bool comp = p.precision == PLACE3D_BF16X3;      // the precision form compensates the sums
   int rc;
   if (c->n_wa_blocks > 0) {
     if (!packed) {
@@ -551,9 +613,10 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
       P3D_LAUNCH(c, "k_pack_xyz");
     }
     ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
-    hipLaunchKernelGGL(k_wl_nets, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz,
-                       (float)p.gamma, (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos,
-                       c->pin_out, c->classes, c->wa_block_order, c->part, c->part_stride);
+    auto kern = comp ? k_wl_nets<true, true> : k_wl_nets<true, false>;
+    hipLaunchKernelGGL(kern, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz, (float)p.gamma,
+                       (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out,
+                       c->classes, c->wa_block_order, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_wl_nets");
     if (p.options & PLACE3D_OPT_FDA_VANILLA) {
       const int nslots = p.n_pins, nnets = c->classes.net_begin[kNumClasses];
@@ -568,7 +631,7 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
   {
     ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
     hipLaunchKernelGGL(k_wl_gather, dim3(nb), dim3(256), 0, s, g.n, (int)nlight, c->heavy_list, c->n_heavy, p.kind,
-                       c->node_slot_start, c->pin_out, grad, accumulate, c->wl_gzwa, c->wl_fda, c->part,
+                       c->node_slot_start, c->pin_out, grad, accumulate, dscale, c->wl_gzwa, c->wl_fda, c->part,
                        c->part_stride);
     P3D_LAUNCH(c, "k_wl_gather");
   }
@@ -576,10 +639,33 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
   {
     ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
     hipLaunchKernelGGL(k_wl_finish_z, dim3(blocks_for(std::max(g.n, (int)PLACE3D_NMETRICS), 256)), dim3(256), 0, s,
-                       g.n, c->wl_gzwa, c->wl_fda, red, grad, accumulate, metrics);
+                       g.n, c->wl_gzwa, c->wl_fda, red, with_fda ? 1 : 0, dscale, grad, accumulate, metrics);
     P3D_LAUNCH(c, "k_wl_finish_z");
   }
   return PLACE3D_OK;
+}
+
+int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s) {
+  const Geom& g = c->g;
+  const place3d_problem& p = c->prob;
+  const bool comp = p.precision == PLACE3D_BF16X3;
+  int rc;
+  if (c->n_wa_blocks > 0) {
+    {
+      ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
+      hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, xyz, c->xyzp);
+      P3D_LAUNCH(c, "k_pack_xyz");
+    }
+    ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
+    auto kern = comp ? k_wl_nets<false, true> : k_wl_nets<false, false>;
+    hipLaunchKernelGGL(kern, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz, (float)p.gamma,
+                       (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out,
+                       c->classes, c->wa_block_order, c->part, c->part_stride);
+    P3D_LAUNCH(c, "k_wl_nets(value)");
+  }
+  // the five net totals straight into the metrics; the gradient norms are not computed here
+  if ((rc = launch_zero_f64(c, metrics, PLACE3D_NMETRICS, s))) return rc;
+  return reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, metrics + PLACE3D_M_WA_BI, s);
 }
 
 }  // namespace p3d

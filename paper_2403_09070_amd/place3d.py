@@ -25,7 +25,8 @@ OPT_MACRO_INSTANCE, OPT_FDA_VANILLA = 1, 2
 KIND_MACRO, KIND_FIXED, KIND_FILLER, KIND_ZFIXED = 1, 2, 4, 8
 NMETRICS, NSCALARS = 16, 32
 M = dict(wa_bi=0, wa_z=1, hpwl=2, hpwl3d=3, ncut=4, norm_x=5, norm_y=6, norm_fda=7, fda_scale=8)
-S = dict(a=0, lam=1, step=2, it=3, ovfl_bot=4, ovfl_top=5, energy=6, wl=8)
+S = dict(a=0, lam=1, step=2, it=3, ovfl_bot=4, ovfl_top=5, energy=6, nonfinite=7, wl=8)
+WLZ_FDA, WLZ_VALUE = 0, 1
 STAGES = ("density", "gemm", "zmix", "dgrad", "wl_nets", "wl_nodes", "update", "bucket")
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SIZE", -3: "ERR_HIP", -4: "ERR_NONFINITE",
           -5: "ERR_UNSUPPORTED", -6: "ERR_NETLIST"}
@@ -80,8 +81,11 @@ def lib():
             "place3d_density": (i32, [vp, vp, vp, vp]),
             "place3d_field": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
             "place3d_field_force": (i32, [vp, vp, vp, vp, vp, f32, vp, i32, vp]),
-            "place3d_density_vjp": (i32, [vp, vp, vp, vp, i32, vp]),
+            "place3d_density_vjp": (i32, [vp, vp, vp, f32, vp, vp, i32, vp]),
             "place3d_wl_grad": (i32, [vp, vp, vp, vp, i32, vp]),
+            "place3d_wl_value": (i32, [vp, vp, vp, vp]),
+            "place3d_wl_vjp": (i32, [vp, vp, vp, i32, vp, i32, vp]),
+            "place3d_read_scalars": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
             "place3d_gp_init": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
             "place3d_step": (i32, [vp, ctypes.POINTER(State_), vp]),
             "place3d_profile_enable": (i32, [vp, i32]),
@@ -94,7 +98,7 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        if L.place3d_abi_version() != 1:
+        if L.place3d_abi_version() != 2:
             raise ImportError("libplace3d ABI version mismatch")
         _lib = L
     return _lib
@@ -268,11 +272,13 @@ class Problem:
                                          int(accumulate), _stream()), self._ctx)
         return g
 
-    def density_vjp(self, xyz, g_rho, out=None, accumulate=False):
+    def density_vjp(self, xyz, g_rho, out=None, accumulate=False, scale=1.0, d_scale=None):
+        """grad (+)= scale * d_scale[0] * J^T g_rho; d_scale a one-element float64 device tensor or None."""
         xyz = self.xyz(xyz)
         g = self._grad(out)
-        _check(lib().place3d_density_vjp(self._ctx, _ptr(xyz), _ptr(self.map_in(g_rho)), _ptr(g), int(accumulate),
-                                         _stream()), self._ctx)
+        ds = None if d_scale is None else d_scale.to(device=self.device, dtype=torch.float64).contiguous()
+        _check(lib().place3d_density_vjp(self._ctx, _ptr(xyz), _ptr(self.map_in(g_rho)), float(scale), _ptr(ds),
+                                         _ptr(g), int(accumulate), _stream()), self._ctx)
         return g
 
     def wl_grad(self, xyz, out=None, accumulate=False):
@@ -282,6 +288,31 @@ class Problem:
         _check(lib().place3d_wl_grad(self._ctx, _ptr(xyz), _ptr(g), _ptr(met), int(accumulate), _stream()),
                self._ctx)
         return g, met
+
+    def wl_value(self, xyz):
+        """The model's net totals at xyz (float64 [NMETRICS]; no gradient, nothing stored per pin)."""
+        xyz = self.xyz(xyz)
+        met = torch.empty(NMETRICS, dtype=torch.float64, device=self.device)
+        _check(lib().place3d_wl_value(self._ctx, _ptr(xyz), _ptr(met), _stream()), self._ctx)
+        return met
+
+    def wl_vjp(self, xyz, d_scale=None, z_mode=WLZ_FDA, out=None, accumulate=False):
+        """Backward of the wirelength model, recomputed from xyz: grad (+)= d_scale[0] * dW/dxyz."""
+        xyz = self.xyz(xyz)
+        g = self._grad(out)
+        ds = None if d_scale is None else d_scale.to(device=self.device, dtype=torch.float64).contiguous()
+        _check(lib().place3d_wl_vjp(self._ctx, _ptr(xyz), _ptr(ds), int(z_mode), _ptr(g), int(accumulate),
+                                    _stream()), self._ctx)
+        return g
+
+    def read_scalars(self, state):
+        """The state's scalars on the host after waiting for the stream; raises Place3dError
+        (ERR_NONFINITE) when an iteration met a NaN or infinity."""
+        host = np.zeros(NSCALARS, dtype=np.float64)
+        cs = state.cstruct()
+        _check(lib().place3d_read_scalars(self._ctx, ctypes.byref(cs), ctypes.c_void_p(host.ctypes.data), _stream()),
+               self._ctx)
+        return host
 
     def new_state(self):
         z = lambda: torch.zeros((3, self.n), dtype=torch.float32, device=self.device)  # noqa: E731

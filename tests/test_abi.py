@@ -33,7 +33,7 @@ def test_header_declares_the_hot_path_calls():
 def test_every_declared_symbol_is_exported(L):
     for n in declared():
         assert hasattr(L, n), n
-    assert L.place3d_abi_version() == 1
+    assert L.place3d_abi_version() == 2
 
 
 def _problem(**kw):
@@ -56,6 +56,17 @@ def test_workspace_size_rejects_bad_problems(L, field, value, code):
     assert L.place3d_last_error(None)
 
 
+@pytest.mark.parametrize("nx,nz,code", [(6400, 4, 0), (6464, 4, -2), (8192, 2, -2), (3200, 16, 0), (3264, 16, -2)])
+def test_grids_beyond_the_bucket_histogram_are_refused(L, nx, nz, code):
+    """The bucketing passes hold one counter per density tile in LDS: grids with more tiles than
+    that budget are refused at creation (PLACE3D_ERR_SIZE), not at their first launch."""
+    n = ctypes.c_size_t()
+    p = _problem(nx=nx, ny=nx, nz=nz)
+    assert L.place3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == code
+    if code:
+        assert b"density tiles" in L.place3d_last_error(None)
+
+
 def test_workspace_size_accepts_a_valid_problem_and_grows_with_the_grid(L):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.place3d_workspace_size(ctypes.byref(_problem()), ctypes.byref(a)) == 0
@@ -75,6 +86,10 @@ def test_create_rejects_null_or_misaligned_workspace_without_a_device_call(L):
 def test_calls_reject_a_null_context(L):
     assert L.place3d_density(None, None, None, None) == -1
     assert L.place3d_step(None, None, None) == -1
+    assert L.place3d_wl_value(None, None, None, None) == -1
+    assert L.place3d_wl_vjp(None, None, None, 0, None, 0, None) == -1
+    assert L.place3d_read_scalars(None, None, None, None) == -1
+    assert L.place3d_density_vjp(None, None, None, 1.0, None, None, 0, None) == -1
     assert L.place3d_destroy(None) == 0
 
 

@@ -1,11 +1,15 @@
 """The torch.autograd Functions over the C ABI (paper_2403_09070_amd.autograd) against the oracle.
 
 * Field: the GPU solve is symmetric, <phi(a), b> = <a, phi(b)> (the property its backward uses).
-* Density + Field: the gradient of U = 1/2 sum rho phi vol(b) through autograd equals the oracle's
-  exact adjoint of the density map applied to phi vol(b) (Sec. III-A energy, reading 6).
-* WAWirelength: forward value = the oracle's smoothed bistratal wirelength plus its z term; the
-  backward returns the library's gradient scaled by the upstream gradient.
-* The autograd gradient of U against central differences of the FP64 oracle's U (C1).
+* DensityEnergy: U = 1/2 sum rho phi vol(b) reduced in float64 by the library equals the oracle's,
+  and its gradient equals the oracle's exact adjoint of the density map applied to phi vol(b)
+  (Sec. III-A energy, reading 6).
+* WAWirelength: forward value = the oracle's smoothed bistratal wirelength plus its z term (no
+  gradient computed, nothing stored per pin); the backward recomputes the sums and returns the
+  paper's gradient (FDA z part) or the value's own derivative, scaled by the incoming gradient.
+* The autograd gradients against central differences of the FP64 oracle's U and W: C1 with full
+  evaluations, and the 200k-instance netlist on 1,000 instances x {x, y, z} (3,000 coordinates)
+  with the local differences of tests/fd_local.py.
 """
 import numpy as np
 import pytest
@@ -60,24 +64,34 @@ def test_density_energy_gradient_matches_the_oracle_adjoint(which):
     assert err <= 1e-4
 
 
-def test_wirelength_function():
+@pytest.mark.parametrize("precision", [place3d.FP32, place3d.BF16X3])
+def test_wirelength_function(precision):
     need_gpu()
     from paper_2403_09070_amd import autograd as ag
     case = synth.make_case("c1", 2403)
     geo = geometry_of(case)
     pb = oracle_problem(case)
-    prob = gpu_problem(case)
-    xyz = torch.from_numpy(case.xyz0).cuda().requires_grad_(True)
-    w = ag.WAWirelength.apply(prob, xyz)
-    (2.0 * w).backward()
+    prob = gpu_problem(case, precision=precision)
     ref = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
     want = ref["wa_bi"] + ref["wa_z"]
-    w_gpu = float(w.detach())
-    log(f"[autograd] wirelength gpu={w_gpu:.9g} ref={want:.9g}")
-    assert abs(w_gpu - want) <= 1e-5 * abs(want)
-    g, _ = prob.wl_grad(case.xyz0)
-    assert torch.equal(xyz.grad, 2.0 * g)
-    assert rel_l2(xyz.grad[:2].cpu().numpy(), 2.0 * ref["grad"][:2]) <= 1e-5
+    g_lib, met = prob.wl_grad(case.xyz0)
+    for fda in (True, False):
+        xyz = torch.from_numpy(case.xyz0).cuda().requires_grad_(True)
+        w = ag.wirelength(prob, xyz, fda=fda)
+        (2.0 * w).backward()
+        w_gpu = float(w.detach())
+        log(f"[autograd] wirelength precision={precision} fda={fda} gpu={w_gpu:.12g} ref={want:.12g}")
+        assert abs(w_gpu - want) <= 1e-5 * abs(want)
+        g = xyz.grad.cpu().numpy()
+        assert rel_l2(g[:2], 2.0 * ref["grad"][:2]) <= 1e-5
+        if fda:     # the paper's z-gradient, the same kernels as place3d_wl_grad
+            assert torch.equal(xyz.grad, 2.0 * g_lib)
+        else:       # the derivative of the value: alpha dp^(z)/dz
+            assert rel_l2(g[2], 2.0 * ref["grad_zwa"]) <= 1e-5
+    # the value call writes the net totals only
+    m = prob.wl_value(case.xyz0).cpu().numpy()
+    assert np.array_equal(m[:5], met.cpu().numpy()[:5])
+    assert np.all(m[5:] == 0.0)
 
 
 def test_energy_gradient_matches_fp64_finite_differences():
@@ -117,3 +131,55 @@ def test_energy_gradient_matches_fp64_finite_differences():
         ok += abs(g[a, i] - fd) <= 1e-4 * abs(fd) + 1e-5 * med
     log(f"[autograd] FD check: {ok}/{total} within the bound")
     assert ok >= 0.99 * total
+
+
+def test_c3_gradients_match_fp64_finite_differences_on_the_200k_netlist():
+    """The differentiation form at the 200k-instance netlist (C3: 200k cells + 40 macros, 220k nets,
+    512 x 512 x 4 bins; float32 spectral solve): the autograd gradients of U (DensityEnergy) and W
+    (WAWirelength, its value's own z-derivative) on 1,000 random movable instances x {x, y, z},
+    3,000 coordinates each, against central differences (h = 1e-3 bin widths) of the FP64 oracle's U
+    and W: |g - g_FD| <= 1e-4 |g_FD| + 1e-5 median|g| on at least 99 % of the coordinates off
+    kinks; kinks (one-sided differences that disagree) are counted and reported.  The U gradient
+    also matches the oracle's exact adjoint over all instances (1e-4 rel L2)."""
+    need_gpu()
+    import fd_local
+    from paper_2403_09070_amd import autograd as ag
+    case = synth.make_case("c2", 2403)
+    geo = geometry_of(case)
+    pb = oracle_problem(case)
+    prob = gpu_problem(case, precision=place3d.FP32, dgrad=place3d.DGRAD_ADJOINT)
+    xyz = torch.from_numpy(case.xyz0).cuda().requires_grad_(True)
+    u = ag.density_energy(prob, xyz)
+    (g_u,) = torch.autograd.grad(u, xyz)
+    w = ag.wirelength(prob, xyz, fda=False)
+    (g_w,) = torch.autograd.grad(w, xyz)
+    g_u = g_u.cpu().numpy().astype(np.float64)
+    g_w = g_w.cpu().numpy().astype(np.float64)
+    log("[autograd] c3: GPU gradients done, oracle density and potential")
+    v = case.xyz0.astype(np.float64)
+    rho = oden.density_map(case.size, case.kind, v, geo)
+    phi = opois.solve(rho, geo, want=("phi",))["phi"]
+    e_ref = opois.energy(rho, phi, geo)
+    log(f"[autograd] c3 energy gpu={float(u):.9g} ref={e_ref:.9g}")
+    assert abs(float(u) - e_ref) <= 1e-5 * abs(e_ref)
+    ref_adj = odg.density_vjp(case.size, case.kind, v, phi * geo.vol_bin, geo)
+    err_adj = rel_l2(g_u, ref_adj)
+    log(f"[autograd] c3 dU/dxyz vs oracle adjoint rel_l2={err_adj:.3e}")
+    assert err_adj <= 1e-4
+    rng = np.random.default_rng(2403)
+    movable = np.nonzero((case.kind & place3d.KIND_FIXED) == 0)[0]
+    inst = rng.choice(movable, size=1000, replace=False)
+    probes = [(int(i), a) for i in inst for a in range(3)]
+    h = 1e-3 * geo.wb
+    c, up, dn = fd_local.energy_differences(case, geo, phi, v, probes, h)
+    gu = np.array([g_u[a, i] for i, a in probes])
+    ok, judged, kinks, worst = fd_local.judge(gu, c, up, dn)
+    log(f"[autograd] c3 U: {ok}/{judged} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
+    assert judged >= 0.9 * len(probes) and ok >= 0.99 * judged
+    # W: skip z probes whose stencil crosses the die switch at d_z/2 (a step of the bistratal part)
+    wprobes = [(i, a) for i, a in probes if not (a == 2 and abs(v[2, i] - 0.5 * geo.dz) < 2 * h)]
+    c, up, dn = fd_local.wirelength_differences(pb, v, wprobes, h)
+    gw = np.array([g_w[a, i] for i, a in wprobes])
+    ok, judged, kinks, worst = fd_local.judge(gw, c, up, dn)
+    log(f"[autograd] c3 W: {ok}/{judged} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
+    assert judged >= 0.9 * len(wprobes) and ok >= 0.99 * judged

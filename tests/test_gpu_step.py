@@ -211,3 +211,24 @@ def test_baseline_algorithms_in_the_step():
         do = max(abs(ra["ovfl_bot"] - rb["ovfl_bot"]), abs(ra["ovfl_top"] - rb["ovfl_top"]))
         log(f"[step] options it {k} hpwl rel={dh:.2e} ovfl diff={do:.2e}")
         assert dh <= 1e-4 and do <= 1e-4
+
+
+def test_nonfinite_iteration_is_flagged_and_reported():
+    """A NaN density weight (set from the host) makes the step's float64 gradient-change norm NaN:
+    the step records the iteration and place3d_read_scalars returns PLACE3D_ERR_NONFINITE.  The
+    positions stay finite (the clamp takes a NaN move to the region's bound), so no kernel sees a
+    NaN index.  A clean run reads back without error."""
+    need_gpu()
+    log("[step] non-finite flag")
+    case = tiny_case(5)
+    prob = gpu_problem(case)
+    st = prob.gp_init(case.xyz0)
+    prob.step(st)
+    sc = prob.read_scalars(st)
+    assert sc[place3d.S["nonfinite"]] == 0.0 and sc[place3d.S["it"]] == 1.0
+    st.scalars[place3d.S["lam"]] = float("nan")
+    prob.step(st)
+    with pytest.raises(place3d.Place3dError) as e:
+        prob.read_scalars(st)
+    assert e.value.code == -4 and "iteration 1" in str(e.value)
+    assert torch.isfinite(st.v).all()
