@@ -28,7 +28,11 @@ ceil(e/s) - 1, provided 0 < e <= L (s the bin size, L the region's extent); an e
 ranges is held by the region and changes nothing.  A z within 2^-20 d_z of a bound counts as on
 it (the bounds are rounded when the coordinates are float32), and its z-edges are taken exactly
 on the faces they then sit on: the floor and the mid-plane at d_z/4, the mid-plane and the ceiling
-at 3 d_z/4 (N_z is even).
+at 3 d_z/4 (N_z is even).  Likewise a planar edge within 2^-20 of the region's extent of a region
+face is on that face when the derivative's direction and bin are decided: the clamp holds an
+instance against a die side at a float32 position, which leaves its edge a rounding away from
+the face on either side, and the derivative must not depend on which (the overlap lengths
+themselves are taken from the edges as they are).
 """
 from __future__ import annotations
 
@@ -57,6 +61,10 @@ def _edges(size, kind, xyz, geo):
                     xyz[2] - 0.25 * geo.dz, xyz[2] + 0.25 * geo.dz])
     lim = np.array([geo.die_x, geo.die_x, geo.die_y, geo.die_y, geo.dz, geo.dz])[:, None]
     box = np.clip(raw, 0.0, lim)
+    # planar edges a rounding away from a region face are on it (for the one-sided decisions only)
+    for k in range(4):
+        band = CLAMP_BAND * lim[k, 0]
+        raw[k] = np.where(np.abs(raw[k]) <= band, 0.0, np.where(np.abs(raw[k] - lim[k, 0]) <= band, lim[k, 0], raw[k]))
     below = raw[1::2] >= lim[1::2]          # [3][n]: upper edge on or past the region's upper face
     at_lo, at_hi = z_bands(xyz[2], geo.dz)
     below[2] = at_hi | (~at_lo & below[2])

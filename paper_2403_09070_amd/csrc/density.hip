@@ -184,15 +184,28 @@ __device__ __forceinline__ float2 local_faces(float die, int cb, double step) {
   return make_float2((float)-o, (float)((double)die - o));
 }
 
+// A planar edge within 2^-20 of the region's extent of a region face is on that face for the
+// one-sided decisions: the clamp holds an instance against a die side at a float32 position and
+// the local coordinate rounds again, which leaves the edge a rounding away from the face on
+// either side.  (The overlap lengths keep the edges as they are.)
+__device__ __forceinline__ float snap_face(float e, float2 face, float band) {
+  if (fabsf(e - face.x) <= band) return face.x;
+  if (fabsf(e - face.y) <= band) return face.y;
+  return e;
+}
+
 __device__ __forceinline__ EdgeBins edge_bins(const Geom& g, const Foot& f) {
   EdgeBins e;
   const float2 fx = local_faces(g.dx, f.cbx, g.wbd), fy = local_faces(g.dy, f.cby, g.hbd);
-  e.down_x = f.rx1 >= fx.y;
-  e.down_y = f.ry1 >= fy.y;
-  e.xl = edge_bin(f.rx0, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
-  e.xh = edge_bin(f.rx1, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
-  e.yl = edge_bin(f.ry0, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
-  e.yh = edge_bin(f.ry1, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
+  const float bx = kClampBand * g.dx, by = kClampBand * g.dy;
+  const float x0 = snap_face(f.rx0, fx, bx), x1 = snap_face(f.rx1, fx, bx);
+  const float y0 = snap_face(f.ry0, fy, by), y1 = snap_face(f.ry1, fy, by);
+  e.down_x = x1 >= fx.y;
+  e.down_y = y1 >= fy.y;
+  e.xl = edge_bin(x0, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
+  e.xh = edge_bin(x1, fx.x, fx.y, g.inv_wb, e.down_x, f.cbx, g.nx);
+  e.yl = edge_bin(y0, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
+  e.yh = edge_bin(y1, fy.x, fy.y, g.inv_hb, e.down_y, f.cby, g.ny);
   const int zb = z_bound(g, f.z);
   if (zb < 0) {            // on the lower bound: edges on the floor and the mid-plane, moving up
     e.down_z = false; e.zl = 0; e.zh = g.nz / 2;
@@ -902,11 +915,12 @@ __device__ __forceinline__ AdjSums adjoint_sums(const Geom& g, const Foot& f, Ma
   int sxl = -1, sxh = -1, syl = -1, syh = -1;
   if (with_size_terms) {
     const float2 fx = local_faces(g.dx, f.cbx, g.wbd), fy = local_faces(g.dy, f.cby, g.hbd);
+    const float bx = kClampBand * g.dx, by = kClampBand * g.dy;
     const bool hx = e.down_z != (f.dw < 0.f), hy = e.down_z != (f.dh < 0.f);   // upper edge moving down
-    sxl = edge_bin(f.rx0, fx.x, fx.y, g.inv_wb, !hx, f.cbx, g.nx);
-    sxh = edge_bin(f.rx1, fx.x, fx.y, g.inv_wb, hx, f.cbx, g.nx);
-    syl = edge_bin(f.ry0, fy.x, fy.y, g.inv_hb, !hy, f.cby, g.ny);
-    syh = edge_bin(f.ry1, fy.x, fy.y, g.inv_hb, hy, f.cby, g.ny);
+    sxl = edge_bin(snap_face(f.rx0, fx, bx), fx.x, fx.y, g.inv_wb, !hx, f.cbx, g.nx);
+    sxh = edge_bin(snap_face(f.rx1, fx, bx), fx.x, fx.y, g.inv_wb, hx, f.cbx, g.nx);
+    syl = edge_bin(snap_face(f.ry0, fy, by), fy.x, fy.y, g.inv_hb, !hy, f.cby, g.ny);
+    syh = edge_bin(snap_face(f.ry1, fy, by), fy.x, fy.y, g.inv_hb, hy, f.cby, g.ny);
   }
   int x0 = bx0, x1 = bx1, y0 = by0, y1 = by1, z0 = f.bz0, z1 = f.bz1;
   widen(x0, x1, e.xl, xl0, xl1); widen(x0, x1, e.xh, xl0, xl1);

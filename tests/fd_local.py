@@ -83,15 +83,40 @@ def wirelength_differences(pb, v, probes, h):
     return np.array(c), np.array(u), np.array(d)
 
 
-def judge(g, central, up, down, kink_tol=1e-2):
-    """Bound |g - g_FD| <= 1e-4 |g_FD| + 1e-5 median|g| on the probes off kinks.  A kink turns the
-    derivative by an amount of the order of the gradient inside the stencil, so the one-sided
-    differences then disagree by more than kink_tol (|g_FD| + median|g|); smooth curvature moves
-    them apart by h |f''| only.  Returns (n_ok, n_judged, n_kinks, worst ratio of error to bound)."""
+def jacobian_l1(case, geo, v, probes):
+    """sum_b |d rho_b / d v_a,i| vol(b) per probe (i, a): the l1 norm of the density-Jacobian
+    column, from the stretched, clipped cuboid of the oracle's attributes.  Moving a planar
+    coordinate moves its two edges, each changing the overlap of one layer of bins by the cross
+    extent (omega L_y L_z per edge along x); z likewise, and a macro's z also moves the planar
+    edges (half the size slope each) and, for an extent below the stretch threshold, omega."""
+    from oracle.attributes import instance_size, macro_size_slope, smoothing
+    idx = np.array([i for i, _ in probes])
+    ax = np.array([a for _, a in probes])
+    xyz = np.asarray(v, dtype=np.float64)[:, idx]
+    size, kind = case.size[:, idx], case.kind[idx]
+    w, h = instance_size(size, kind, xyz[2], geo.dz)
+    wt, ht, omega = smoothing(w, h, geo.wb, geo.hb)
+    lx = np.clip(xyz[0] + 0.5 * wt, 0, geo.die_x) - np.clip(xyz[0] - 0.5 * wt, 0, geo.die_x)
+    ly = np.clip(xyz[1] + 0.5 * ht, 0, geo.die_y) - np.clip(xyz[1] - 0.5 * ht, 0, geo.die_y)
+    lz = np.clip(xyz[2] + 0.25 * geo.dz, 0, geo.dz) - np.clip(xyz[2] - 0.25 * geo.dz, 0, geo.dz)
+    dw, dh = macro_size_slope(size, kind, geo.dz)
+    r2 = np.sqrt(2.0)
+    domega = np.abs(dw) / (r2 * geo.wb) + np.abs(dh) / (r2 * geo.hb)
+    out = np.where(ax == 0, 2 * omega * ly * lz, np.where(ax == 1, 2 * omega * lx * lz, 2 * omega * lx * ly))
+    zsize = domega * lx * ly * lz + omega * (np.abs(dw) * ly * lz + np.abs(dh) * lx * lz)
+    return out + np.where(ax == 2, zsize, 0.0)
+
+
+def judge(g, central, up, down, kink_tol=1e-2, extra=0.0):
+    """Bound |g - g_FD| <= 1e-4 |g_FD| + 1e-5 median|g| (+ extra, per probe) on the probes off
+    kinks.  A kink turns the derivative by an amount of the order of the gradient inside the
+    stencil, so the one-sided differences then disagree by more than kink_tol (|g_FD| +
+    median|g|); smooth curvature moves them apart by h |f''| only.  Returns (n_ok, n_judged,
+    n_kinks, worst ratio of error to bound)."""
     g = np.asarray(g, dtype=np.float64)
     med = float(np.median(np.abs(g))) if g.size else 0.0
     kink = np.abs(up - down) > kink_tol * (np.abs(central) + med)
-    bound = 1e-4 * np.abs(central) + 1e-5 * med
+    bound = 1e-4 * np.abs(central) + 1e-5 * med + extra
     err = np.abs(g - central)
     judged = ~kink
     ok = judged & (err <= bound)

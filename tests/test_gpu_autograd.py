@@ -80,17 +80,22 @@ def test_wirelength_function(precision):
         w = ag.wirelength(prob, xyz, fda=fda)
         (2.0 * w).backward()
         w_gpu = float(w.detach())
-        log(f"[autograd] wirelength precision={precision} fda={fda} gpu={w_gpu:.12g} ref={want:.12g}")
-        assert abs(w_gpu - want) <= 1e-5 * abs(want)
         g = xyz.grad.cpu().numpy()
-        assert rel_l2(g[:2], 2.0 * ref["grad"][:2]) <= 1e-5
+        e_xy = rel_l2(g[:2], 2.0 * ref["grad"][:2])
+        e_z = rel_l2(g[2], 2.0 * (ref["grad"][2] if fda else ref["grad_zwa"]))
+        log(f"[autograd] wirelength precision={precision} fda={fda} gpu={w_gpu:.12g} ref={want:.12g} "
+            f"grad xy rel_l2={e_xy:.3e} z rel_l2={e_z:.3e}")
+        assert abs(w_gpu - want) <= 1e-5 * abs(want)
+        assert e_xy <= 1e-5
         if fda:     # the paper's z-gradient, the same kernels as place3d_wl_grad
             assert torch.equal(xyz.grad, 2.0 * g_lib)
         else:       # the derivative of the value: alpha dp^(z)/dz
-            assert rel_l2(g[2], 2.0 * ref["grad_zwa"]) <= 1e-5
-    # the value call writes the net totals only
+            assert e_z <= 1e-5
+    # the value call writes the net totals only; it is a separately compiled instance of the net
+    # kernel (no per-pin phase), whose float32 contractions may round differently: 1e-6 relative
     m = prob.wl_value(case.xyz0).cpu().numpy()
-    assert np.array_equal(m[:5], met.cpu().numpy()[:5])
+    mg = met.cpu().numpy()[:5]
+    assert np.all(np.abs(m[:5] - mg) <= 1e-6 * np.abs(mg))
     assert np.all(m[5:] == 0.0)
 
 
@@ -140,7 +145,9 @@ def test_c3_gradients_match_fp64_finite_differences_on_the_200k_netlist():
     3,000 coordinates each, against central differences (h = 1e-3 bin widths) of the FP64 oracle's U
     and W: |g - g_FD| <= 1e-4 |g_FD| + 1e-5 median|g| on at least 99 % of the coordinates off
     kinks; kinks (one-sided differences that disagree) are counted and reported.  The U gradient
-    also matches the oracle's exact adjoint over all instances (1e-4 rel L2)."""
+    also matches the oracle's exact adjoint over all instances (1e-4 rel L2).  The U bound adds
+    what the float32 potential can move a gradient: the largest error of the GPU's float32 phi
+    against the oracle's times the l1 norm of the instance's density-Jacobian column."""
     need_gpu()
     import fd_local
     from paper_2403_09070_amd import autograd as ag
@@ -173,7 +180,16 @@ def test_c3_gradients_match_fp64_finite_differences_on_the_200k_netlist():
     h = 1e-3 * geo.wb
     c, up, dn = fd_local.energy_differences(case, geo, phi, v, probes, h)
     gu = np.array([g_u[a, i] for i, a in probes])
-    ok, judged, kinks, worst = fd_local.judge(gu, c, up, dn)
+    # the GPU gradient is <phi_32, d rho / d v> vol(b) with the float32 potential of the float32
+    # solve: its error is at most max|phi_32 - phi| times the l1 norm of the density Jacobian
+    # column (plus the float32 accumulation), which at this grid exceeds 1e-4 |g| for many cells
+    # (phi ~ 2e4 against face differences ~ 1e2; phi rounded to float32 alone fails the bare bound
+    # on 2.5 % of these coordinates)
+    phi32 = prob.field(prob.density(xyz.detach()), want=("phi",))["phi"].cpu().numpy().astype(np.float64)
+    dphi = float(np.max(np.abs(phi32 - phi))) + 4.0 * 2.0 ** -24 * float(np.max(np.abs(phi)))
+    l1 = fd_local.jacobian_l1(case, geo, v, probes)
+    log(f"[autograd] c3 max|phi_32 - phi| = {dphi:.3e} (max|phi| {np.max(np.abs(phi)):.3e})")
+    ok, judged, kinks, worst = fd_local.judge(gu, c, up, dn, extra=dphi * l1)
     log(f"[autograd] c3 U: {ok}/{judged} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
     assert judged >= 0.9 * len(probes) and ok >= 0.99 * judged
     # W: skip z probes whose stencil crosses the die switch at d_z/2 (a step of the bistratal part)

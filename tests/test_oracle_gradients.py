@@ -271,3 +271,37 @@ def test_field_gather_z_agrees_with_adjoint_at_the_clamp_bounds():
         g_a = dg.density_vjp(c.size, c.kind, v, sol["phi"] * geo.vol_bin, geo)[2]
         cos = float(np.sum(g_f * g_a) / (np.linalg.norm(g_f) * np.linalg.norm(g_a)))
         assert cos >= 0.85, (n, cos)
+
+
+def test_adjoint_at_a_die_side_does_not_depend_on_the_rounding_of_the_clamp():
+    """A macro at the upper z bound held against the far x and y sides grows as z moves into the
+    range (down), pushing its far edges outward, where the region holds them.  At the exact
+    position the adjoint's z component is the inward one-sided difference; with the position
+    rounded to float32 (the clamp's arithmetic), the far edges sit a rounding inside or outside the
+    faces, and the adjoint must take them as on the faces all the same: a rule that decided by the
+    rounding would count or drop whole face terms."""
+    c = _case(23, nz=4, macros=("uniform", 3, 0.04, 0.06))
+    geo = geometry_of(c)
+    rng = np.random.default_rng(6)
+    w = rng.normal(size=(geo.nz, geo.ny, geo.nx))
+    v = c.xyz0.astype(np.float64)
+    macros = [i for i in range(c.meta["n_cells"], c.n_inst) if (c.kind[i] & 2) == 0]
+    i = macros[0]
+    v[2, i] = 0.75 * geo.dz                      # top-die size exactly; moving down grows it
+    wt, ht = float(c.size[2, i]), float(c.size[3, i])
+    assert c.size[0, i] > c.size[2, i] and c.size[1, i] > c.size[3, i]
+    v[0, i] = geo.die_x - 0.5 * wt
+    v[1, i] = geo.die_y - 0.5 * ht
+    g = dg.density_vjp(c.size, c.kind, v, w, geo)
+    h = 1e-7 * geo.db
+    inward = _one_sided(c, v, w, geo, 2, i, h, False)
+    outward = _one_sided(c, v, w, geo, 2, i, h, True)
+    assert abs(g[2, i] - inward) <= 1e-5 * max(1.0, abs(inward)), (g[2, i], inward, outward)
+    assert abs(inward - outward) > 1e-3 * max(1.0, abs(inward))
+    for step in (-np.inf, np.inf):               # the float32 neighbours of the exact position
+        r = v.copy()
+        for a in (0, 1):
+            r[a, i] = float(np.nextafter(np.float32(v[a, i]), np.float32(step)))
+        r[2, i] = float(np.float32(v[2, i]))
+        gr = dg.density_vjp(c.size, c.kind, r, w, geo)
+        assert abs(gr[2, i] - g[2, i]) <= 1e-5 * max(1.0, abs(g[2, i])), (step, gr[2, i], g[2, i])
