@@ -264,6 +264,19 @@ PLACE3D_API int32_t place3d_wl_grad(place3d_ctx* ctx, const float* xyz, float* g
  * wirelength call of that form. */
 PLACE3D_API int32_t place3d_wl_value(place3d_ctx* ctx, const float* xyz, double* metrics, void* stream);
 
+/* place3d_wl_value for callers that cannot allocate device memory or take workspace scratch
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same metrics, with the call's scratch -- the packed positions and one float64
+ * partial per wirelength workgroup and net total -- in a static device array of the library
+ * (42 MiB on every GPU the library runs on, held until the process ends; its device address is
+ * looked up once per device, by place3d_create or the first call on that device) instead of the
+ * context's workspace.  It calls no allocating routine.  Limits: at most 2,097,152 instances and
+ * 262,144 wirelength workgroups (PLACE3D_ERR_SIZE beyond, nothing enqueued).  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race on it; calls ordered on one stream do not.  Nothing in it needs clearing: each
+ * call writes every word it reads first. */
+PLACE3D_API int32_t place3d_wl_value_static(place3d_ctx* ctx, const float* xyz, double* metrics, void* stream);
+
 /* Backward pass of the wirelength model: every net's extremes and shifted exponential sums are
  * recomputed from `xyz` (none is kept from the forward pass), and grad (+)= s * dW/dxyz with
  * s = d_scale ? d_scale[0] : 1 (device float64, the incoming gradient) and W = sum_e (W^_e(x) +

@@ -423,6 +423,8 @@ int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t by
     }
   }
   rc = build_schedule(c, s);
+  // the device address of the static scratch of place3d_wl_value_static, once per device
+  if (rc == PLACE3D_OK) rc = p3d::static_scratch_setup(c, nullptr);
   if (rc == PLACE3D_OK) {
     hipError_t e = hipMemsetAsync(c->red, 0, sizeof(double) * p3d::R_COUNT, s);
     if (e != hipSuccess) rc = p3d::hip_fail(c, e, "hipMemsetAsync(create)");
@@ -529,6 +531,13 @@ int32_t place3d_wl_value(place3d_ctx* ctx, const float* xyz, double* metrics, vo
   if (bad_ptr(xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "xyz NULL or misaligned");
   if (!metrics || (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "metrics NULL or misaligned");
   return p3d::wirelength_value(ctx, xyz, metrics, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t place3d_wl_value_static(place3d_ctx* ctx, const float* xyz, double* metrics, void* stream) {
+  if (int rc = check_ctx(ctx)) return rc;
+  if (bad_ptr(xyz)) return set_err(ctx, PLACE3D_ERR_ARG, "xyz NULL or misaligned");
+  if (!metrics || (reinterpret_cast<uintptr_t>(metrics) & 7)) return set_err(ctx, PLACE3D_ERR_ARG, "metrics NULL or misaligned");
+  return p3d::wirelength_value_static(ctx, xyz, metrics, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t place3d_wl_vjp(place3d_ctx* ctx, const float* xyz, const double* d_scale, int32_t z_mode, float* grad_xyz,

@@ -1131,9 +1131,14 @@ int launch_fill_f32(place3d_ctx* c, float* p, long long n, float v, hipStream_t 
 }
 
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s) {
+  return reduce_final_in(c, c->part, c->part_stride, slot0, nq, nparts, is_max, out, s);
+}
+
+int reduce_final_in(place3d_ctx* c, const double* part, int stride, int slot0, int nq, int nparts, bool is_max,
+                    double* out, hipStream_t s) {
   ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
-  hipLaunchKernelGGL(k_red_final, dim3(nq), dim3(256), 0, s, c->part, c->part_stride, slot0, nq, nparts,
-                     is_max ? 1 : 0, out, 0, 0, out);
+  hipLaunchKernelGGL(k_red_final, dim3(nq), dim3(256), 0, s, part, stride, slot0, nq, nparts, is_max ? 1 : 0, out,
+                     0, 0, out);
   P3D_LAUNCH(c, "k_red_final");
   return PLACE3D_OK;
 }

@@ -230,6 +230,9 @@ int field_split(place3d_ctx* c, const float* rho, float* phi, float* ex, float* 
 
 // out[0..nq) = sums (max if is_max) of partial slots slot0.. over nparts blocks, fixed order
 int reduce_final(place3d_ctx* c, int slot0, int nq, int nparts, bool is_max, double* out, hipStream_t s);
+// the same over the partials in `part` (stride per slot) instead of the workspace's
+int reduce_final_in(place3d_ctx* c, const double* part, int stride, int slot0, int nq, int nparts, bool is_max,
+                    double* out, hipStream_t s);
 // two sum reductions in one launch: slots slot0.. (nq0 of them, nparts0 partials) into out0[] and
 // slots slot1.. (nq1, nparts1) into out1[]
 int reduce_final2(place3d_ctx* c, int slot0, int nq0, int nparts0, double* out0, int slot1, int nq1, int nparts1,
@@ -258,7 +261,16 @@ int density_adjoint(place3d_ctx* c, const float* xyz, const float* gmap, float s
 int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulate, double* red,
                     double* metrics, hipStream_t s, bool packed = false, const double* dscale = nullptr,
                     bool with_fda = true);
-// the model's net totals only (no gradient, nothing per pin) into metrics[PLACE3D_NMETRICS]
-int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s);
+// the model's net totals only (no gradient, nothing per pin) into metrics[PLACE3D_NMETRICS]; the
+// packed positions and the per-workgroup partials go to xyzp / part (stride per slot) when given,
+// else to the workspace's
+int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s, float4* xyzp = nullptr,
+                     double* part = nullptr, int stride = 0);
+// the same with the scratch in the library's static device array (place3d_wl_value_static)
+constexpr int kStaticMaxInst = 1 << 21;      // instances whose positions the static scratch holds
+constexpr int kStaticMaxBlocks = 1 << 18;    // wirelength workgroups whose partials it holds
+int wirelength_value_static(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s);
+// device address of the static scratch on the current device, looked up once per device
+int static_scratch_setup(place3d_ctx* c, void** out);
 
 }  // namespace p3d

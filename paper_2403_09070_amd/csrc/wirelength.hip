@@ -25,6 +25,8 @@
 // a pin is (4/d_z)(W(owner on top) - W(owner on bottom)) in O(1): the pin leaves its set (the
 // second extreme replaces it when it was the first) and joins the other set at its other-die
 // offset.
+#include <mutex>
+
 #include "internal.h"
 
 namespace p3d {
@@ -645,27 +647,78 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
   return PLACE3D_OK;
 }
 
-int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s) {
+int wirelength_value(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s, float4* xyzp, double* part,
+                     int stride) {
   const Geom& g = c->g;
   const place3d_problem& p = c->prob;
   const bool comp = p.precision == PLACE3D_BF16X3;
+  if (!xyzp) { xyzp = c->xyzp; part = c->part; stride = c->part_stride; }
   int rc;
   if (c->n_wa_blocks > 0) {
     {
       ProfScope prof_(c, PLACE3D_STAGE_WL_NODES, s);
-      hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, xyz, c->xyzp);
+      hipLaunchKernelGGL(k_pack_xyz, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.n, xyz, xyzp);
       P3D_LAUNCH(c, "k_pack_xyz");
     }
     ProfScope prof_(c, PLACE3D_STAGE_WL_NETS, s);
     auto kern = comp ? k_wl_nets<false, true> : k_wl_nets<false, false>;
     hipLaunchKernelGGL(kern, dim3(c->n_wa_blocks), dim3(kWaBlock), 0, s, g.half_dz, 4.f / g.dz, (float)p.gamma,
-                       (float)p.alpha, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out,
-                       c->classes, c->wa_block_order, c->part, c->part_stride);
+                       (float)p.alpha, xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out,
+                       c->classes, c->wa_block_order, part, stride);
     P3D_LAUNCH(c, "k_wl_nets(value)");
   }
   // the five net totals straight into the metrics; the gradient norms are not computed here
   if ((rc = launch_zero_f64(c, metrics, PLACE3D_NMETRICS, s))) return rc;
-  return reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, metrics + PLACE3D_M_WA_BI, s);
+  return reduce_final_in(c, part, stride, R_WA_BI, 5, c->n_wa_blocks, false, metrics + PLACE3D_M_WA_BI, s);
+}
+
+// ---- the value call without workspace scratch (place3d_wl_value_static)
+//
+// Its per-call scratch lives in this array instead of the context's workspace: the packed
+// positions (16 B per instance) and one float64 partial per wirelength workgroup for each of the
+// five net totals.  Every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is only a stand-in): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticPosBytes = size_t(kStaticMaxInst) * sizeof(float4);
+constexpr size_t kStaticPartBytes = size_t(5 + R_WA_BI) * kStaticMaxBlocks * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kStaticPosBytes + kStaticPartBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch_setup(place3d_ctx* c, void** out) {
+  int dev = -1;
+  P3D_HIP(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(c, PLACE3D_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    P3D_HIP(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255))
+      return set_err(c, PLACE3D_ERR_HIP, "static scratch: no 256-byte aligned device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  if (out) *out = g_scratch_ptr[dev];
+  return PLACE3D_OK;
+}
+
+int wirelength_value_static(place3d_ctx* c, const float* xyz, double* metrics, hipStream_t s) {
+  if (c->g.n > kStaticMaxInst)
+    return set_err(c, PLACE3D_ERR_SIZE, "place3d_wl_value_static: more than " + std::to_string(kStaticMaxInst) +
+                                            " instances (its static scratch holds that many positions)");
+  if (c->n_wa_blocks > kStaticMaxBlocks)
+    return set_err(c, PLACE3D_ERR_SIZE, "place3d_wl_value_static: more than " + std::to_string(kStaticMaxBlocks) +
+                                            " wirelength workgroups (its static scratch holds that many partials)");
+  void* base = nullptr;
+  if (int rc = static_scratch_setup(c, &base)) return rc;
+  // every word of the scratch that is read is written first by the same call (positions by the
+  // pack pass, one partial per workgroup and total by the net pass), so nothing is cleared
+  float4* xyzp = reinterpret_cast<float4*>(base);
+  double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(base) + kStaticPosBytes);
+  return wirelength_value(c, xyz, metrics, s, xyzp, part, kStaticMaxBlocks);
 }
 
 }  // namespace p3d

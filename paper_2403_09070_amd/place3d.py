@@ -84,6 +84,7 @@ def lib():
             "place3d_density_vjp": (i32, [vp, vp, vp, f32, vp, vp, i32, vp]),
             "place3d_wl_grad": (i32, [vp, vp, vp, vp, i32, vp]),
             "place3d_wl_value": (i32, [vp, vp, vp, vp]),
+            "place3d_wl_value_static": (i32, [vp, vp, vp, vp]),
             "place3d_wl_vjp": (i32, [vp, vp, vp, i32, vp, i32, vp]),
             "place3d_read_scalars": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
             "place3d_gp_init": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
@@ -294,6 +295,13 @@ class Problem:
         xyz = self.xyz(xyz)
         met = torch.empty(NMETRICS, dtype=torch.float64, device=self.device)
         _check(lib().place3d_wl_value(self._ctx, _ptr(xyz), _ptr(met), _stream()), self._ctx)
+        return met
+
+    def wl_value_static(self, xyz):
+        """wl_value with the call's scratch in the library's static device array (no workspace scratch)."""
+        xyz = self.xyz(xyz)
+        met = torch.empty(NMETRICS, dtype=torch.float64, device=self.device)
+        _check(lib().place3d_wl_value_static(self._ctx, _ptr(xyz), _ptr(met), _stream()), self._ctx)
         return met
 
     def wl_vjp(self, xyz, d_scale=None, z_mode=WLZ_FDA, out=None, accumulate=False):
