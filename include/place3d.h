@@ -21,6 +21,8 @@
  *                       (Eq. improved-precond) and a Nesterov move
  *   place3d_plan_fillers host-side sizing of z-fixed and free fillers (Eqs. filler-vol,
  *                       free-filler-vol), appended by the caller as instances of kind FILLER
+ *   place3d_md2d_*      multi-die 2D global placement over three 2D fields (Sec. III-C,
+ *                       Eq. 2d-place), built on the calls above
  *
  * Instance kinds (PLACE3D_KIND_*) mark macros, fixed instances, fillers and z-held instances;
  * place3d_problem.options selects the paper's baseline algorithms for comparison (Sec. IV).
@@ -336,6 +338,89 @@ PLACE3D_API int32_t place3d_plan_fillers(int32_t n_inst, const float* size, cons
 PLACE3D_API int32_t place3d_profile_enable(place3d_ctx* ctx, int32_t on);
 PLACE3D_API int32_t place3d_profile_read(place3d_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
                                          int32_t reset);
+
+/* ------------------------------------------------------------------------------------------
+ * Multi-die 2D global placement (Sec. III-C, Eq. 2d-place).  With the die of every instance fixed
+ * by a 3D placement, the z axis is dropped: the bottom die, the top die and the layer of hybrid
+ * bonding terminals (HBTs) are three independent 2D electrostatic systems with their own weights,
+ * and the objective over the planar positions of all nodes is
+ *     sum_e W^_e(x, y) + lambda_bot U_bot + lambda_top U_top + lambda_hbt U_hbt,
+ * W^_e the WA model (Eq. wa-model-approx) of every partial net: a net with pins on both dies is
+ * split into a top and a bottom partial net that share one movable HBT node (the caller builds the
+ * nodes and partial nets; the HBTs are nodes of the HBT layer).  Each layer's density, potential,
+ * field and field-gather gradient are the 2D forms of place3d_density, place3d_field and
+ * place3d_field_force on that layer's nodes; the optimiser is place3d_step's in x and y, with the
+ * preconditioner of Eq. improved-precond taken with the node's layer weight and q = w h, lambda_0
+ * = |grad W|_1 / |grad U_L|_1 over each layer's movable nodes and all three weights multiplied by
+ * lambda_ramp every step.  Overflow of a layer: sum_b max(rho_b - rho_t, 0) area(b) over the map
+ * without fillers, divided by the area of its movable non-filler nodes.
+ * Conventions as above; positions are float32 [2][n_nodes] (x row, y row). */
+
+enum { PLACE3D_LAYER_BOTTOM = 0, PLACE3D_LAYER_TOP = 1, PLACE3D_LAYER_HBT = 2 };
+
+typedef struct place3d_md2d_problem {
+  int32_t n_nodes;         /* instances, HBTs and fillers                                     */
+  int32_t n_layer[3];      /* nodes on each layer (must match `layer`; each >= 1)             */
+  int32_t n_pins, n_nets;  /* partial nets                                                   */
+  int32_t nx, ny;          /* bin grid of every layer; nx, ny in [2, 8192]                   */
+  double die_x, die_y;
+  double gamma;            /* WA smoothing, length units (> 0)                               */
+  double target_density;   /* rho_t of the overflow metric                                    */
+  double lambda_ramp;
+  int32_t precision;       /* PLACE3D_FP32 or PLACE3D_BF16X3: the three spectral solves       */
+  /* device arrays, caller-owned, read-only, must outlive the context */
+  const float* size;       /* float32 [2][n_nodes]: w, h on the node's layer                  */
+  const uint8_t* kind;     /* uint8 [n_nodes]: PLACE3D_KIND_MACRO, _FIXED, _FILLER bits        */
+  const uint8_t* layer;    /* uint8 [n_nodes]: PLACE3D_LAYER_*                                */
+  const int32_t* net_start;/* int32 [n_nets+1], partial nets                                  */
+  const int32_t* pin2node; /* int32 [n_pins]                                                  */
+  const float* pin_off;    /* float32 [2][n_pins]: offset from the owner's centre             */
+  const float* fixed_xy;   /* float32 [2][n_nodes]: positions of the fixed nodes              */
+} place3d_md2d_problem;
+
+/* Metrics of a multi-die 2D evaluation (device float64 [PLACE3D_NMETRICS]). */
+enum { PLACE3D_MD_WA = 0,        /* sum of the partial nets' WA wirelength, x + y            */
+       PLACE3D_MD_HPWL = 1,      /* sum of their exact HPWL                                  */
+       PLACE3D_MD_OVFL = 2,      /* slots 2, 3, 4: overflow of the bottom, top and HBT layer */
+       PLACE3D_MD_ENERGY = 5 };  /* slots 5, 6, 7: U of each layer (place3d_md2d_eval only)   */
+
+/* Optimiser scalars of a multi-die 2D state (device float64 [PLACE3D_NSCALARS]). */
+enum { PLACE3D_MS_A = 0,         /* Nesterov a_k                                             */
+       PLACE3D_MS_LAMBDA = 1,    /* slots 1, 2, 3: lambda of the bottom, top and HBT layer   */
+       PLACE3D_MS_STEP = 4, PLACE3D_MS_ITER = 5,
+       PLACE3D_MS_METRICS = 8,   /* slots 8..12: PLACE3D_MD_WA .. OVFL+2 at the evaluation point */
+       PLACE3D_MS_NONFINITE = 16 /* as PLACE3D_S_NONFINITE                                    */ };
+
+typedef struct place3d_md2d_state {
+  float* u;        /* float32 [2][n_nodes] */
+  float* v;
+  float* v_prev;
+  float* g_prev;
+  double* scalars; /* float64 [PLACE3D_NSCALARS], PLACE3D_MS_* slots */
+} place3d_md2d_state;
+
+typedef struct place3d_md2d_ctx place3d_md2d_ctx;
+
+/* Workspace bytes (256-byte aligned base) of a multi-die 2D context. */
+PLACE3D_API int32_t place3d_md2d_workspace_size(const place3d_md2d_problem* prob, size_t* bytes);
+/* Validate, read the node arrays and netlist back once, build the per-layer and wirelength
+ * sub-problems in the workspace and create their contexts.  Synchronises `stream`. */
+PLACE3D_API int32_t place3d_md2d_create(const place3d_md2d_problem* prob, void* d_workspace, size_t bytes,
+                                        void* stream, place3d_md2d_ctx** out);
+PLACE3D_API int32_t place3d_md2d_destroy(place3d_md2d_ctx* ctx);
+PLACE3D_API const char* place3d_md2d_last_error(const place3d_md2d_ctx* ctx);
+/* The objective's parts at `xy`: grad_wl (+)= dW/dxy, grad_den = d U_L / dxy of every node for its
+ * own layer L (field gather, not scaled by lambda; zero for fixed nodes), both float32
+ * [2][n_nodes]; rho (may be NULL) the three layer maps float32 [3][ny][nx]; metrics (may be NULL)
+ * the PLACE3D_MD_* values. */
+PLACE3D_API int32_t place3d_md2d_eval(place3d_md2d_ctx* ctx, const float* xy, float* grad_wl, float* grad_den,
+                                      float* rho, double* metrics, void* stream);
+/* u = v = clamp(xy0), lambda_0 of each layer, the bootstrap point and its gradient. */
+PLACE3D_API int32_t place3d_md2d_gp_init(place3d_md2d_ctx* ctx, place3d_md2d_state* state, const float* xy0,
+                                         void* stream);
+/* One iteration: both objective parts at state->v, the preconditioned gradient, the Lipschitz
+ * step, the Nesterov move and the clamp; the three lambdas grow by lambda_ramp. */
+PLACE3D_API int32_t place3d_md2d_step(place3d_md2d_ctx* ctx, place3d_md2d_state* state, void* stream);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libplace3d.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["context.cpp", "density.hip", "spectral.hip", "spectral_split.hip", "wirelength.hip", "step.hip"]
+SOURCES = ["context.cpp", "density.hip", "spectral.hip", "spectral_split.hip", "wirelength.hip", "step.hip",
+           "multidie.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

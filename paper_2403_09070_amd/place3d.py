@@ -61,6 +61,20 @@ class State_(ctypes.Structure):
                 ("g_prev", ctypes.c_void_p), ("scalars", ctypes.c_void_p)]
 
 
+class MdProblem_(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_layer", ctypes.c_int32 * 3), ("n_pins", ctypes.c_int32),
+                ("n_nets", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("die_x", ctypes.c_double), ("die_y", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("target_density", ctypes.c_double), ("lambda_ramp", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("size", ctypes.c_void_p), ("kind", ctypes.c_void_p), ("layer", ctypes.c_void_p),
+                ("net_start", ctypes.c_void_p), ("pin2node", ctypes.c_void_p), ("pin_off", ctypes.c_void_p),
+                ("fixed_xy", ctypes.c_void_p)]
+
+
+LAYER_BOTTOM, LAYER_TOP, LAYER_HBT = 0, 1, 2
+MD = dict(wa=0, hpwl=1, ovfl_bot=2, ovfl_top=3, ovfl_hbt=4, energy_bot=5, energy_top=6, energy_hbt=7)
+MS = dict(a=0, lam_bot=1, lam_top=2, lam_hbt=3, step=4, it=5, metrics=8, nonfinite=16)
+
 _lib = None
 
 
@@ -94,6 +108,13 @@ def lib():
                                            ctypes.c_double, ctypes.c_double, ctypes.POINTER(FillerPlan_)]),
             "place3d_profile_read": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64), i32]),
+            "place3d_md2d_workspace_size": (i32, [ctypes.POINTER(MdProblem_), ctypes.POINTER(ctypes.c_size_t)]),
+            "place3d_md2d_create": (i32, [ctypes.POINTER(MdProblem_), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+            "place3d_md2d_destroy": (i32, [vp]),
+            "place3d_md2d_last_error": (ctypes.c_char_p, [vp]),
+            "place3d_md2d_eval": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+            "place3d_md2d_gp_init": (i32, [vp, ctypes.POINTER(State_), vp, vp]),
+            "place3d_md2d_step": (i32, [vp, ctypes.POINTER(State_), vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -359,3 +380,115 @@ class Problem:
 def metrics_dict(met):
     m = met.cpu().numpy()
     return {k: float(m[v]) for k, v in M.items()}
+
+
+def _check_md(rc, ctx=None):
+    if rc != OK:
+        msg = lib().place3d_md2d_last_error(ctx)
+        raise Place3dError(rc, msg.decode() if msg else "")
+
+
+@dataclass
+class MdState:
+    u: torch.Tensor
+    v: torch.Tensor
+    v_prev: torch.Tensor
+    g_prev: torch.Tensor
+    scalars: torch.Tensor
+
+    def cstruct(self):
+        return State_(self.u.data_ptr(), self.v.data_ptr(), self.v_prev.data_ptr(), self.g_prev.data_ptr(),
+                      self.scalars.data_ptr())
+
+    def read(self):
+        s = self.scalars.cpu().numpy()
+        out = {k: float(s[v]) for k, v in MS.items() if k != "metrics"}
+        for k, v in MD.items():
+            if v < 5:
+                out[k] = float(s[MS["metrics"] + v])
+        return out
+
+
+class MultiDie2D:
+    """A multi-die 2D placement problem (Sec. III-C, Eq. 2d-place) on the GPU with its context:
+    nodes (instances at their die's size, HBTs, fillers) with a layer each, and the partial nets.
+    ``size`` is [2][n] (w, h), ``pin_off`` [2][P]; the arrays are copied to the device once."""
+
+    def __init__(self, *, size, kind, layer, net_start, pin2node, pin_off, fixed_xy, die_x, die_y, nx, ny, gamma,
+                 target_density=1.0, lambda_ramp=1.05, precision=FP32, device="cuda"):
+        L = lib()
+        dev = torch.device(device)
+        self.device = dev
+        layer = np.asarray(layer, dtype=np.uint8)
+        self.n = int(layer.shape[0])
+        self.P = int(np.asarray(pin2node).shape[0])
+        self.m = int(np.asarray(net_start).shape[0] - 1)
+        self.nx, self.ny = int(nx), int(ny)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+        self.size = t(size, torch.float32)
+        self.kind = t(kind, torch.uint8)
+        self.layer = t(layer, torch.uint8)
+        self.net_start = t(net_start, torch.int32)
+        self.pin2node = t(pin2node if self.P else np.zeros(1, np.int32), torch.int32)
+        self.pin_off = t(pin_off if self.P else np.zeros((2, 1), np.float32), torch.float32)
+        self.fixed_xy = t(fixed_xy, torch.float32)
+        counts = np.bincount(layer, minlength=3)[:3]
+        self._p = MdProblem_(self.n, (ctypes.c_int32 * 3)(*[int(c) for c in counts]), self.P, self.m, self.nx,
+                             self.ny, float(die_x), float(die_y), float(gamma), float(target_density),
+                             float(lambda_ramp), int(precision), self.size.data_ptr(), self.kind.data_ptr(),
+                             self.layer.data_ptr(), self.net_start.data_ptr(), self.pin2node.data_ptr(),
+                             self.pin_off.data_ptr(), self.fixed_xy.data_ptr())
+        nbytes = ctypes.c_size_t()
+        _check_md(L.place3d_md2d_workspace_size(ctypes.byref(self._p), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self._ctx = ctypes.c_void_p()
+        _check_md(L.place3d_md2d_create(ctypes.byref(self._p), ctypes.c_void_p(aligned), nbytes.value, _stream(),
+                                        ctypes.byref(self._ctx)))
+
+    @classmethod
+    def from_layered(cls, lay, **kw):
+        """From a multi-die problem in the layout the multi-die oracle uses (w, h, kind, layer, partial
+        nets, grid, gamma, ramp, target as attributes; fixed nodes take fixed_xy, default zeros)."""
+        fixed_xy = kw.pop("fixed_xy", np.zeros((2, len(lay.w)), np.float32))
+        g = lay.grid
+        return cls(size=np.stack([lay.w, lay.h]).astype(np.float32), kind=lay.kind, layer=lay.layer,
+                   net_start=np.asarray(lay.net_start, np.int32), pin2node=np.asarray(lay.pin2node, np.int32),
+                   pin_off=np.asarray(lay.pin_off, np.float32), fixed_xy=fixed_xy, die_x=g.die_x, die_y=g.die_y,
+                   nx=g.nx, ny=g.ny, gamma=lay.gamma, target_density=lay.target, lambda_ramp=lay.ramp, **kw)
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value and _lib is not None:
+            _lib.place3d_md2d_destroy(ctx)
+            self._ctx = None
+
+    def xy(self, a):
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(self.device) \
+            if not isinstance(a, torch.Tensor) else a.to(device=self.device, dtype=torch.float32).contiguous()
+
+    def eval(self, xy, want_maps=True):
+        """(grad_wl [2][n], grad_den [2][n], rho [3][ny][nx] or None, metrics float64 [NMETRICS])."""
+        xy = self.xy(xy)
+        gw = torch.empty((2, self.n), dtype=torch.float32, device=self.device)
+        gd = torch.empty_like(gw)
+        rho = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device=self.device) if want_maps else None
+        met = torch.empty(NMETRICS, dtype=torch.float64, device=self.device)
+        _check_md(lib().place3d_md2d_eval(self._ctx, _ptr(xy), _ptr(gw), _ptr(gd), _ptr(rho), _ptr(met), _stream()),
+                  self._ctx)
+        return gw, gd, rho, met
+
+    def new_state(self):
+        z = lambda: torch.zeros((2, self.n), dtype=torch.float32, device=self.device)  # noqa: E731
+        return MdState(z(), z(), z(), z(), torch.zeros(NSCALARS, dtype=torch.float64, device=self.device))
+
+    def gp_init(self, xy0, state=None):
+        st = self.new_state() if state is None else state
+        xy0 = self.xy(xy0)
+        cs = st.cstruct()
+        _check_md(lib().place3d_md2d_gp_init(self._ctx, ctypes.byref(cs), _ptr(xy0), _stream()), self._ctx)
+        return st
+
+    def step(self, state):
+        cs = state.cstruct()
+        _check_md(lib().place3d_md2d_step(self._ctx, ctypes.byref(cs), _stream()), self._ctx)

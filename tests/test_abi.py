@@ -113,3 +113,47 @@ def test_filler_plan_matches_the_oracle(L):
         place3d.plan_fillers(c.size, c.kind, c.xyz0[2], c.die_x, c.die_y, c.nx, c.ny, c.nz, 1.5, 0.8)
     with pytest.raises(place3d.Place3dError):
         place3d.plan_fillers(c.size, np.full_like(c.kind, 1), c.xyz0[2], c.die_x, c.die_y, c.nx, c.ny, c.nz, 0.8, 0.8)
+
+
+def _md_problem(**kw):
+    from paper_2403_09070_amd.place3d import MdProblem_
+    p = MdProblem_(120, (ctypes.c_int32 * 3)(60, 50, 10), 40, 12, 16, 16, 10.0, 10.0, 1.0, 1.0, 1.05, 0,
+                   16, 32, 48, 64, 80, 96, 112)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n_nodes", 2, -2), ("n_nodes", 121, -2), ("layer", 0, -1), ("size", 0, -1), ("pin_off", 18, -1), ("nx", 1, -2),
+    ("gamma", 0.0, -1), ("precision", 3, -1),
+])
+def test_md2d_workspace_size_rejects_bad_problems(L, field, value, code):
+    """The multi-die 2D context checks its problem on the host; sizes beyond the sub-problems'
+    limits come back from their own checks."""
+    n = ctypes.c_size_t()
+    p = _md_problem(**{field: value})
+    assert L.place3d_md2d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == code
+    assert L.place3d_md2d_last_error(None)
+
+
+def test_md2d_workspace_covers_four_contexts(L):
+    """The multi-die workspace holds the wirelength context's and the three layer contexts'
+    workspaces (each at least that of a one-layer-pair 3D problem of its node count)."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.place3d_md2d_workspace_size(ctypes.byref(_md_problem()), ctypes.byref(a)) == 0
+    one = _problem(n_inst=120, n_pins=40, n_nets=12, nx=16, ny=16, nz=2, alpha=0.0)
+    assert L.place3d_workspace_size(ctypes.byref(one), ctypes.byref(b)) == 0
+    assert a.value > 2 * b.value and a.value % 256 == 0
+
+
+def test_md2d_calls_reject_a_null_context_or_workspace(L):
+    out = ctypes.c_void_p()
+    p = _md_problem()
+    assert L.place3d_md2d_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(out)) == -1
+    assert L.place3d_md2d_create(ctypes.byref(p), ctypes.c_void_p(4096 + 8), 1 << 20, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert L.place3d_md2d_eval(None, None, None, None, None, None, None) == -1
+    assert L.place3d_md2d_gp_init(None, None, None, None) == -1
+    assert L.place3d_md2d_step(None, None, None) == -1
+    assert L.place3d_md2d_destroy(None) == 0
