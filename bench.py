@@ -167,12 +167,25 @@ def run_forms(case, names, forms, args, log):
     return out
 
 
-def cpu_baseline(case, frac=4):
-    """FP64 oracle, one GP iteration estimated from a bounded sample of the same workload: the
-    density map and field gather on every frac-th instance, the wirelength (with the vanilla FDA)
-    on the first 1/frac of the nets, each time scaled by frac, plus one full spectral solve."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case):
+    """One full FP64 oracle GP iteration of the same workload, stage by stage and unsampled: the
+    wirelength with the vanilla FDA, the density map, the dense spectral solve, the field gather,
+    the preconditioned gradient, the Nesterov move and the overflow (the steps of
+    oracle.optimizer.gp_step, called one by one to time them), from the start placement.  The
+    spectral solve's contractions run on the BLAS thread pool and are timed again on one thread;
+    every other stage is single-threaded NumPy."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import density as den
     from oracle import density_grad as dg
     from oracle import optimizer as opt
@@ -180,31 +193,49 @@ def cpu_baseline(case, frac=4):
     from oracle import wirelength as wl
     pb = opt.problem_of(case)
     geo = pb.geo
-    idx = np.arange(0, case.n_inst, frac)
+    pool = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     t = {}
+    v = opt.clamp(pb, case.xyz0)
     t0 = time.perf_counter()
-    rho = den.density_map(case.size[:, idx], case.kind[idx], case.xyz0[:, idx], geo)
-    t["density"] = (time.perf_counter() - t0) * frac
+    w = wl.wirelength(pb.size, pb.kind, v, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+    t["wirelength"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    sol = poisson.solve(rho, geo, want=("ex", "ey", "ez"))
+    rho = den.density_map(pb.size, pb.kind, v, geo)
+    t["density"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sol = poisson.solve(rho, geo, want=("phi", "ex", "ey", "ez"))
     t["field"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    dg.field_gather(case.size[:, idx], case.kind[idx], case.xyz0[:, idx], sol["ex"], sol["ey"], sol["ez"], geo)
-    t["gather"] = (time.perf_counter() - t0) * frac
-    m = case.n_nets // frac
-    P = int(case.net_start[m])
+    gd = dg.field_gather(pb.size, pb.kind, v, sol["ex"], sol["ey"], sol["ez"], geo)
+    t["gather"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    wl.wirelength(case.size, case.kind, case.xyz0, case.net_start[:m + 1], case.pin2node[:P],
-                  case.pin_off[:, :P], geo, pb.gamma, pb.alpha)
-    t["wirelength"] = (time.perf_counter() - t0) * frac
+    lam = 1.0
+    g = (w["grad"] + lam * gd) / opt.preconditioner(pb, v, lam)[None, :]
+    st = opt.GPState(u=v.copy(), v=v.copy(), v_prev=v.copy(), g_prev=np.zeros_like(g), a=1.0, lam=lam)
+    opt.nesterov_update(st, g, lambda p: opt.clamp(pb, p), pb.movable)
+    opt.overflow(pb, rho, v)
+    t["update"] = time.perf_counter() - t0
     per_iter = sum(t.values())
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return {"value": 1.0 / per_iter, "unit": "iterations/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"one FP64 oracle iteration of the same 1.2M-cell workload, estimated from every "
-                       f"{frac}th instance (density, field gather) and the first 1/{frac} of the nets "
-                       f"(WA + vanilla FDA), each scaled x{frac}, plus one full dense spectral solve; "
-                       f"per-stage seconds " + ", ".join(f"{k} {v:.2f}" for k, v in t.items())),
-            "seconds_per_iteration": per_iter}
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        poisson.solve(rho, geo, want=("phi", "ex", "ey", "ez"))
+        field_1 = time.perf_counter() - t0
+    per_iter_1 = per_iter - t["field"] + field_1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": 1.0 / per_iter, "unit": "iterations/s", "cores": int(pool), "kind": "oracle",
+            "sample": (f"one full FP64 oracle GP iteration of the same {case.n_inst}-instance workload at its "
+                       f"start placement, every instance and net (no sampling, no extrapolation): the stages of "
+                       f"oracle.optimizer.gp_step timed one by one"),
+            "seconds_per_iteration": per_iter,
+            "stage_seconds": {k: round(x, 3) for k, x in t.items()},
+            "threads_per_stage": {"wirelength": 1, "density": 1, "field": int(pool), "gather": 1, "update": 1},
+            "one_thread": {"value": 1.0 / per_iter_1, "seconds_per_iteration": per_iter_1,
+                           "field_seconds": round(field_1, 3)},
+            "host": {"nproc": os.cpu_count(), "affinity": affinity, "cpu_model": _cpu_model(),
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}}
 
 
 def precond_ablation(args, log):
@@ -401,7 +432,7 @@ def main():
     ap.add_argument("--readback-every", type=int, default=10,
                     help="read the metrics back to the host every this many timed steps (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mixed")
+    ap.add_argument("--forms", default="plain,mixed,autograd")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -436,8 +467,6 @@ def main():
         return
     if args.ablation == "converge":
         args.config = args.config or "c5"
-        if args.forms == "plain,mixed":
-            args.forms = "plain,mixed,autograd"
         converge_run(args, log)
         return
     args.config = args.config or "c4"
@@ -506,6 +535,11 @@ def main():
                                "mixed_over_plain": round(res["mixed"]["ips"] / res["plain"]["ips"], 3),
                                "hpwl_plain": hp, "hpwl_mixed": hm, "hpwl_rel_diff": abs(hm - hp) / hp,
                                "iterations": args.warmup + args.profile_steps + args.steps})
+    if "plain" in res and "autograd" in res:
+        hp, ha = res["plain"]["state"]["hpwl"], res["autograd"]["state"]["hpwl"]
+        line["config"].update({"autograd_iters_per_s": round(res["autograd"]["ips"], 2),
+                               "autograd_over_plain": round(res["autograd"]["ips"] / res["plain"]["ips"], 3),
+                               "hpwl_autograd": ha, "hpwl_autograd_rel_diff": abs(ha - hp) / hp})
     if roof:
         line["roofline"] = roof
     if not args.no_cpu_baseline:

@@ -1,12 +1,14 @@
-"""Parity at the full 1.2M-cell workload (1.3M nets, 4.5M pins, grid 1024 x 1024 x 4) in the
-configuration the benchmark times: split-bf16 contractions, field-gather density gradient,
-launched exactly as place3d_step launches them (folded contractions, the net schedule and the
-tile bucketing of that size).  Every output is compared in full against the oracle on the same
-seeded inputs, with the tolerances of the small-case parity tests:
+"""Parity at the full 1.2M-cell workload (1.3M nets, 4.5M pins, grid 1024 x 1024 x 4) in every
+form the benchmark times -- split-bf16 and float32 contractions, compensated and plain
+exponential sums, field-gather and exact-adjoint density gradients -- launched exactly as
+place3d_step launches them (folded contractions, the net schedule and the tile bucketing of that
+size).  Every output is compared in full against the oracle on the same seeded inputs, with the
+tolerances of the small-case parity tests:
   density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
   many overlapping cells), field rel L2 <= 1e-4, wirelength totals rel <= 1e-5, WA x/y gradient
-  rel L2 <= 1e-5, FDA z-gradient within (4/d_z) npins 8 ulp(d_x) per instance, field gather rel L2
-  <= 1e-5.  Inputs of a stage come from the oracle (rounded to float32 for both sides).
+  rel L2 <= 1e-5, FDA z-gradient within (4/d_z) npins 8 ulp(d_x) per instance, field gather and
+  exact adjoint rel L2 <= 1e-5.  Inputs of a stage come from the oracle (rounded to float32 for
+  both sides).
 """
 import numpy as np
 import pytest
@@ -22,17 +24,21 @@ from paper_2403_09070_amd import synth
 pytestmark = pytest.mark.gpu
 
 
+PRECISIONS = ["bf16x3", "fp32"]
+
+
 @pytest.fixture(scope="module")
 def full():
     need_gpu()
     from paper_2403_09070_amd import place3d
     log("[full] generating the 1.2M-cell workload")
     case = synth.make_case("c4", 2403)
-    prob = gpu_problem(case, precision=place3d.BF16X3, dgrad=place3d.DGRAD_FIELD)
+    probs = {"bf16x3": gpu_problem(case, precision=place3d.BF16X3, dgrad=place3d.DGRAD_FIELD),
+             "fp32": gpu_problem(case, precision=place3d.FP32, dgrad=place3d.DGRAD_FIELD)}
     geo = geometry_of(case)
     log("[full] oracle density map")
     rho = oden.density_map(case.size, case.kind, case.xyz0, geo)
-    return case, prob, geo, rho
+    return case, probs, geo, rho
 
 
 def _clustered(case, seed=11):
@@ -49,7 +55,8 @@ def _clustered(case, seed=11):
 
 @pytest.mark.parametrize("where", ["generated", "clustered"])
 def test_density_full(full, where):
-    case, prob, geo, rho_gen = full
+    case, probs, geo, rho_gen = full
+    prob = probs["bf16x3"]
     xyz = case.xyz0 if where == "generated" else _clustered(case)
     ref = rho_gen if where == "generated" else oden.density_map(case.size, case.kind, xyz, geo)
     got = prob.density(xyz).cpu().numpy()
@@ -59,21 +66,23 @@ def test_density_full(full, where):
     assert abs(got.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
 
 
-def test_field_full(full):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_field_full(full, precision):
     import torch
-    case, prob, geo, rho = full
+    case, probs, geo, rho = full
     rho32 = rho.astype(np.float32)
-    out = prob.field(torch.from_numpy(rho32).cuda(), want=("phi", "ex", "ey", "ez"))
+    out = probs[precision].field(torch.from_numpy(rho32).cuda(), want=("phi", "ex", "ey", "ez"))
     ref = opois.solve(rho32.astype(np.float64), geo)
     for k in ("phi", "ex", "ey", "ez"):
         err = rel_l2(out[k].cpu().numpy(), ref[k])
-        log(f"[full] field {k} rel_l2={err:.3e}")
+        log(f"[full] {precision} field {k} rel_l2={err:.3e}")
         assert err <= 1e-4, k
 
 
 def test_field_gather_full(full):
     import torch
-    case, prob, geo, rho = full
+    case, probs, geo, rho = full
+    prob = probs["bf16x3"]
     sol = opois.solve(rho.astype(np.float32).astype(np.float64), geo, want=("ex", "ey", "ez"))
     maps = [sol[k].astype(np.float32) for k in ("ex", "ey", "ez")]
     g = prob.field_force(case.xyz0, *(torch.from_numpy(m).cuda() for m in maps), lam=1.0).cpu().numpy()
@@ -84,21 +93,28 @@ def test_field_gather_full(full):
     assert err <= 1e-5
 
 
-def test_wirelength_full(full):
-    case, prob, geo, rho = full
+@pytest.fixture(scope="module")
+def wl_ref(full):
+    case, probs, geo, rho = full
     pb = oracle_problem(case)
-    g, met = prob.wl_grad(case.xyz0)
+    log("[full] oracle wirelength")
+    return owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_wirelength_full(full, wl_ref, precision):
+    case, probs, geo, rho = full
+    g, met = probs[precision].wl_grad(case.xyz0)
     g = g.cpu().numpy()
     met = met.cpu().numpy()
-    log("[full] oracle wirelength")
-    ref = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+    ref = wl_ref
     for key, slot in (("wa_bi", 0), ("wa_z", 1), ("hpwl_d2d", 2), ("hpwl_3d", 3)):
         err = abs(met[slot] - ref[key]) / abs(ref[key])
-        log(f"[full] {key} gpu={met[slot]:.10g} ref={ref[key]:.10g} rel={err:.2e}")
+        log(f"[full] {precision} {key} gpu={met[slot]:.10g} ref={ref[key]:.10g} rel={err:.2e}")
         assert err <= 1e-5, key
     assert int(round(met[4])) == ref["ncut"]
     ex, ey = rel_l2(g[0], ref["grad_x"]), rel_l2(g[1], ref["grad_y"])
-    log(f"[full] wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
+    log(f"[full] {precision} wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
     assert ex <= 1e-5 and ey <= 1e-5
     scale = met[8]
     assert abs(scale - ref["fda_scale"]) <= 1e-5 * ref["fda_scale"]
@@ -109,3 +125,19 @@ def test_wirelength_full(full):
     diff = np.abs(g[2] - want)
     log(f"[full] z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e}")
     assert np.all(diff <= bound)
+
+
+def test_density_vjp_full(full):
+    """The exact adjoint (the differentiation form's density backward) at full size, applied to the
+    oracle's potential times the bin volume (rounded to float32 on both sides): the gradient of
+    the energy, against the oracle's adjoint."""
+    import torch
+    case, probs, geo, rho = full
+    phi = opois.solve(rho.astype(np.float32).astype(np.float64), geo, want=("phi",))["phi"]
+    gmap = (phi * geo.vol_bin).astype(np.float32)
+    g = probs["bf16x3"].density_vjp(case.xyz0, torch.from_numpy(gmap).cuda()).cpu().numpy()
+    log("[full] oracle exact adjoint")
+    ref = odg.density_vjp(case.size, case.kind, case.xyz0, gmap.astype(np.float64), geo)
+    err = rel_l2(g, ref)
+    log(f"[full] density-vjp rel_l2={err:.3e}")
+    assert err <= 1e-5

@@ -3,9 +3,10 @@
 * gp_init: lambda_0 and the bootstrap point agree with the oracle's.
 * One step from the same state (the oracle's state rounded to float32 on both sides): the
   metrics at the evaluation point and the new iterate agree.  The step size divides by
-  |g_k - g_{k-1}|, which amplifies the float32 rounding of the gradient by |g| / |g_k - g_{k-1}|,
-  so the displacement is compared at 1e-3 relative (measured well below).
-* A short trajectory: the D2D HPWL of GPU and oracle stay within 1e-3 of each other.
+  |g_k - g_{k-1}|, which amplifies the float32 rounding of the gradient by |g| / |g_k - g_{k-1}|;
+  the bars are about ten times the measured errors of each form (DISP_BAR).
+* A short trajectory: the D2D HPWL of GPU and oracle stay within 2e-6 of each other (measured
+  1.9e-7 over 20 steps).
 * The ePlace and ePlace3D preconditioners of Eq. general-precond: init and one step, as above.
 * Fillers (z-fixed and free): init, one step and a 20-step trajectory with the overflow measured
   without them; z-fixed fillers keep their z exactly.
@@ -30,6 +31,11 @@ FORMS = {
     "field-bf16x3-eplace3d": dict(dgrad=place3d.DGRAD_FIELD, precision=place3d.BF16X3,
                                   precond=place3d.PRECOND_EPLACE3D),
 }
+# one-step displacement bars, about ten times the measured rel L2 (float32 field gather 1.3e-6,
+# split-bf16 3.7e-6, split-bf16 with the exact adjoint 2.4e-5, ePlace 5.1e-6, ePlace3D 3.1e-6)
+DISP_BAR = {"field-fp32": 2e-5, "field-bf16x3": 5e-5, "adjoint-bf16x3": 3e-4, "field-bf16x3-eplace": 1e-4,
+            "field-bf16x3-eplace3d": 5e-5}
+STEP_BAR = 1e-5      # the Lipschitz step size (measured <= 9.1e-7)
 PRECOND_NAMES = {place3d.PRECOND_MIXED: "mixed", place3d.PRECOND_EPLACE: "eplace",
                  place3d.PRECOND_EPLACE3D: "eplace3d"}
 
@@ -103,7 +109,7 @@ def test_one_step_from_the_same_state(form):
     step_err = abs(s["step"] - m["step"]) / m["step"]
     disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
     log(f"[step] {form} step rel={step_err:.3e} displacement rel_l2={disp:.3e}")
-    assert step_err <= 1e-3 and disp <= 1e-3
+    assert step_err <= STEP_BAR and disp <= DISP_BAR[form]
     if FORMS[form]["dgrad"] == place3d.DGRAD_ADJOINT:
         assert abs(s["energy"] - m["energy"]) <= 1e-4 * abs(m["energy"])
 
@@ -125,7 +131,7 @@ def test_short_trajectory_tracks_the_oracle():
         worst = max(worst, d)
         log(f"[step] it {k} hpwl gpu={s['hpwl']:.7g} ref={m['hpwl_d2d']:.7g} rel={d:.2e} "
             f"ovfl gpu={s['ovfl_bot']:.4f}/{s['ovfl_top']:.4f} ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
-    assert worst <= 1e-3
+    assert worst <= 2e-6
 
 
 def test_fillers_init_step_and_trajectory():
@@ -160,12 +166,13 @@ def test_fillers_init_step_and_trajectory():
         worst_h, worst_o = max(worst_h, dh), max(worst_o, do)
         saw_overflow |= max(m["ovfl_bot"], m["ovfl_top"]) > 0.05
         log(f"[step] fillers it {k} hpwl rel={dh:.2e} ovfl gpu={s['ovfl_bot']:.4f}/{s['ovfl_top']:.4f} "
-            f"ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
+            f"ref={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f} diff={do:.2e}")
     v = st.v.cpu().numpy()
     assert np.array_equal(v[2, held], z_held) and np.array_equal(st.u.cpu().numpy()[2, held], z_held)
     assert np.abs(v[2, free] - z_free).max() > 0.0
     assert saw_overflow
-    assert worst_h <= 1e-3 and worst_o <= 1e-3
+    # measured: HPWL 3.1e-6 after 20 steps, overflow equal to the fourth decimal every step
+    assert worst_h <= 3e-5 and worst_o <= 1e-5
 
 
 def test_fillers_one_step_from_the_same_state():
@@ -190,7 +197,7 @@ def test_fillers_one_step_from_the_same_state():
     disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
     log(f"[step] fillers step rel={step_err:.3e} displacement rel_l2={disp:.3e} "
         f"ovfl={m['ovfl_bot']:.4f}/{m['ovfl_top']:.4f}")
-    assert step_err <= 1e-3 and disp <= 1e-3
+    assert step_err <= STEP_BAR and disp <= 3e-4        # measured 1.5e-8, 2.6e-5
 
 
 def test_baseline_algorithms_in_the_step():
@@ -210,7 +217,7 @@ def test_baseline_algorithms_in_the_step():
         dh = abs(ra["hpwl"] - rb["hpwl"]) / ra["hpwl"]
         do = max(abs(ra["ovfl_bot"] - rb["ovfl_bot"]), abs(ra["ovfl_top"] - rb["ovfl_top"]))
         log(f"[step] options it {k} hpwl rel={dh:.2e} ovfl diff={do:.2e}")
-        assert dh <= 1e-4 and do <= 1e-4
+        assert dh <= 1e-5 and do <= 1e-5                   # measured 1.3e-6, 0
 
 
 def test_nonfinite_iteration_is_flagged_and_reported():
