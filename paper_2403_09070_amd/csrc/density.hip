@@ -309,29 +309,62 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(Geom g, TileGeo
       for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * t.ntx + tx], 1);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) counts[(size_t)k * t.nblk + blockIdx.x] = hist[k];
+  // block-major: this block's counts are one contiguous row
+  for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) counts[(size_t)blockIdx.x * t.ntiles + k] = hist[k];
 }
 
-// exclusive scan of one tile's counts over the bucket blocks (in place); the tile total to totals
-__global__ __launch_bounds__(256) void k_bucket_scan_rows(int nblk, int32_t* __restrict__ counts,
-                                                          int32_t* __restrict__ totals) {
-  __shared__ int sh[256];
-  int32_t* row = counts + (size_t)blockIdx.x * nblk;
-  const int per = (nblk + 255) / 256;
-  const int b0 = threadIdx.x * per, b1 = min(b0 + per, nblk);
+// Exclusive scan of every tile's counts over the bucket blocks (in place, counts block-major
+// [nblk][ntiles]); the tile totals to totals.  A workgroup takes 64 adjacent tiles: lane l of
+// wavefront q scans tile 64 g + l over the q-th of kScanParts ranges of blocks, so that a
+// wavefront reads 64 adjacent counts (256 bytes) of one block row at a time; each range is then
+// offset by the sums of the ranges before it.  A range of up to kScanHeld rows is loaded once into
+// registers (all its loads in flight together) and written back from them.
+constexpr int kScanTiles = 64;
+constexpr int kScanParts = 16;
+constexpr int kScanHeld = 48;
+__global__ __launch_bounds__(kScanTiles * kScanParts) void k_bucket_scan_cols(int nblk, int ntiles,
+                                                                             int32_t* __restrict__ counts,
+                                                                             int32_t* __restrict__ totals) {
+  __shared__ int part[kScanParts][kScanTiles];
+  const int l = threadIdx.x & (kScanTiles - 1), q = threadIdx.x / kScanTiles;
+  const int tile = blockIdx.x * kScanTiles + l;
+  const int per = (nblk + kScanParts - 1) / kScanParts;
+  const int b0 = min(q * per, nblk), b1 = min(b0 + per, nblk);
+  const bool held = per <= kScanHeld;
+  int v[kScanHeld];
   int s = 0;
-  for (int b = b0; b < b1; ++b) s += row[b];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {           // inclusive Hillis-Steele scan
-    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+  if (tile < ntiles) {
+    if (held) {
+#pragma unroll
+      for (int j = 0; j < kScanHeld; ++j) v[j] = b0 + j < b1 ? counts[(size_t)(b0 + j) * ntiles + tile] : 0;
+#pragma unroll
+      for (int j = 0; j < kScanHeld; ++j) s += v[j];
+    } else {
+      for (int b = b0; b < b1; ++b) s += counts[(size_t)b * ntiles + tile];
+    }
   }
-  int run = sh[threadIdx.x] - s;                // exclusive prefix of this thread's chunk
-  for (int b = b0; b < b1; ++b) { const int c = row[b]; row[b] = run; run += c; }
-  if (threadIdx.x == 255) totals[blockIdx.x] = sh[255];
+  part[q][l] = s;
+  __syncthreads();
+  int run = 0;
+  for (int u = 0; u < q; ++u) run += part[u][l];
+  if (tile < ntiles) {
+    if (held) {
+#pragma unroll
+      for (int j = 0; j < kScanHeld; ++j)
+        if (b0 + j < b1) {
+          counts[(size_t)(b0 + j) * ntiles + tile] = run;
+          run += v[j];
+        }
+    } else {
+      for (int b = b0; b < b1; ++b) {
+        const size_t o = (size_t)b * ntiles + tile;
+        const int c = counts[o];
+        counts[o] = run;
+        run += c;
+      }
+    }
+    if (q == kScanParts - 1) totals[tile] = run;
+  }
 }
 
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
@@ -372,7 +405,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileG
   for (int k = k0; k < k1; ++k) {
     const int v = cursor[k];
     if (blockIdx.x == 0) tile_start[k] = run;
-    cursor[k] = run + counts[(size_t)k * t.nblk + blockIdx.x];
+    cursor[k] = run + counts[(size_t)blockIdx.x * t.ntiles + k];
     run += v;
   }
   if (blockIdx.x == 0 && k0 < k1 && k1 == t.ntiles) tile_start[t.ntiles] = run;
@@ -1177,8 +1210,9 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part) {
     P3D_LAUNCH(c, "k_bucket_count");
   }
   if (part == 1) return PLACE3D_OK;
-  hipLaunchKernelGGL(k_bucket_scan_rows, dim3(t.ntiles), dim3(256), 0, s, t.nblk, c->bk_counts, c->bk_totals);
-  P3D_LAUNCH(c, "k_bucket_scan_rows");
+  hipLaunchKernelGGL(k_bucket_scan_cols, dim3((t.ntiles + kScanTiles - 1) / kScanTiles), dim3(kScanTiles * kScanParts), 0, s, t.nblk,
+                     t.ntiles, c->bk_counts, c->bk_totals);
+  P3D_LAUNCH(c, "k_bucket_scan_cols");
   hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
                      c->bk_counts, c->bk_totals, c->bk_tile_start, c->bk_entries, c->cell_entry);
   P3D_LAUNCH(c, "k_bucket_scatter");

@@ -125,7 +125,7 @@ struct place3d_ctx {
   int32_t n_fillers = 0;               // instances of kind FILLER (bucketed cells)
   // tiles and per-call buckets
   p3d::TileGeom tg = {};
-  int32_t* bk_counts = nullptr;        // [ntiles][nblk] counts, then exclusive offsets
+  int32_t* bk_counts = nullptr;        // [nblk][ntiles] counts, then exclusive offsets
   int32_t* bk_totals = nullptr;        // [ntiles]
   int32_t* bk_tile_start = nullptr;    // [ntiles + 1]
   float4* bk_entries = nullptr;        // [2 * 4n] (cell, tile) entries

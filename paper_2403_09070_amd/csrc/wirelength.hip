@@ -178,8 +178,9 @@ __device__ __forceinline__ void sums_merge(Sums4<C>& s) {
   s.sm.template merge<M>(); s.tm.template merge<M>();
 }
 
+// the sums of one axis: the top set, the bottom set
 template <bool C>
-struct NetSums { Sums4<C> xt, xb, yt, yb, z; };
+struct AxisSums { Sums4<C> t, b; };
 
 template <bool C>
 __device__ __forceinline__ void sums_add(Sums4<C>& s, bool in, float du, float dl, float ep, float em) {
@@ -189,19 +190,18 @@ __device__ __forceinline__ void sums_add(Sums4<C>& s, bool in, float du, float d
   s.tm.add(in ? dl * em : 0.f);
 }
 
+// one pin's terms along one axis: u its coordinate, (M, m) the extremes of its own set
 template <bool C>
-__device__ __forceinline__ void sums_pin(NetSums<C>& S, const NetExt& a, const PinRel& p, float ig) {
-  const float Mx = p.top ? a.tx.max1 : a.bx.max1, mx = p.top ? a.tx.min1 : a.bx.min1;
-  const float My = p.top ? a.ty.max1 : a.by.max1, my = p.top ? a.ty.min1 : a.by.min1;
-  const float dux = p.ux - Mx, dlx = p.ux - mx, duy = p.uy - My, dly = p.uy - my;
-  const float epx = __expf(dux * ig), emx = __expf(-dlx * ig);
-  const float epy = __expf(duy * ig), emy = __expf(-dly * ig);
-  sums_add(S.xt, p.top, dux, dlx, epx, emx);
-  sums_add(S.xb, !p.top, dux, dlx, epx, emx);
-  sums_add(S.yt, p.top, duy, dly, epy, emy);
-  sums_add(S.yb, !p.top, duy, dly, epy, emy);
+__device__ __forceinline__ void sums_axis(AxisSums<C>& S, bool top, float u, float M, float m, float ig) {
+  const float du = u - M, dl = u - m;
+  const float ep = __expf(du * ig), em = __expf(-dl * ig);
+  sums_add(S.t, top, du, dl, ep, em);
+  sums_add(S.b, !top, du, dl, ep, em);
+}
+template <bool C>
+__device__ __forceinline__ void sums_z(Sums4<C>& S, const NetExt& a, const PinRel& p, float ig) {
   const float duz = p.z - a.zmax, dlz = p.z - a.zmin;
-  sums_add(S.z, true, duz, dlz, __expf(duz * ig), __expf(-dlz * ig));
+  sums_add(S, true, duz, dlz, __expf(duz * ig), __expf(-dlz * ig));
 }
 
 // gradient coefficients of one set along one axis for the chosen branch:
@@ -312,8 +312,12 @@ __device__ __forceinline__ void merge_step(NetExt& a) {
   a.cb += xchg<M>(a.cb);
 }
 template <int M, bool C>
-__device__ __forceinline__ void merge_step(NetSums<C>& S) {
-  sums_merge<M>(S.xt); sums_merge<M>(S.xb); sums_merge<M>(S.yt); sums_merge<M>(S.yb); sums_merge<M>(S.z);
+__device__ __forceinline__ void merge_step(AxisSums<C>& S) {
+  sums_merge<M>(S.t); sums_merge<M>(S.b);
+}
+template <int M, bool C>
+__device__ __forceinline__ void merge_step(Sums4<C>& S) {
+  sums_merge<M>(S);
 }
 // reduce over a group of G lanes, widest step first
 template <int G, class T>
@@ -373,22 +377,48 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   for (int k = lg + G * kPinsPerLane; k < d; k += G) ext_add(a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya));
   group_merge<G>(a);
 
-  // ---- phase B: shifted exponential sums
-  NetSums<C> S = {};
-#pragma unroll
-  for (int j = 0; j < kPinsPerLane; ++j)
-    if (lg + G * j < d) sums_pin(S, a, pc[j], ig);
-  for (int k = lg + G * kPinsPerLane; k < d; k += G)
-    sums_pin(S, a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), ig);
-  group_merge<G>(S);
-
+  // ---- phase B: shifted exponential sums, one axis at a time, each reduced to its gradient
+  // coefficients before the next axis starts (one axis's sums live at a time: compensated sums
+  // hold two floats each)
   NetCoef c;
-  c.x = axis_coef(a.tx, val(S.xt), a.ct, a.bx, val(S.xb), a.cb, ig);
-  c.y = axis_coef(a.ty, val(S.yt), a.ct, a.by, val(S.yb), a.cb, ig);
+  {
+    AxisSums<C> S = {};
+#pragma unroll
+    for (int j = 0; j < kPinsPerLane; ++j)
+      if (lg + G * j < d)
+        sums_axis(S, pc[j].top, pc[j].ux, pc[j].top ? a.tx.max1 : a.bx.max1, pc[j].top ? a.tx.min1 : a.bx.min1, ig);
+    for (int k = lg + G * kPinsPerLane; k < d; k += G) {
+      const PinRel p = load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya);
+      sums_axis(S, p.top, p.ux, p.top ? a.tx.max1 : a.bx.max1, p.top ? a.tx.min1 : a.bx.min1, ig);
+    }
+    group_merge<G>(S);
+    c.x = axis_coef(a.tx, val(S.t), a.ct, a.bx, val(S.b), a.cb, ig);
+  }
+  {
+    AxisSums<C> S = {};
+#pragma unroll
+    for (int j = 0; j < kPinsPerLane; ++j)
+      if (lg + G * j < d)
+        sums_axis(S, pc[j].top, pc[j].uy, pc[j].top ? a.ty.max1 : a.by.max1, pc[j].top ? a.ty.min1 : a.by.min1, ig);
+    for (int k = lg + G * kPinsPerLane; k < d; k += G) {
+      const PinRel p = load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya);
+      sums_axis(S, p.top, p.uy, p.top ? a.ty.max1 : a.by.max1, p.top ? a.ty.min1 : a.by.min1, ig);
+    }
+    group_merge<G>(S);
+    c.y = axis_coef(a.ty, val(S.t), a.ct, a.by, val(S.b), a.cb, ig);
+  }
+  {
+    Sums4<C> S = {};
+#pragma unroll
+    for (int j = 0; j < kPinsPerLane; ++j)
+      if (lg + G * j < d) sums_z(S, a, pc[j], ig);
+    for (int k = lg + G * kPinsPerLane; k < d; k += G) sums_z(S, a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), ig);
+    group_merge<G>(S);
+    const Sums4v sz = val(S);
+    c.az_p = rcp(sz.sp); c.Az_p = sz.tp * c.az_p;
+    c.az_m = rcp(sz.sm); c.Az_m = sz.tm * c.az_m;
+  }
   c.zmax = a.zmax; c.zmin = a.zmin;
-  const Sums4v sz = val(S.z);
-  c.az_p = rcp(sz.sp); c.Az_p = sz.tp * c.az_p;
-  c.az_m = rcp(sz.sm); c.Az_m = sz.tm * c.az_m;
   c.Wx = w_exact(a.tx.max1, a.tx.min1, a.ct, a.bx.max1, a.bx.min1, a.cb);
   c.Wy = w_exact(a.ty.max1, a.ty.min1, a.ct, a.by.max1, a.by.min1, a.cb);
 
