@@ -133,7 +133,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->bk_totals = w.take<int32_t>(c->tg.ntiles);
   c->bk_tile_start = w.take<int32_t>(c->tg.ntiles + 1);
   c->bk_entries = w.take<float4>(8 * n);
-  c->cell_entry = w.take<int32_t>(4 * n);
+  c->cell_entry = w.take<int32_t>(n);
   c->entry_out = w.take<float4>(4 * n);
   c->part = w.take<double>((size_t)p3d::R_COUNT * c->part_stride);
   c->npins = w.take<float>(n);

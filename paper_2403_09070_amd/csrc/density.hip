@@ -79,12 +79,21 @@ __device__ __forceinline__ void foot_local(const Geom& g, Foot& f, int cbx, int 
   f.bz1 = max(f.bz1, f.bz0);
 }
 
-__device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict__ xyz,
-                                          const float* __restrict__ size, uint8_t kind, int i) {
-  Foot f;
+// an instance's inputs of the footprint, loaded together (so that callers can have the loads of
+// several instances in flight before any arithmetic)
+struct InstIn { float x, y, z, wbot, hbot, wtop, htop; uint8_t kind; };
+
+__device__ __forceinline__ InstIn inst_in(const Geom& g, const float* __restrict__ xyz, const float* __restrict__ size,
+                                          const uint8_t* __restrict__ kind, int i) {
   const int n = g.n;
-  const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-  const float wbot = size[i], hbot = size[n + i], wtop = size[2 * n + i], htop = size[3 * n + i];
+  return {xyz[i], xyz[n + i], xyz[2 * n + i], size[i], size[n + i], size[2 * n + i], size[3 * n + i], kind[i]};
+}
+
+__device__ __forceinline__ Foot footprint_of(const Geom& g, const InstIn& in) {
+  Foot f;
+  const float x = in.x, y = in.y, z = in.z;
+  const float wbot = in.wbot, hbot = in.hbot, wtop = in.wtop, htop = in.htop;
+  const uint8_t kind = in.kind;
   float w, h;
   f.dw = 0.f;
   f.dh = 0.f;
@@ -118,11 +127,26 @@ __device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict
   return f;
 }
 
-// bucket entry: (cbx | cby << 16, rx, ry, z), (hw, hh, omega, 1 for a filler else 0)
+__device__ __forceinline__ Foot footprint(const Geom& g, const float* __restrict__ xyz,
+                                          const float* __restrict__ size, uint8_t kind, int i) {
+  const int n = g.n;
+  return footprint_of(g, {xyz[i], xyz[n + i], xyz[2 * n + i], size[i], size[n + i], size[2 * n + i], size[3 * n + i],
+                          kind});
+}
+
+// bucket entry: (cbx | cby << 13 | q << 26 | filler << 28, rx, ry, z), (hw, hh, omega, cell index
+// as int bits); q is the entry's ordinal among its cell's (at most four) tiles
+__device__ __forceinline__ unsigned entry_word(int cbx, int cby, int q, bool filler) {
+  return (unsigned)cbx | ((unsigned)cby << 13) | ((unsigned)q << 26) | ((filler ? 1u : 0u) << 28);
+}
+__device__ __forceinline__ int entry_q(float4 a) { return (int)((__float_as_uint(a.x) >> 26) & 3u); }
+__device__ __forceinline__ bool entry_filler(float4 a) { return ((__float_as_uint(a.x) >> 28) & 1u) != 0u; }
+__device__ __forceinline__ int entry_cell(float4 b) { return __float_as_int(b.w); }
+
 __device__ __forceinline__ Foot foot_entry(const Geom& g, float4 a, float4 b) {
   Foot f;
   const unsigned packed = __float_as_uint(a.x);
-  foot_local(g, f, (int)(packed & 0xFFFFu), (int)(packed >> 16), a.y, a.z, a.w, b.x, b.y);
+  foot_local(g, f, (int)(packed & 0x1FFFu), (int)((packed >> 13) & 0x1FFFu), a.y, a.z, a.w, b.x, b.y);
   f.omega = b.z;
   f.w = f.h = 0.f;
   f.dw = f.dh = 0.f;
@@ -259,6 +283,12 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
 // threads of a bucketing workgroup: its 2048 instances take two rounds, and 16 wavefronts per
 // workgroup keep enough loads in flight at a few workgroups per compute unit
 constexpr int kBucketThreads = 1024;
+constexpr int kCellsPerThread = 2;      // cells a bucketing thread loads together per round
+
+// number of entries (tiles) of a bucketed cell from its packed tile range, 0 for -1 (not bucketed)
+__host__ __device__ inline int entry_count(int packed) {
+  return packed < 0 ? 0 : (1 + ((packed >> 24) & 1)) * (1 + ((packed >> 25) & 1));
+}
 
 // tiles overlapped by a bucketed cell (at most 2 x 2 for the cells this path takes)
 __device__ __forceinline__ void cell_tiles(const Foot& f, const TileGeom& t, int& tx0, int& tx1, int& ty0, int& ty1) {
@@ -294,19 +324,31 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(Geom g, TileGeo
   for (int k = threadIdx.x; k < t.ntiles; k += blockDim.x) hist[k] = 0;
   __syncthreads();
   const int base = blockIdx.x * t.cpb;
-  for (int c = threadIdx.x; c < t.cpb; c += blockDim.x) {
-    const int i = base + c;
-    if (i >= g.n) continue;
-    xyzp[i] = make_float4(xyz[i], xyz[g.n + i], xyz[2 * g.n + i], 0.f);
-    if (cls[i] != kClsCell) { tiles_of[i] = -1; continue; }
-    const Foot f = footprint(g, xyz, size, kind[i], i);
-    int tx0, tx1, ty0, ty1;
-    cell_tiles(f, t, tx0, tx1, ty0, ty1);
-    tx1 = min(tx1, tx0 + 1);           // bucketed cells span at most two tiles per axis
-    ty1 = min(ty1, ty0 + 1);
-    tiles_of[i] = pack_tiles(tx0, tx1, ty0, ty1);
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * t.ntx + tx], 1);
+  // kCellsPerThread cells per thread and round, every load of the round issued before any use
+  for (int c0 = threadIdx.x; c0 < t.cpb; c0 += kCellsPerThread * blockDim.x) {
+    InstIn in[kCellsPerThread];
+    uint8_t cl[kCellsPerThread];
+#pragma unroll
+    for (int u = 0; u < kCellsPerThread; ++u) {
+      const int c = c0 + u * (int)blockDim.x, i = min(base + c, g.n - 1);   // clamped: loads stay in bounds
+      in[u] = inst_in(g, xyz, size, kind, i);
+      cl[u] = cls[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCellsPerThread; ++u) {
+      const int c = c0 + u * (int)blockDim.x, i = base + c;
+      if (c >= t.cpb || i >= g.n) continue;
+      xyzp[i] = make_float4(in[u].x, in[u].y, in[u].z, 0.f);
+      if (cl[u] != kClsCell) { tiles_of[i] = -1; continue; }
+      const Foot f = footprint_of(g, in[u]);
+      int tx0, tx1, ty0, ty1;
+      cell_tiles(f, t, tx0, tx1, ty0, ty1);
+      tx1 = min(tx1, tx0 + 1);           // bucketed cells span at most two tiles per axis
+      ty1 = min(ty1, ty0 + 1);
+      tiles_of[i] = pack_tiles(tx0, tx1, ty0, ty1);
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * t.ntx + tx], 1);
+    }
   }
   __syncthreads();
   // block-major: this block's counts are one contiguous row
@@ -412,27 +454,33 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileG
   __syncthreads();
   const int n = g.n;
   const int base = blockIdx.x * t.cpb;
-  for (int c = threadIdx.x; c < t.cpb; c += blockDim.x) {
-    const int i = base + c;
-    if (i >= n) continue;
-    int slots[4] = {-1, -1, -1, -1};
-    const int packed = cell_entry[i];   // tile range recorded by the count pass, -1 if none
-    if (packed >= 0) {
-      const Foot f = footprint(g, xyz, size, kind[i], i);
+  for (int c0 = threadIdx.x; c0 < t.cpb; c0 += kCellsPerThread * blockDim.x) {
+    InstIn in[kCellsPerThread];
+    int pk[kCellsPerThread];
+#pragma unroll
+    for (int u = 0; u < kCellsPerThread; ++u) {
+      const int c = c0 + u * (int)blockDim.x, i = min(base + c, n - 1);     // clamped: loads stay in bounds
+      in[u] = inst_in(g, xyz, size, kind, i);
+      pk[u] = (c < t.cpb && base + c < n) ? cell_entry[i] : -1;         // tile range from the count pass
+    }
+#pragma unroll
+    for (int u = 0; u < kCellsPerThread; ++u) {
+      const int packed = pk[u];
+      if (packed < 0) continue;
+      const int i = base + c0 + u * (int)blockDim.x;
+      const Foot f = footprint_of(g, in[u]);
       const int tx0 = packed & 0xFFF, ty0 = (packed >> 12) & 0xFFF;
       const int tx1 = tx0 + ((packed >> 24) & 1), ty1 = ty0 + ((packed >> 25) & 1);
-      const float4 ea = make_float4(__uint_as_float((unsigned)f.cbx | ((unsigned)f.cby << 16)), f.rx, f.ry, f.z);
-      const float4 eb = make_float4(f.hw, f.hh, f.omega, (kind[i] & PLACE3D_KIND_FILLER) ? 1.f : 0.f);
+      const bool filler = (in[u].kind & PLACE3D_KIND_FILLER) != 0;
+      const float4 eb = make_float4(f.hw, f.hh, f.omega, __int_as_float(i));
       int q = 0;
       for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
           const int slot = atomicAdd(&cursor[ty * t.ntx + tx], 1);
-          entries[2 * (size_t)slot] = ea;
+          entries[2 * (size_t)slot] = make_float4(__uint_as_float(entry_word(f.cbx, f.cby, q++, filler)), f.rx, f.ry, f.z);
           entries[2 * (size_t)slot + 1] = eb;
-          slots[q++] = slot;
         }
     }
-    for (int q = 0; q < 4; ++q) cell_entry[(size_t)q * n + i] = slots[q];
   }
 }
 
@@ -554,7 +602,7 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
     const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
     const Foot f = foot_entry(g, ea, eb);
-    unsigned long long* acc = eb.w != 0.f ? SF : S64;
+    unsigned long long* acc = entry_filler(ea) ? SF : S64;
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     const float wgt = f.omega * inv_vol;
@@ -781,7 +829,9 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
   __syncthreads();
   const int e1 = tile_start[tile + 1];
   for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+    const Foot f = foot_entry(g, ea, eb);
+    const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     float sx = 0.f, sy = 0.f, sz = 0.f;
@@ -820,7 +870,7 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
         }
       }
     }
-    out[e] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
+    out[oi] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
   }
   if (!lpart) return;
   for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
@@ -1027,7 +1077,9 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
   auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
   const int e1 = tile_start[tile + 1];
   for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const Foot f = foot_entry(g, entries[2 * (size_t)e], entries[2 * (size_t)e + 1]);
+    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+    const Foot f = foot_entry(g, ea, eb);
+    const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
     const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
     float3 r = make_float3(0.f, 0.f, 0.f);
@@ -1036,7 +1088,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
                                      tb.y0 + tb.wy - 1, 0, 1, false);
       r = adjoint_finish(g, f, a);
     }
-    out[e] = make_float4(r.x, r.y, r.z, 0.f);
+    out[oi] = make_float4(r.x, r.y, r.z, 0.f);
   }
   if (!lpart) return;
   for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
@@ -1121,9 +1173,9 @@ __global__ void k_adjoint_large(Geom g, const float* __restrict__ xyz, const flo
   }
 }
 
-// per instance: the sum of its (<= 4) entry results for bucketed cells, zero for fixed
-// instances; large instances are written by their own kernel
-__global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ cell_entry,
+// per instance: the sum of its (<= 4) entry results (cell-major, res[q][n]) for bucketed cells,
+// zero for fixed instances; large instances are written by their own kernel
+__global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const int32_t* __restrict__ tiles_of,
                                 const float4* __restrict__ res, float scale, const double* __restrict__ dscale,
                                 float* __restrict__ grad, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1133,10 +1185,8 @@ __global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const in
   if (dscale) scale *= (float)dscale[0];
   float sx = 0.f, sy = 0.f, sz = 0.f;
   if (c == kClsCell) {
-    for (int q = 0; q < 4; ++q) {
-      const int e = cell_entry[(size_t)q * n + i];
-      if (e >= 0) { const float4 v = res[e]; sx += v.x; sy += v.y; sz += v.z; }
-    }
+    const int cnt = entry_count(tiles_of[i]);
+    for (int q = 0; q < cnt; ++q) { const float4 v = res[(size_t)q * n + i]; sx += v.x; sy += v.y; sz += v.z; }
     sx *= scale; sy *= scale; sz *= scale;
   }
   if (accumulate) { grad[i] += sx; grad[n + i] += sy; grad[2 * n + i] += sz; }

@@ -129,8 +129,8 @@ struct place3d_ctx {
   int32_t* bk_totals = nullptr;        // [ntiles]
   int32_t* bk_tile_start = nullptr;    // [ntiles + 1]
   float4* bk_entries = nullptr;        // [2 * 4n] (cell, tile) entries
-  int32_t* cell_entry = nullptr;       // [4][n] entries of each cell, -1 if none
-  float4* entry_out = nullptr;         // [4n] per-entry gather / adjoint results
+  int32_t* cell_entry = nullptr;       // [n] packed tile range of each bucketed cell, -1 if none
+  float4* entry_out = nullptr;         // [4][n] per-(cell, tile) gather / adjoint results, cell-major
   // two-stage reductions: part[slot * part_stride + block]
   double* part = nullptr;
   int32_t part_stride = 0;

@@ -105,8 +105,9 @@ __global__ void k_l1_parts(Geom g, const uint8_t* __restrict__ kind, const float
 // g = (gw + lambda gd) / H.  Mode 0 (init): write g to `gout` and track max|g|.  Mode 1 (step):
 // accumulate |v - v_prev|^2 and |g - g_prev|^2, store g over g_prev, and the movable charge
 // per die without fillers (overflow denominators).  A z-held instance's z-gradient is zero.
-// Cell density gradients held as per-(cell, tile) shares (CellShares.entry != nullptr) are summed
-// here, in the order the separate combine pass uses, instead of being materialised first.
+// Cell density gradients held as per-(cell, tile) shares (CellShares.entry != nullptr, cell-major
+// [q][n], q < the cell's entry count read from its packed tile range) are summed here, in the
+// order the separate combine pass uses, instead of being materialised first.
 struct CellShares {
   const uint8_t* cls;
   const int32_t* cell_entry;
@@ -127,10 +128,10 @@ __device__ __forceinline__ void density_grad_of(const CellShares& cs, const floa
   }
   float sx = 0.f, sy = 0.f, sz = 0.f;
   if (c == kClsCell) {
-    for (int q = 0; q < 4; ++q) {
-      const int e = cs.cell_entry[(size_t)q * n + i];
-      if (e >= 0) { const float4 v = cs.entry[e]; sx += v.x; sy += v.y; sz += v.z; }
-    }
+    // the cell's entry count from its packed tile range; its shares are cell-major [q][n]
+    const int packed = cs.cell_entry[i];
+    const int cnt = packed < 0 ? 0 : (1 + ((packed >> 24) & 1)) * (1 + ((packed >> 25) & 1));
+    for (int q = 0; q < cnt; ++q) { const float4 v = cs.entry[(size_t)q * n + i]; sx += v.x; sy += v.y; sz += v.z; }
     sx *= cs.scale; sy *= cs.scale; sz *= cs.scale;
   }
   d[0] = sx; d[1] = sy; d[2] = sz;
