@@ -516,7 +516,13 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": key,
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_step": lps,
                 "timing": "HIP events around this stage's launches during the timed steps",
-                "stage_ms_per_step_all_events": {k: round(v, 4) for k, v in per_step_ms.items()}}
+                "stage_ms_per_step_all_events": {k: round(v, 4) for k, v in per_step_ms.items()},
+                # HBM bytes per launch of each stage from the recorded FETCH_SIZE / WRITE_SIZE counters
+                # (null where none is recorded for the current source), beside its algorithmic bytes
+                "stage_traffic_bytes": {k: recorded_traffic(k, head_name, args.config)
+                                        for k in ("bucket", "density", "gemm", "wl_nets")},
+                "stage_algorithmic_bytes": {"bucket+density": density_bytes(n, bins),
+                                            "wl_nets": wl_bytes(n, P, m)}}
 
     line = {
         "metric": METRIC, "value": round(head["ips"], 2), "unit": "iterations/s", "n_gpus": 1,
