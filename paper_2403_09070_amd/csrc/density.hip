@@ -555,6 +555,27 @@ __device__ __forceinline__ unsigned long long to_fix_unit(float v) {   // 0 <= v
 // x bins of a bucketed entry whose overlap lengths are held in registers
 constexpr int kSpanX = 4;
 
+// A thread's entries of one tile (first, first + step, ... below last), read one entry ahead: the
+// next entry's two loads are issued before the current entry is processed, and the first entry's
+// before the tile's maps are staged, so that their latency overlaps work already in hand.
+struct EntryStream {
+  const float4* __restrict__ entries;
+  int e, last, step;
+  float4 na, nb;
+  __device__ __forceinline__ EntryStream(const float4* __restrict__ en, int first, int last_, int step_)
+      : entries(en), e(first), last(last_), step(step_), na(make_float4(0.f, 0.f, 0.f, 0.f)), nb(na) {
+    if (e < last) { na = entries[2 * (size_t)e]; nb = entries[2 * (size_t)e + 1]; }
+  }
+  __device__ __forceinline__ bool next(float4& a, float4& b) {
+    if (e >= last) return false;
+    a = na;
+    b = nb;
+    e += step;
+    if (e < last) { na = entries[2 * (size_t)e]; nb = entries[2 * (size_t)e + 1]; }
+    return true;
+  }
+};
+
 __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
                                                        const int32_t* __restrict__ tile_start,
                                                        const float* __restrict__ fixed_map,
@@ -565,6 +586,7 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
+  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
   // with fillers, their share accumulates apart (SF) so that the overflow can leave them out;
   // the map written is the sum of both (exact: integer fixed point)
   unsigned long long* SF = fillers ? S64 + tsz : S64;
@@ -598,9 +620,8 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
     }
   }
   // bucketed cells
-  const int e1 = tile_start[tile + 1];
-  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+  float4 ea, eb;
+  while (es.next(ea, eb)) {
     const Foot f = foot_entry(g, ea, eb);
     unsigned long long* acc = entry_filler(ea) ? SF : S64;
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
@@ -786,6 +807,7 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
+  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
   // natural-order maps whose rows and tile width are multiples of 4 bins: stage 4 bins per load
   // (the row start tb.x0 + lx is then a multiple of 4, so the 16-byte loads are aligned)
   const bool vec = !fx.on && (g.nx & 3) == 0 && (tb.wx & 3) == 0 &&
@@ -827,9 +849,8 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
     S[2 * tsz + k] = d;
   }
   __syncthreads();
-  const int e1 = tile_start[tile + 1];
-  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+  float4 ea, eb;
+  while (es.next(ea, eb)) {
     const Foot f = foot_entry(g, ea, eb);
     const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
@@ -1061,6 +1082,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
   const int tile = blockIdx.x;
   const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
+  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
   // rows and tile width multiples of 4 bins: stage 4 bins per load (aligned, as in the gather)
   const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0;
   for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
@@ -1075,9 +1097,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
   }
   __syncthreads();
   auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
-  const int e1 = tile_start[tile + 1];
-  for (int e = tile_start[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-    const float4 ea = entries[2 * (size_t)e], eb = entries[2 * (size_t)e + 1];
+  float4 ea, eb;
+  while (es.next(ea, eb)) {
     const Foot f = foot_entry(g, ea, eb);
     const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
     const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
