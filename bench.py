@@ -11,13 +11,15 @@ bistratal WA wirelength with the FDA z-gradient, preconditioned Nesterov move.  
 mixed form's iterations/s over exactly --steps timed steps after --warmup warm-up and
 --profile-steps untimed ones, with the metrics read back to the host every --readback-every
 steps inside the timed loop (a placer's convergence check); the plain form's rate, both final
-D2D HPWLs and their relative difference are reported beside it.  With --repeats R the forms
+D2D HPWLs and their relative difference are reported beside it, the HPWLs taken after
+--hpwl-iters iterations (untimed steps follow the timed ones when fewer were run).  With --repeats R the forms
 alternate R times, each repeat from the same start, and the median rate is reported.
 
 The roofline entry is for the stage with the largest GPU time in the mixed step (found in an
 untimed block of steps with every stage's launches bracketed by HIP events); its average launch
 time comes from HIP events on the launch stream around that stage's launches only, during the
-timed steps.  The CPU baseline is the FP64 oracle on a bounded sample of the same workload.
+timed steps.  The CPU baseline is one full FP64 oracle iteration of the same workload, stage by
+stage.
 
 ``--ablation precond`` runs the preconditioner ablation instead (one JSON line, curves to
 ``--ablation-csv``): the mixed-size preconditioner against the ePlace and ePlace3D forms on the
@@ -25,7 +27,8 @@ macro-heavy 200k-cell workload from a clustered start.  ``--ablation algo`` time
 and the wirelength call with the paper's baseline algorithms (instance-parallel macro scatter,
 O(|P_e|^2) FDA) against the default ones on the 1.2M-cell workload.  ``--ablation converge`` runs
 global placement on the 4M-cell workload from a clustered start until the overflow is below 0.1,
-for the plain, mixed and autograd forms.
+for the plain, mixed and autograd forms.  ``--ablation divergence`` records the per-iteration
+HPWL of plain, mixed, and plain from a start moved by one ulp (default workload c1).
 """
 from __future__ import annotations
 
@@ -155,6 +158,10 @@ def run_forms(case, names, forms, args, log):
                 prob.profile(False)
                 ev_ms, ev_n = ev_ms + ms, ev_n + cnt
             out[nm]["runs"].append(args.steps / dt)
+            # untimed steps after the timed ones, so that the final HPWLs compared between the
+            # forms are taken at --hpwl-iters iterations whatever --steps is
+            for _ in range(max(0, args.hpwl_iters - (args.warmup + args.profile_steps + args.steps))):
+                prob.step(st)
             out[nm]["state"] = st.read()
             log(f"[bench] repeat {r} form {nm}: {args.steps / dt:.1f} it/s, hpwl {out[nm]['state']['hpwl']:.6e}")
     for nm in names:
@@ -375,6 +382,55 @@ def algo_ablation(args, log):
                       "paper_context": {"density": 4.7, "fda": 1.7}}), flush=True)
 
 
+def divergence_run(args, log):
+    """Per-iteration D2D HPWL of three runs from the workload's start: plain (float32 contractions),
+    mixed (split-bf16) and plain again from the start with one coordinate (the first movable
+    instance's x) moved by one float32 ulp.  The relative HPWL difference of mixed against plain,
+    beside that of the one-ulp run against plain, separates what the split form changes from the
+    trajectory's own sensitivity to rounding.  --ablation-iters iterations (default: 525, 1025 for
+    c2); the full curves go to --ablation-csv."""
+    import numpy as np
+    import torch
+    from paper_2403_09070_amd import place3d, synth
+    case = synth.make_case(args.config, args.seed)
+    iters = args.ablation_iters
+    mov = np.nonzero((case.kind & synth.KIND_FIXED) == 0)[0]
+    xyz_ulp = case.xyz0.copy()
+    i0 = int(mov[0])
+    xyz_ulp[0, i0] = np.nextafter(xyz_ulp[0, i0], np.float32(np.inf))
+    runs = {"plain": (place3d.FP32, case.xyz0), "mixed": (place3d.BF16X3, case.xyz0),
+            "plain_1ulp": (place3d.FP32, xyz_ulp)}
+    curves = {}
+    for name, (precision, xyz0) in runs.items():
+        prob = place3d.Problem.from_case(case, precision=precision)
+        st = prob.gp_init(xyz0)
+        h = np.empty(iters)
+        for k in range(iters):
+            prob.step(st)
+            h[k] = st.read()["hpwl"]
+        curves[name] = h
+        log(f"[divergence] {name}: hpwl at {iters} = {h[-1]:.6e}")
+        del prob
+        torch.cuda.empty_cache()
+    d_mixed = np.abs(curves["mixed"] - curves["plain"]) / curves["plain"]
+    d_ulp = np.abs(curves["plain_1ulp"] - curves["plain"]) / curves["plain"]
+    marks = [k for k in (1, 2, 5, 10, 20, 50, 100, 200, 300, 400, 500, 700, 1000) if k <= iters]
+    if iters not in marks:
+        marks.append(iters)
+    if args.ablation_csv:
+        with open(args.ablation_csv, "w") as f:
+            f.write("iteration,hpwl_plain,hpwl_mixed,hpwl_plain_1ulp,rel_mixed,rel_1ulp\n")
+            for k in range(iters):
+                f.write(f"{k + 1},{curves['plain'][k]:.9e},{curves['mixed'][k]:.9e},{curves['plain_1ulp'][k]:.9e},"
+                        f"{d_mixed[k]:.3e},{d_ulp[k]:.3e}\n")
+    print(json.dumps({"run": "divergence", "workload": f"{args.config} seed {args.seed}: {case.meta['n_cells']} "
+                      f"cells + {case.meta['n_macros']} macros, {case.n_nets} nets, {case.n_pins} pins, grid "
+                      f"{case.nx}x{case.ny}x{case.nz}", "iterations": iters, "perturbed": f"x of instance {i0}, +1 ulp",
+                      "rel_hpwl_mixed_vs_plain": {str(k): float(d_mixed[k - 1]) for k in marks},
+                      "rel_hpwl_1ulp_vs_plain": {str(k): float(d_ulp[k - 1]) for k in marks},
+                      "max_rel_mixed": float(d_mixed.max()), "max_rel_1ulp": float(d_ulp.max())}), flush=True)
+
+
 def converge_run(args, log):
     """Global placement from a clustered start until the larger per-die overflow falls below
     --converge-overflow (or --converge-max iterations), for the plain (float32, field gather),
@@ -431,13 +487,16 @@ def main():
     ap.add_argument("--repeats", type=int, default=1, help="timed repeats per form (median reported)")
     ap.add_argument("--readback-every", type=int, default=10,
                     help="read the metrics back to the host every this many timed steps (0: never)")
+    ap.add_argument("--hpwl-iters", type=int, default=525,
+                    help="iterations after gp_init at which the forms' final HPWLs are compared (untimed steps "
+                         "follow the timed ones when --warmup + --profile-steps + --steps is fewer)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain,mixed,autograd")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
-    ap.add_argument("--ablation", choices=["precond", "algo", "converge"], default=None,
-                    help="run the preconditioner ablation instead of the timing benchmark")
+    ap.add_argument("--ablation", choices=["precond", "algo", "converge", "divergence"], default=None,
+                    help="run an ablation or study instead of the timing benchmark")
     ap.add_argument("--ablation-iters", type=int, default=1000)
     ap.add_argument("--ablation-every", type=int, default=5)
     ap.add_argument("--ablation-spread", type=float, default=0.02)
@@ -468,6 +527,12 @@ def main():
     if args.ablation == "converge":
         args.config = args.config or "c5"
         converge_run(args, log)
+        return
+    if args.ablation == "divergence":
+        args.config = args.config or "c1"
+        if "--ablation-iters" not in sys.argv:
+            args.ablation_iters = 1025 if args.config == "c2" else 525
+        divergence_run(args, log)
         return
     args.config = args.config or "c4"
     if args.copy_mb > 0:
@@ -540,7 +605,7 @@ def main():
         line["config"].update({"plain_iters_per_s": round(res["plain"]["ips"], 2),
                                "mixed_over_plain": round(res["mixed"]["ips"] / res["plain"]["ips"], 3),
                                "hpwl_plain": hp, "hpwl_mixed": hm, "hpwl_rel_diff": abs(hm - hp) / hp,
-                               "iterations": args.warmup + args.profile_steps + args.steps})
+                               "iterations": max(args.hpwl_iters, args.warmup + args.profile_steps + args.steps)})
     if "plain" in res and "autograd" in res:
         hp, ha = res["plain"]["state"]["hpwl"], res["autograd"]["state"]["hpwl"]
         line["config"].update({"autograd_iters_per_s": round(res["autograd"]["ips"], 2),
