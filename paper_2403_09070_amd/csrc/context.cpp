@@ -133,6 +133,10 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->bk_totals = w.take<int32_t>(c->tg.ntiles);
   c->bk_tile_start = w.take<int32_t>(c->tg.ntiles + 1);
   c->bk_entries = w.take<float4>(8 * n);
+  c->max_extra = (int32_t)(4 * n / p3d::kChunkEntries + 1);
+  c->max_heavy = std::min(c->max_extra, c->tg.ntiles);
+  c->bk_plan = w.take<int32_t>(2 + (size_t)c->tg.ntiles + 2 * (size_t)c->max_extra + c->max_heavy);
+  c->heavy_acc = w.take<unsigned long long>((size_t)c->max_heavy * 2 * c->tg.T * c->tg.T * p.nz);
   c->cell_entry = w.take<int32_t>(n);
   c->entry_out = w.take<float4>(4 * n);
   c->part = w.take<double>((size_t)p3d::R_COUNT * c->part_stride);
@@ -427,6 +431,11 @@ int32_t place3d_create(const place3d_problem* prob, void* d_workspace, size_t by
   if (rc == PLACE3D_OK) rc = p3d::static_scratch_setup(c, nullptr);
   if (rc == PLACE3D_OK) {
     hipError_t e = hipMemsetAsync(c->red, 0, sizeof(double) * p3d::R_COUNT, s);
+    // the heavy tiles' accumulators and chunk counters start at zero; every call leaves them so
+    const size_t acc = sizeof(unsigned long long) * (size_t)c->max_heavy * 2 * c->tg.T * c->tg.T * prob->nz;
+    if (e == hipSuccess) e = hipMemsetAsync(c->heavy_acc, 0, acc, s);
+    int32_t* done = c->bk_plan + 2 + c->tg.ntiles + 2 * (size_t)c->max_extra;
+    if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int32_t) * c->max_heavy, s);
     if (e != hipSuccess) rc = p3d::hip_fail(c, e, "hipMemsetAsync(create)");
   }
   if (rc == PLACE3D_OK) rc = p3d::build_dct_bases(c, s);

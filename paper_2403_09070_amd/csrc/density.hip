@@ -409,12 +409,56 @@ __global__ __launch_bounds__(kScanTiles * kScanParts) void k_bucket_scan_cols(in
   }
 }
 
+// Chunk plan of the current buckets, made by workgroup 0 of the scatter pass (every thread
+// takes the tiles [k0, k1) of the tile scan): a tile of more than kChunkEntries entries is heavy;
+// its chunks after the first are numbered after the tiles, in tile order, and it takes the next
+// accumulator slot.  Layout of plan: [0] extra chunks, [1] heavy tiles, [2 + k] slot of tile k
+// (-1 for a tile of one chunk), [2 + ntiles + e] tile of extra chunk e, [2 + ntiles + max_extra
+// + e] its index within the tile.
+__device__ void chunk_plan(const int32_t* __restrict__ totals, int k0, int k1, int ntiles, int max_extra,
+                           int32_t* __restrict__ plan) {
+  __shared__ int wx[kBucketThreads / kWave], wh[kBucketThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int ox = 0, oh = 0;
+  for (int k = k0; k < k1; ++k) {
+    const int v = totals[k];
+    if (v > kChunkEntries) { ox += (v - 1) / kChunkEntries; ++oh; }
+  }
+  int ix = ox, ih = oh;                 // inclusive scans within the wavefront
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int ux = __shfl_up(ix, o), uh = __shfl_up(ih, o);
+    if (lane >= o) { ix += ux; ih += uh; }
+  }
+  if (lane == kWave - 1) { wx[wave] = ix; wh[wave] = ih; }
+  __syncthreads();
+  int ex = ix - ox, eh = ih - oh;       // exclusive prefixes of this thread's tiles
+  for (int w = 0; w < wave; ++w) { ex += wx[w]; eh += wh[w]; }
+  int32_t* extra = plan + 2 + ntiles;
+  for (int k = k0; k < k1; ++k) {
+    const int v = totals[k];
+    if (v > kChunkEntries) {
+      const int nx = (v - 1) / kChunkEntries;
+      for (int j = 0; j < nx; ++j) {
+        extra[ex + j] = k;
+        extra[max_extra + ex + j] = j + 1;
+      }
+      ex += nx;
+      plan[2 + k] = eh++;
+    } else {
+      plan[2 + k] = -1;
+    }
+  }
+  // the last thread's tile range ends at the last tile: its running counts are the totals
+  if (threadIdx.x == blockDim.x - 1) { plan[0] = ex; plan[1] = eh; }
+}
+
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileGeom t, const float* __restrict__ xyz,
                                                         const float* __restrict__ size, const uint8_t* __restrict__ kind,
                                                         const uint8_t* __restrict__ cls, const int32_t* __restrict__ counts,
                                                         const int32_t* __restrict__ totals,
                                                         int32_t* __restrict__ tile_start,
-                                                        float4* __restrict__ entries, int32_t* __restrict__ cell_entry) {
+                                                        float4* __restrict__ entries, int32_t* __restrict__ cell_entry,
+                                                        int max_extra, int32_t* __restrict__ plan) {
   // every workgroup scans the tile totals itself (exclusive prefix = tile_start) and workgroup 0
   // stores the result for the later passes; the cursor of tile k starts at tile_start[k] plus
   // this workgroup's offset within the tile
@@ -452,6 +496,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(Geom g, TileG
   }
   if (blockIdx.x == 0 && k0 < k1 && k1 == t.ntiles) tile_start[t.ntiles] = run;
   __syncthreads();
+  if (blockIdx.x == 0) chunk_plan(totals, k0, k1, t.ntiles, max_extra, plan);
   const int n = g.n;
   const int base = blockIdx.x * t.cpb;
   for (int c0 = threadIdx.x; c0 < t.cpb; c0 += kCellsPerThread * blockDim.x) {
@@ -576,84 +621,54 @@ struct EntryStream {
   }
 };
 
-__global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
-                                                       const int32_t* __restrict__ tile_start,
-                                                       const float* __restrict__ fixed_map,
-                                                       const float4* __restrict__ lrec, int nlarge, float target,
-                                                       int fillers, float* __restrict__ rho,
-                                                       double* __restrict__ part, int stride) {
-  extern __shared__ unsigned long long S64[];
-  const int tile = blockIdx.x;
-  const TileBox tb = tile_box(g, t, tile);
+// The chunk plan of the current buckets, as the tile kernels take it.  Chunk q < ntiles is the
+// first chunk of tile q; chunk ntiles + e is extra chunk e (its tile and its index >= 1 within the
+// tile in the plan).  A launch of ntiles + max_extra workgroups gives workgroup q chunk q
+// (straight-line code: a loop over chunks would hold more registers and cost the common
+// one-chunk tiles occupancy).
+struct Chunks {
+  const int32_t* __restrict__ tile_start;   // [ntiles + 1] entry ranges of the tiles
+  int32_t* plan;                            // the context's chunk plan (layout in plan_*)
+  int ntiles, max_extra;
+  __device__ __forceinline__ int n_extra() const { return plan[0]; }
+  __device__ __forceinline__ int slot(int tile) const { return plan[2 + tile]; }
+  __device__ __forceinline__ int extra_tile(int e) const { return plan[2 + ntiles + e]; }
+  __device__ __forceinline__ int extra_index(int e) const { return plan[2 + ntiles + max_extra + e]; }
+  __device__ __forceinline__ int32_t* done(int slot) const { return plan + 2 + ntiles + 2 * max_extra + slot; }
+};
+
+struct ChunkRef {
+  int tile, first, last;    // entries [first, last) of the chunk
+  int nchunks;              // chunks of its tile
+  bool chunk0;
+};
+
+// (q is the same in every lane: the values are moved to scalar registers, which the compiler
+// cannot assume for loads through the struct's pointers)
+__device__ __forceinline__ ChunkRef chunk_ref(const Chunks& ch, const TileGeom& t, int q) {
+  ChunkRef ck;
+  int kc = 0;
+  if (q < t.ntiles) {
+    ck.tile = q;
+  } else {
+    ck.tile = __builtin_amdgcn_readfirstlane(ch.extra_tile(q - t.ntiles));
+    kc = __builtin_amdgcn_readfirstlane(ch.extra_index(q - t.ntiles));
+  }
+  const int ts = __builtin_amdgcn_readfirstlane(ch.tile_start[ck.tile]);
+  const int te = __builtin_amdgcn_readfirstlane(ch.tile_start[ck.tile + 1]);
+  ck.nchunks = te - ts > kChunkEntries ? (te - ts - 1) / kChunkEntries + 1 : 1;
+  ck.chunk0 = kc == 0;
+  ck.first = ts + kc * kChunkEntries;
+  ck.last = min(ck.first + kChunkEntries, te);
+  return ck;
+}
+
+// the finished tile into rho and its overflow partials; fix(k, real, filler) gives bin k's sums
+template <class Fix>
+__device__ __forceinline__ void write_tile(const Geom& g, const TileGeom& t, const TileBox& tb, int tile, float target,
+                                           int fillers, Fix fix, float* __restrict__ rho, double* __restrict__ part,
+                                           int stride) {
   const int tsz = t.T * t.T * g.nz;
-  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
-  // with fillers, their share accumulates apart (SF) so that the overflow can leave them out;
-  // the map written is the sum of both (exact: integer fixed point)
-  unsigned long long* SF = fillers ? S64 + tsz : S64;
-  for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    // fixed_map is null when the problem has no fixed instances (the map is then all zero)
-    S64[k] = (fixed_map && lx < tb.wx && ly < tb.wy) ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)])
-                                                      : 0ull;
-    if (fillers) SF[k] = 0ull;
-  }
-  __syncthreads();
-  // large instances: bin-parallel sweep of their part of this tile
-  __shared__ int hits[kTileThreads];
-  __shared__ int wave_cnt[kTileThreads / kWave];
-  const float inv_vol = 1.f / g.vol_bin;
-  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
-    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
-    for (int r = 0; r < nh; ++r) {
-      const Foot h = foot_record(g, lrec, hits[r]);
-      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
-      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
-      const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
-      const int total_bins = nbx * nby * nbz;
-      const float wgt = h.omega * inv_vol;
-      for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
-        const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
-        const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz) * wgt;
-        S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix_unit(v);   // one thread per bin within one instance
-      }
-      __syncthreads();
-    }
-  }
-  // bucketed cells
-  float4 ea, eb;
-  while (es.next(ea, eb)) {
-    const Foot f = foot_entry(g, ea, eb);
-    unsigned long long* acc = entry_filler(ea) ? SF : S64;
-    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
-    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
-    const float wgt = f.omega * inv_vol;
-    const int nbx = bx1 - bx0 + 1;
-    if (nbx <= kSpanX) {
-      float lxs[kSpanX];
-#pragma unroll
-      for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
-      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-        const float lz = len_z(g, f, bz) * wgt;
-        for (int by = by0; by <= by1; ++by) {
-          const float lyz = len_y(g, f, by) * lz;
-          unsigned long long* row = &acc[lds_index(t, bz, by - tb.y0, bx0 - tb.x0)];
-#pragma unroll
-          for (int j = 0; j < kSpanX; ++j)
-            if (j < nbx) atomicAdd(row + j, to_fix_unit(lxs[j] * lyz));
-        }
-      }
-    } else {
-      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-        const float lz = len_z(g, f, bz) * wgt;
-        for (int by = by0; by <= by1; ++by) {
-          const float lyz = len_y(g, f, by) * lz;
-          for (int bx = bx0; bx <= bx1; ++bx)
-            atomicAdd(&acc[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix_unit(len_x(g, f, bx) * lyz));
-        }
-      }
-    }
-  }
-  __syncthreads();
   float ex[2] = {0.f, 0.f};
   const int half = g.nz / 2;
   // rows and tile width multiples of 4 bins: write 4 bins per store (aligned, as in the gather)
@@ -664,8 +679,9 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
       float v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const unsigned long long real = S64[k + j];
-        v[j] = (float)((double)(fillers ? real + SF[k + j] : real) * kUnfix);
+        unsigned long long real, fil;
+        fix(k + j, real, fil);
+        v[j] = (float)((double)(real + fil) * kUnfix);
         const float vr = fillers ? (float)((double)real * kUnfix) : v[j];
         ex[bz < half ? 0 : 1] += fmaxf(vr - target, 0.f) * g.vol_bin;
       }
@@ -675,14 +691,142 @@ __global__ __launch_bounds__(kTileThreads) void k_density_tiles(Geom g, TileGeom
   for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
     const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
     if (lx < tb.wx && ly < tb.wy) {
-      const unsigned long long real = S64[k];
-      const float v = (float)((double)(fillers ? real + SF[k] : real) * kUnfix);
+      unsigned long long real, fil;
+      fix(k, real, fil);
+      const float v = (float)((double)(real + fil) * kUnfix);
       const float vr = fillers ? (float)((double)real * kUnfix) : v;
       rho[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] = v;
       ex[bz < half ? 0 : 1] += fmaxf(vr - target, 0.f) * g.vol_bin;
     }
   }
   block_partials<2>(ex, part, stride, R_EXCESS_BOT, tile);
+}
+
+// A chunk accumulates in LDS: its tile's fixed map and large-instance sweep with the first chunk,
+// then its entries.  A tile of one chunk is written from LDS.  The chunks of a heavy tile add
+// their LDS sums into the tile's accumulator slot (64-bit integer atomics, so the sum does not
+// depend on their order) and count themselves done; the last one reads the slot back, clearing
+// it, and writes the tile.
+// (eight wavefronts per SIMD: the scalar registers its heavy-tile path needs would otherwise cost
+// one; the excess goes to vector-register lanes)
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_density_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
+                                                       Chunks ch, unsigned long long* __restrict__ heavy_acc,
+                                                       const float* __restrict__ fixed_map,
+                                                       const float4* __restrict__ lrec, int nlarge, float target,
+                                                       int fillers, float* __restrict__ rho,
+                                                       double* __restrict__ part, int stride) {
+  extern __shared__ unsigned long long S64[];
+  __shared__ int hits[kTileThreads];
+  __shared__ int wave_cnt[kTileThreads / kWave];
+  __shared__ int last_chunk;
+  const int tsz = t.T * t.T * g.nz;
+  const float inv_vol = 1.f / g.vol_bin;
+  // with fillers, their share accumulates apart (SF) so that the overflow can leave them out;
+  // the map written is the sum of both (exact: integer fixed point)
+  unsigned long long* SF = fillers ? S64 + tsz : S64;
+  // workgroup q takes chunk q; past the tile count, workgroups without an extra chunk leave
+  const int qc = blockIdx.x;
+  if (qc >= t.ntiles && qc >= t.ntiles + __builtin_amdgcn_readfirstlane(ch.n_extra())) return;
+  {
+    const ChunkRef ck = chunk_ref(ch, t, qc);
+    const TileBox tb = tile_box(g, t, ck.tile);
+    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+      const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+      // fixed_map is null when the problem has no fixed instances (the map is then all zero)
+      S64[k] = (ck.chunk0 && fixed_map && lx < tb.wx && ly < tb.wy)
+                   ? to_fix(fixed_map[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)])
+                   : 0ull;
+      if (fillers) SF[k] = 0ull;
+    }
+    __syncthreads();
+    // large instances: bin-parallel sweep of their part of this tile (first chunk)
+    for (int chunk = 0; ck.chunk0 && chunk < nlarge; chunk += blockDim.x) {
+      const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+      for (int h_ = 0; h_ < nh; ++h_) {
+        const Foot h = foot_record(g, lrec, hits[h_]);
+        const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+        const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+        const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
+        const int total_bins = nbx * nby * nbz;
+        const float wgt = h.omega * inv_vol;
+        for (int b = threadIdx.x; b < total_bins; b += blockDim.x) {
+          const int bx = bx0 + b % nbx, by = by0 + (b / nbx) % nby, bz = h.bz0 + b / (nbx * nby);
+          const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz) * wgt;
+          S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix_unit(v);   // one thread per bin within one instance
+        }
+        __syncthreads();
+      }
+    }
+    // bucketed cells
+    float4 ea, eb;
+    while (es.next(ea, eb)) {
+      const Foot f = foot_entry(g, ea, eb);
+      unsigned long long* acc = entry_filler(ea) ? SF : S64;
+      const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+      const float wgt = f.omega * inv_vol;
+      const int nbx = bx1 - bx0 + 1;
+      if (nbx <= kSpanX) {
+        float lxs[kSpanX];
+#pragma unroll
+        for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
+        for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+          const float lz = len_z(g, f, bz) * wgt;
+          for (int by = by0; by <= by1; ++by) {
+            const float lyz = len_y(g, f, by) * lz;
+            unsigned long long* row = &acc[lds_index(t, bz, by - tb.y0, bx0 - tb.x0)];
+#pragma unroll
+            for (int j = 0; j < kSpanX; ++j)
+              if (j < nbx) atomicAdd(row + j, to_fix_unit(lxs[j] * lyz));
+          }
+        }
+      } else {
+        for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+          const float lz = len_z(g, f, bz) * wgt;
+          for (int by = by0; by <= by1; ++by) {
+            const float lyz = len_y(g, f, by) * lz;
+            for (int bx = bx0; bx <= bx1; ++bx)
+              atomicAdd(&acc[lds_index(t, bz, by - tb.y0, bx - tb.x0)], to_fix_unit(len_x(g, f, bx) * lyz));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (ck.nchunks == 1) {
+      write_tile(g, t, tb, ck.tile, target, fillers,
+                 [&](int k, unsigned long long& real, unsigned long long& fil) {
+                   real = S64[k];
+                   fil = fillers ? SF[k] : 0ull;
+                 },
+                 rho, part, stride);
+    } else {
+      const int slot = ch.slot(ck.tile);
+      unsigned long long* acc = heavy_acc + (size_t)slot * 2 * tsz;
+      for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
+        const unsigned long long a = S64[k];
+        if (a) atomicAdd(acc + k, a);
+        if (fillers) {
+          const unsigned long long b = SF[k];
+          if (b) atomicAdd(acc + tsz + k, b);
+        }
+      }
+      __threadfence();          // this chunk's sums are in place before it counts itself done
+      __syncthreads();
+      if (threadIdx.x == 0) last_chunk = atomicAdd(ch.done(slot), 1) == ck.nchunks - 1;
+      __syncthreads();
+      if (last_chunk) {
+        __threadfence();        // and the other chunks' sums before the last one reads them
+        write_tile(g, t, tb, ck.tile, target, fillers,
+                   [&](int k, unsigned long long& real, unsigned long long& fil) {
+                     real = atomicExch(acc + k, 0ull);
+                     fil = fillers ? atomicExch(acc + tsz + k, 0ull) : 0ull;
+                   },
+                   rho, part, stride);
+        if (threadIdx.x == 0) atomicExch(ch.done(slot), 0);
+      }
+    }
+  }
 }
 
 // fixed map: one workgroup per fixed instance, global atomics (built once)
@@ -795,7 +939,7 @@ __global__ __launch_bounds__(256) void k_red_final(const double* __restrict__ pa
 struct FoldX { int on, hx; float sx, sy, sz; };
 
 __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
-                                                      const int32_t* __restrict__ tile_start,
+                                                      Chunks ch,
                                                       const float* __restrict__ mx, const float* __restrict__ my,
                                                       const float* __restrict__ mz, FoldX fx, float4* __restrict__ out,
                                                       const float4* __restrict__ lrec, int nlarge,
@@ -804,127 +948,135 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
   __shared__ int hits[kTileThreads];
   __shared__ int wave_cnt[kTileThreads / kWave];
   __shared__ float rsh[3][kTileThreads / kWave];
-  const int tile = blockIdx.x;
-  const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
-  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
-  // natural-order maps whose rows and tile width are multiples of 4 bins: stage 4 bins per load
-  // (the row start tb.x0 + lx is then a multiple of 4, so the 16-byte loads are aligned)
-  const bool vec = !fx.on && (g.nx & 3) == 0 && (tb.wx & 3) == 0 &&
-                   ((reinterpret_cast<uintptr_t>(mx) | reinterpret_cast<uintptr_t>(my) |
-                     reinterpret_cast<uintptr_t>(mz)) & 15) == 0;
-  for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
-    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, d = a;
-    if (lx < tb.wx && ly < tb.wy) {
-      const size_t q = bin_index(g, bz, tb.y0 + ly, tb.x0 + lx);
-      a = *reinterpret_cast<const float4*>(mx + q);
-      b = *reinterpret_cast<const float4*>(my + q);
-      d = *reinterpret_cast<const float4*>(mz + q);
-    }
-    *reinterpret_cast<float4*>(S + k) = a;
-    *reinterpret_cast<float4*>(S + tsz + k) = b;
-    *reinterpret_cast<float4*>(S + 2 * tsz + k) = d;
-  }
-  for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    float a = 0.f, b = 0.f, d = 0.f;
-    if (lx < tb.wx && ly < tb.wy) {
-      const int gx = tb.x0 + lx;
-      if (fx.on) {
-        const bool up = gx >= fx.hx;
-        const size_t e = bin_index(g, bz, tb.y0 + ly, up ? g.nx - 1 - gx : gx), o = e + fx.hx;
-        a = up ? fx.sx * (mx[e] - mx[o]) : mx[e] + mx[o];
-        b = up ? fx.sy * (my[e] - my[o]) : my[e] + my[o];
-        d = up ? fx.sz * (mz[e] - mz[o]) : mz[e] + mz[o];
-      } else {
-        const size_t q = bin_index(g, bz, tb.y0 + ly, gx);
-        a = mx[q];
-        b = my[q];
-        d = mz[q];
+  // workgroup q takes chunk q; past the tile count, workgroups without an extra chunk leave
+  const int qc = blockIdx.x;
+  if (qc >= t.ntiles && qc >= t.ntiles + __builtin_amdgcn_readfirstlane(ch.n_extra())) return;
+  {
+    const ChunkRef ck = chunk_ref(ch, t, qc);
+    const int tile = ck.tile;
+    const TileBox tb = tile_box(g, t, tile);
+    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    // natural-order maps whose rows and tile width are multiples of 4 bins: stage 4 bins per load
+    // (the row start tb.x0 + lx is then a multiple of 4, so the 16-byte loads are aligned)
+    const bool vec = !fx.on && (g.nx & 3) == 0 && (tb.wx & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(mx) | reinterpret_cast<uintptr_t>(my) |
+                       reinterpret_cast<uintptr_t>(mz)) & 15) == 0;
+    for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
+      const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, d = a;
+      if (lx < tb.wx && ly < tb.wy) {
+        const size_t q = bin_index(g, bz, tb.y0 + ly, tb.x0 + lx);
+        a = *reinterpret_cast<const float4*>(mx + q);
+        b = *reinterpret_cast<const float4*>(my + q);
+        d = *reinterpret_cast<const float4*>(mz + q);
       }
+      *reinterpret_cast<float4*>(S + k) = a;
+      *reinterpret_cast<float4*>(S + tsz + k) = b;
+      *reinterpret_cast<float4*>(S + 2 * tsz + k) = d;
     }
-    S[k] = a;
-    S[tsz + k] = b;
-    S[2 * tsz + k] = d;
-  }
-  __syncthreads();
-  float4 ea, eb;
-  while (es.next(ea, eb)) {
-    const Foot f = foot_entry(g, ea, eb);
-    const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
-    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
-    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    const int nbx = bx1 - bx0 + 1;
-    if (nbx <= kSpanX) {
-      float lxs[kSpanX];
-#pragma unroll
-      for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
-      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-        const float lz = len_z(g, f, bz);
-        for (int by = by0; by <= by1; ++by) {
-          const float lyz = len_y(g, f, by) * lz;
-          const int k0 = lds_index(t, bz, by - tb.y0, bx0 - tb.x0);
-#pragma unroll
-          for (int j = 0; j < kSpanX; ++j)
-            if (j < nbx) {
-              const float v = lxs[j] * lyz;
-              sx += v * S[k0 + j];
-              sy += v * S[tsz + k0 + j];
-              sz += v * S[2 * tsz + k0 + j];
-            }
+    for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
+      const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+      float a = 0.f, b = 0.f, d = 0.f;
+      if (lx < tb.wx && ly < tb.wy) {
+        const int gx = tb.x0 + lx;
+        if (fx.on) {
+          const bool up = gx >= fx.hx;
+          const size_t e = bin_index(g, bz, tb.y0 + ly, up ? g.nx - 1 - gx : gx), o = e + fx.hx;
+          a = up ? fx.sx * (mx[e] - mx[o]) : mx[e] + mx[o];
+          b = up ? fx.sy * (my[e] - my[o]) : my[e] + my[o];
+          d = up ? fx.sz * (mz[e] - mz[o]) : mz[e] + mz[o];
+        } else {
+          const size_t q = bin_index(g, bz, tb.y0 + ly, gx);
+          a = mx[q];
+          b = my[q];
+          d = mz[q];
         }
       }
-    } else {
-      for (int bz = f.bz0; bz <= f.bz1; ++bz) {
-        const float lz = len_z(g, f, bz);
-        for (int by = by0; by <= by1; ++by) {
-          const float lyz = len_y(g, f, by) * lz;
-          for (int bx = bx0; bx <= bx1; ++bx) {
-            const float v = len_x(g, f, bx) * lyz;
+      S[k] = a;
+      S[tsz + k] = b;
+      S[2 * tsz + k] = d;
+    }
+    __syncthreads();
+    float4 ea, eb;
+    while (es.next(ea, eb)) {
+      const Foot f = foot_entry(g, ea, eb);
+      const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
+      const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      const int nbx = bx1 - bx0 + 1;
+      if (nbx <= kSpanX) {
+        float lxs[kSpanX];
+  #pragma unroll
+        for (int j = 0; j < kSpanX; ++j) lxs[j] = j < nbx ? len_x(g, f, bx0 + j) : 0.f;
+        for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+          const float lz = len_z(g, f, bz);
+          for (int by = by0; by <= by1; ++by) {
+            const float lyz = len_y(g, f, by) * lz;
+            const int k0 = lds_index(t, bz, by - tb.y0, bx0 - tb.x0);
+  #pragma unroll
+            for (int j = 0; j < kSpanX; ++j)
+              if (j < nbx) {
+                const float v = lxs[j] * lyz;
+                sx += v * S[k0 + j];
+                sy += v * S[tsz + k0 + j];
+                sz += v * S[2 * tsz + k0 + j];
+              }
+          }
+        }
+      } else {
+        for (int bz = f.bz0; bz <= f.bz1; ++bz) {
+          const float lz = len_z(g, f, bz);
+          for (int by = by0; by <= by1; ++by) {
+            const float lyz = len_y(g, f, by) * lz;
+            for (int bx = bx0; bx <= bx1; ++bx) {
+              const float v = len_x(g, f, bx) * lyz;
+              const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
+              sx += v * S[k];
+              sy += v * S[tsz + k];
+              sz += v * S[2 * tsz + k];
+            }
+          }
+        }
+      }
+      out[oi] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
+    }
+    // large instances' partial sums over the tile (first chunk)
+    if (lpart && ck.chunk0) {
+      for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
+        const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+        for (int r = 0; r < nh; ++r) {
+          const int j = hits[r];
+          const Foot h = foot_record(g, lrec, j);
+          const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+          const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+          const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
+          const int total_bins = nbx * nby * nbz;
+          float sx = 0.f, sy = 0.f, sz = 0.f;
+          for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
+            const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
+            const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz);
             const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
             sx += v * S[k];
             sy += v * S[tsz + k];
             sz += v * S[2 * tsz + k];
           }
+          for (int o = kWave / 2; o > 0; o >>= 1) {
+            sx += __shfl_xor(sx, o); sy += __shfl_xor(sy, o); sz += __shfl_xor(sz, o);
+          }
+          if ((threadIdx.x & (kWave - 1)) == 0) {
+            rsh[0][threadIdx.x / kWave] = sx; rsh[1][threadIdx.x / kWave] = sy; rsh[2][threadIdx.x / kWave] = sz;
+          }
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            float a = 0.f, b = 0.f, c = 0.f;
+            for (int w = 0; w < (int)(blockDim.x / kWave); ++w) { a += rsh[0][w]; b += rsh[1][w]; c += rsh[2][w]; }
+            lpart[(size_t)j * t.ntiles + tile] = make_float4(h.omega * a, h.omega * b, h.omega * c, 0.f);
+          }
+          __syncthreads();
         }
       }
-    }
-    out[oi] = make_float4(f.omega * sx, f.omega * sy, f.omega * sz, 0.f);
-  }
-  if (!lpart) return;
-  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
-    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
-    for (int r = 0; r < nh; ++r) {
-      const int j = hits[r];
-      const Foot h = foot_record(g, lrec, j);
-      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
-      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
-      const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
-      const int total_bins = nbx * nby * nbz;
-      float sx = 0.f, sy = 0.f, sz = 0.f;
-      for (int q = threadIdx.x; q < total_bins; q += blockDim.x) {
-        const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = h.bz0 + q / (nbx * nby);
-        const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz);
-        const int k = lds_index(t, bz, by - tb.y0, bx - tb.x0);
-        sx += v * S[k];
-        sy += v * S[tsz + k];
-        sz += v * S[2 * tsz + k];
-      }
-      for (int o = kWave / 2; o > 0; o >>= 1) {
-        sx += __shfl_xor(sx, o); sy += __shfl_xor(sy, o); sz += __shfl_xor(sz, o);
-      }
-      if ((threadIdx.x & (kWave - 1)) == 0) {
-        rsh[0][threadIdx.x / kWave] = sx; rsh[1][threadIdx.x / kWave] = sy; rsh[2][threadIdx.x / kWave] = sz;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float a = 0.f, b = 0.f, c = 0.f;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) { a += rsh[0][w]; b += rsh[1][w]; c += rsh[2][w]; }
-        lpart[(size_t)j * t.ntiles + tile] = make_float4(h.omega * a, h.omega * b, h.omega * c, 0.f);
-      }
-      __syncthreads();
     }
   }
 }
@@ -1071,7 +1223,7 @@ __device__ __forceinline__ float3 adjoint_finish(const Geom& g, const Foot& f, c
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom t, const float4* __restrict__ entries,
-                                                       const int32_t* __restrict__ tile_start,
+                                                       Chunks ch,
                                                        const float* __restrict__ m, float4* __restrict__ out,
                                                        const float4* __restrict__ lrec, int nlarge,
                                                        float4* __restrict__ lpart) {
@@ -1079,62 +1231,70 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
   __shared__ int hits[kTileThreads];
   __shared__ int wave_cnt[kTileThreads / kWave];
   __shared__ float rsh[6][kTileThreads / kWave];
-  const int tile = blockIdx.x;
-  const TileBox tb = tile_box(g, t, tile);
   const int tsz = t.T * t.T * g.nz;
-  EntryStream es(entries, tile_start[tile] + (int)threadIdx.x, tile_start[tile + 1], (int)blockDim.x);
-  // rows and tile width multiples of 4 bins: stage 4 bins per load (aligned, as in the gather)
-  const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0;
-  for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
-    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    *reinterpret_cast<float4*>(S + k) =
-        (lx < tb.wx && ly < tb.wy) ? *reinterpret_cast<const float4*>(m + bin_index(g, bz, tb.y0 + ly, tb.x0 + lx))
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
-    const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
-    S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
-  }
-  __syncthreads();
-  auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
-  float4 ea, eb;
-  while (es.next(ea, eb)) {
-    const Foot f = foot_entry(g, ea, eb);
-    const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
-    const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
-    const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
-    float3 r = make_float3(0.f, 0.f, 0.f);
-    if (bx0 <= bx1 && by0 <= by1) {
-      const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0,
-                                     tb.y0 + tb.wy - 1, 0, 1, false);
-      r = adjoint_finish(g, f, a);
+  // workgroup q takes chunk q; past the tile count, workgroups without an extra chunk leave
+  const int qc = blockIdx.x;
+  if (qc >= t.ntiles && qc >= t.ntiles + __builtin_amdgcn_readfirstlane(ch.n_extra())) return;
+  {
+    const ChunkRef ck = chunk_ref(ch, t, qc);
+    const int tile = ck.tile;
+    const TileBox tb = tile_box(g, t, tile);
+    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    // rows and tile width multiples of 4 bins: stage 4 bins per load (aligned, as in the gather)
+    const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0;
+    for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
+      const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+      *reinterpret_cast<float4*>(S + k) =
+          (lx < tb.wx && ly < tb.wy) ? *reinterpret_cast<const float4*>(m + bin_index(g, bz, tb.y0 + ly, tb.x0 + lx))
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    out[oi] = make_float4(r.x, r.y, r.z, 0.f);
-  }
-  if (!lpart) return;
-  for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
-    const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
-    for (int r = 0; r < nh; ++r) {
-      const int j = hits[r];
-      const Foot h = foot_record(g, lrec, j);
-      const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
-      const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
-      AdjSums a = adjoint_sums(g, h, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1,
-                               threadIdx.x, blockDim.x, true);
-      float v[6] = {a.gx, a.gy, a.gz, a.xs, a.ys, a.all};
-      for (int q = 0; q < 6; ++q) {
-        for (int o = kWave / 2; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
-        if ((threadIdx.x & (kWave - 1)) == 0) rsh[q][threadIdx.x / kWave] = v[q];
+    for (int k = vec ? tsz : (int)threadIdx.x; k < tsz; k += blockDim.x) {
+      const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
+      S[k] = (lx < tb.wx && ly < tb.wy) ? m[bin_index(g, bz, tb.y0 + ly, tb.x0 + lx)] : 0.f;
+    }
+    __syncthreads();
+    auto at = [&](int bz, int by, int bx) { return S[lds_index(t, bz, by - tb.y0, bx - tb.x0)]; };
+    float4 ea, eb;
+    while (es.next(ea, eb)) {
+      const Foot f = foot_entry(g, ea, eb);
+      const size_t oi = (size_t)entry_q(ea) * g.n + entry_cell(eb);   // cell-major result slot
+      const int bx0 = max(f.bx0, tb.x0), bx1 = min(f.bx1, tb.x0 + tb.wx - 1);
+      const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
+      float3 r = make_float3(0.f, 0.f, 0.f);
+      if (bx0 <= bx1 && by0 <= by1) {
+        const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0,
+                                       tb.y0 + tb.wy - 1, 0, 1, false);
+        r = adjoint_finish(g, f, a);
       }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int q = 0; q < 6; ++q)
-          for (int u = 0; u < (int)(blockDim.x / kWave); ++u) w[q] += rsh[q][u];
-        lpart[2 * ((size_t)j * t.ntiles + tile)] = make_float4(w[0], w[1], w[2], 0.f);
-        lpart[2 * ((size_t)j * t.ntiles + tile) + 1] = make_float4(w[3], w[4], w[5], 0.f);
+      out[oi] = make_float4(r.x, r.y, r.z, 0.f);
+    }
+    // large instances' partial sums over the tile (first chunk)
+    if (lpart && ck.chunk0) {
+      for (int chunk = 0; chunk < nlarge; chunk += blockDim.x) {
+        const int nh = large_hits(lrec, nlarge, chunk, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1, hits, wave_cnt);
+        for (int r = 0; r < nh; ++r) {
+          const int j = hits[r];
+          const Foot h = foot_record(g, lrec, j);
+          const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
+          const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
+          AdjSums a = adjoint_sums(g, h, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0, tb.y0 + tb.wy - 1,
+                                   threadIdx.x, blockDim.x, true);
+          float v[6] = {a.gx, a.gy, a.gz, a.xs, a.ys, a.all};
+          for (int q = 0; q < 6; ++q) {
+            for (int o = kWave / 2; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+            if ((threadIdx.x & (kWave - 1)) == 0) rsh[q][threadIdx.x / kWave] = v[q];
+          }
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < 6; ++q)
+              for (int u = 0; u < (int)(blockDim.x / kWave); ++u) w[q] += rsh[q][u];
+            lpart[2 * ((size_t)j * t.ntiles + tile)] = make_float4(w[0], w[1], w[2], 0.f);
+            lpart[2 * ((size_t)j * t.ntiles + tile) + 1] = make_float4(w[3], w[4], w[5], 0.f);
+          }
+          __syncthreads();
+        }
       }
-      __syncthreads();
     }
   }
 }
@@ -1216,6 +1376,8 @@ __global__ void k_cells_combine(int n, const uint8_t* __restrict__ cls, const in
 
 size_t tile_lds(const place3d_ctx* c, int maps) { return sizeof(float) * (size_t)maps * c->tg.T * c->tg.T * c->g.nz; }
 
+Chunks chunks_of(const place3d_ctx* c) { return Chunks{c->bk_tile_start, c->bk_plan, c->tg.ntiles, c->max_extra}; }
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1285,7 +1447,8 @@ int bucket_cells(place3d_ctx* c, const float* xyz, hipStream_t s, int part) {
                      t.ntiles, c->bk_counts, c->bk_totals);
   P3D_LAUNCH(c, "k_bucket_scan_cols");
   hipLaunchKernelGGL(k_bucket_scatter, dim3(t.nblk), dim3(kBucketThreads), hist, s, g, t, xyz, p.size, p.kind, c->cls,
-                     c->bk_counts, c->bk_totals, c->bk_tile_start, c->bk_entries, c->cell_entry);
+                     c->bk_counts, c->bk_totals, c->bk_tile_start, c->bk_entries, c->cell_entry, c->max_extra,
+                     c->bk_plan);
   P3D_LAUNCH(c, "k_bucket_scatter");
   return PLACE3D_OK;
 }
@@ -1298,8 +1461,9 @@ int density_tiles(place3d_ctx* c, const float* xyz, float* rho, double* red, hip
     ProfScope prof_(c, PLACE3D_STAGE_DENSITY, s);
     const int fillers = c->n_fillers > 0 ? 1 : 0;
     const bool inst = (p.options & PLACE3D_OPT_MACRO_INSTANCE) != 0;
-    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles), dim3(kTileThreads), (2 + 2 * fillers) * tile_lds(c, 1), s, g,
-                       t, c->bk_entries, c->bk_tile_start, c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec,
+    hipLaunchKernelGGL(k_density_tiles, dim3(t.ntiles + c->max_extra), dim3(kTileThreads), (2 + 2 * fillers) * tile_lds(c, 1), s, g,
+                       t, c->bk_entries, chunks_of(c), c->heavy_acc,
+                       c->n_fixed > 0 ? c->fixed_map : nullptr, c->large_rec,
                        inst ? 0 : c->n_large, (float)p.target_density, fillers, rho, c->part, c->part_stride);
     P3D_LAUNCH(c, "k_density_tiles");
     if (inst && c->n_large > 0) {
@@ -1330,8 +1494,8 @@ int gather_bucketed(place3d_ctx* c, const float* xyz, const float* ex, const flo
   if (xfold && !tiled) return set_err(c, PLACE3D_ERR_ARG, "x-folded field maps need the tiled large-instance path");
   // Ex comes from the sine basis (unfold sign -1), Ey and Ez from the cosine basis (+1)
   const FoldX fx{xfold ? 1 : 0, g.nx / 2, -1.f, 1.f, 1.f};
-  hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles), dim3(kTileThreads), tile_lds(c, 3), s, g, t, c->bk_entries,
-                     c->bk_tile_start, ex, ey, ez, fx, c->entry_out, c->large_rec, c->n_large,
+  hipLaunchKernelGGL(k_gather_tiles, dim3(t.ntiles + c->max_extra), dim3(kTileThreads), tile_lds(c, 3), s, g, t, c->bk_entries,
+                     chunks_of(c), ex, ey, ez, fx, c->entry_out, c->large_rec, c->n_large,
                      tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_gather_tiles");
   if (c->n_large > 0 && tiled) {
@@ -1358,8 +1522,8 @@ int adjoint_bucketed(place3d_ctx* c, const float* xyz, const float* gmap, float 
   const place3d_problem& p = c->prob;
   const bool tiled = large_in_tiles(c);
   ProfScope prof_(c, PLACE3D_STAGE_DGRAD, s);
-  hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles), dim3(kTileThreads), tile_lds(c, 1), s, g, t, c->bk_entries,
-                     c->bk_tile_start, gmap, c->entry_out, c->large_rec, c->n_large,
+  hipLaunchKernelGGL(k_adjoint_tiles, dim3(t.ntiles + c->max_extra), dim3(kTileThreads), tile_lds(c, 1), s, g, t, c->bk_entries,
+                     chunks_of(c), gmap, c->entry_out, c->large_rec, c->n_large,
                      tiled && c->n_large > 0 ? c->lpart : nullptr);
   P3D_LAUNCH(c, "k_adjoint_tiles");
   if (c->n_large > 0 && tiled) {

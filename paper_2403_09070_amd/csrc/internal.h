@@ -18,6 +18,7 @@ constexpr int kNumXcd = 8;              // accelerator dies; workgroups go to th
 constexpr int kWaBlock = 256;           // threads per wirelength block
 constexpr int kPinsPerLane = 4;         // net pins a wirelength lane keeps in registers
 constexpr int kNumClasses = 7;          // nets by lane group: 1, 2, 4, ..., 64 lanes
+constexpr int kChunkEntries = 16384;    // (cell, tile) entries one tile workgroup takes at a time
 
 // Reduction slots (float64, device) inside the workspace.
 enum RedSlot {
@@ -129,6 +130,16 @@ struct place3d_ctx {
   int32_t* bk_totals = nullptr;        // [ntiles]
   int32_t* bk_tile_start = nullptr;    // [ntiles + 1]
   float4* bk_entries = nullptr;        // [2 * 4n] (cell, tile) entries
+  // tiles holding more than kChunkEntries entries are split into chunks of that many: chunk 0 is
+  // taken by the tile's own workgroup, the extra chunks by the workgroups that loop past the
+  // tile count; their density sums meet in a fixed-point accumulator per heavy tile
+  int32_t max_extra = 0, max_heavy = 0;   // bounds: 4n / kChunkEntries (+1)
+  // chunk plan, one array (the tile kernels take one pointer): [0] extra chunks and [1] heavy
+  // tiles of the current buckets, then per tile its accumulator slot (-1: one chunk), per extra
+  // chunk its tile and its index within the tile, and per slot the chunks finished (zero
+  // between calls)
+  int32_t* bk_plan = nullptr;          // [2 + ntiles + 2 max_extra + max_heavy]
+  unsigned long long* heavy_acc = nullptr;   // [max_heavy][2][T * T * nz] zero between calls
   int32_t* cell_entry = nullptr;       // [n] packed tile range of each bucketed cell, -1 if none
   float4* entry_out = nullptr;         // [4][n] per-(cell, tile) gather / adjoint results, cell-major
   // two-stage reductions: part[slot * part_stride + block]
