@@ -7,7 +7,9 @@
 * The z-gradient of the bistratal wirelength by finite differences (Eq. fda-grad): for every
   instance, the exact bistratal wirelength with the instance on the top die minus that with it
   on the bottom die, times 4/d_z, here computed the vanilla way (every flipped net re-scanned,
-  Sec. IV-B), then normalised to the planar gradient's scale (Eq. fda-normalize).
+  Sec. IV-B), then normalised to the planar gradient's scale (Eq. fda-normalize).  An instance
+  with several pins on one net moves all of them when it changes die, and that net's difference
+  counts once for it.
 
 Readings: the WA sums are shifted by the set's max (min) before exponentiation, which leaves the
 model unchanged and keeps exp finite; an empty set or a single pin has extent 0.  The smoothed
@@ -131,18 +133,19 @@ def wirelength(size, kind, xyz, net_start, pin2node, pin_off, geo, gamma, alpha)
                                        + alpha * exact_extent(uz, everyone)))
         tot["ncut"] += int(np.sum(top.any(axis=1) & (~top).any(axis=1)))
 
-        # vanilla FDA: re-evaluate the whole net with member k on the other die
+        # vanilla FDA: re-evaluate the whole net with member k's instance on the other die (all
+        # of that instance's pins on the net move with it); an instance with several pins on the
+        # net counts once, at its first member
         for k in range(d):
-            t2 = top.copy()
-            t2[:, k] = ~t2[:, k]
-            ux2 = ux.copy()
-            uy2 = uy.copy()
-            ux2[:, k] = fx[:, k]
-            uy2[:, k] = fy[:, k]
+            same = nd == nd[:, k:k + 1]                       # members owned by k's instance
+            first = ~same[:, :k].any(axis=1)
+            t2 = np.where(same, ~top, top)
+            ux2 = np.where(same, fx, ux)
+            uy2 = np.where(same, fy, uy)
             w_flip = bistratal_exact(ux2, t2) + bistratal_exact(uy2, t2)
             w_top = np.where(top[:, k], w_now, w_flip)
             w_bot = np.where(top[:, k], w_flip, w_now)
-            np.add.at(fda, nd[:, k], (4.0 / dz) * (w_top - w_bot))
+            np.add.at(fda, nd[:, k], np.where(first, (4.0 / dz) * (w_top - w_bot), 0.0))
 
     for g in (gx, gy, gzwa, fda):
         g[fixed] = 0.0

@@ -216,6 +216,60 @@ def test_fda_equals_full_reevaluation_with_instance_on_each_die():
         assert abs(out["fda"][i] - ref) < 1e-9 * max(1.0, abs(ref))
 
 
+def test_fda_moves_every_pin_of_an_instance_and_counts_it_once():
+    """An instance with two pins on a net (Eq. fda-grad takes instances, not pins): A owns the
+    pins at x = 0 and x = 10, B and C one pin each at x = 2 and x = 8, all on the bottom die, zero
+    offsets.  With A on top the net splits into {0, 10} and {2, 8}: 10 + 6 = 16 > 10; with A on
+    the bottom W = 10, so A's FDA is (4/d_z) 6 by hand.  Moving one of A's pins at a time would
+    give 0 for each (W stays 10), so a per-pin reading fails here; B and C change nothing."""
+    geo = Geometry(100.0, 100.0, 10, 10, 2)
+    xyz = np.array([[50.0, 52.0, 58.0], [50.0, 50.0, 50.0], [0.25 * geo.dz] * 3])
+    xyz[0] -= 50.0
+    xyz[0] += 20.0                       # A at 20, B at 22, C at 28; A's pins at offsets 0 and 10
+    size = np.ones((4, 3))
+    kind = np.zeros(3, dtype=np.uint8)
+    p2n = np.array([0, 0, 1, 2])
+    off = np.zeros((4, 4))
+    off[0, 1] = off[2, 1] = 10.0         # A's second pin 10 to the right on either die
+    out = wl.wirelength(size, kind, xyz, np.array([0, 4]), p2n, off, geo, gamma=1.0, alpha=0.0)
+    assert abs(out["fda"][0] - 4.0 / geo.dz * 6.0) < 1e-12
+    assert out["fda"][1] == 0.0 and out["fda"][2] == 0.0
+    assert out["hpwl_d2d"] == 10.0
+
+
+def test_fda_with_shared_instances_equals_full_reevaluation():
+    """The full re-evaluation of the design with each instance on either die, on a netlist where a
+    third of the nets hold one instance twice (on different pins)."""
+    c = synth.make_case(config=synth.small_config(n_cells=120, n_nets=150), seed=4)
+    rng = np.random.default_rng(1)
+    p2n = c.pin2node.copy()
+    ns = c.net_start
+    for e in range(len(ns) - 1):
+        if ns[e + 1] - ns[e] >= 3 and rng.random() < 0.33:
+            p2n[ns[e + 1] - 1] = p2n[ns[e]]          # the last pin goes to the first pin's owner
+    import dataclasses
+    c = dataclasses.replace(c, pin2node=p2n)
+    geo = geometry_of(c)
+    pb = problem_of(c)
+    out = wl.wirelength(pb.size, pb.kind, c.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo,
+                        pb.gamma, pb.alpha)
+    shared = set()
+    for e in range(len(ns) - 1):
+        m = p2n[ns[e]:ns[e + 1]]
+        if len(set(m.tolist())) < len(m):
+            shared.update(m.tolist())
+    assert len(shared) > 10
+    for i in sorted(shared)[:20]:
+        if c.kind[i] & 2:
+            continue
+        hi = c.xyz0.astype(np.float64).copy()
+        lo = hi.copy()
+        hi[2, i] = 0.75 * geo.dz
+        lo[2, i] = 0.25 * geo.dz
+        ref = 4.0 / geo.dz * (_total_exact(c, hi, geo) - _total_exact(c, lo, geo))
+        assert abs(out["fda"][i] - ref) < 1e-9 * max(1.0, abs(ref))
+
+
 def test_smoothed_bistratal_gradient_matches_central_differences():
     c = synth.make_case(config=synth.small_config(n_cells=150, n_nets=160), seed=8)
     geo = geometry_of(c)
