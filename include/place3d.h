@@ -72,8 +72,8 @@ typedef enum place3d_status {
   PLACE3D_ERR_HIP = -3,         /* a HIP runtime call failed; the HIP code is in last_error  */
   PLACE3D_ERR_NONFINITE = -4,   /* place3d_read_scalars: a GP iteration met a NaN or infinity  */
   PLACE3D_ERR_UNSUPPORTED = -5, /* valid request this build does not implement               */
-  PLACE3D_ERR_NETLIST = -6      /* CSR not monotone, pin owner out of range, or an instance
-                                   with two pins on one net (the FDA flips whole instances)  */
+  PLACE3D_ERR_NETLIST = -6      /* CSR not monotone, pin owner out of range, or a filler
+                                   with a pin                                                */
 } place3d_status;
 
 /* Arithmetic of the spectral contractions (a4, a5). */
@@ -180,7 +180,9 @@ typedef struct place3d_problem {
   const float* size;       /* float32 [4][n_inst]: w_bot, h_bot, w_top, h_top (Eq. std-size-tech) */
   const uint8_t* kind;     /* uint8 [n_inst], PLACE3D_KIND_* bits                             */
   const int32_t* net_start;/* int32 [n_nets+1]                                                */
-  const int32_t* pin2node; /* int32 [n_pins], owner instance of each pin                      */
+  const int32_t* pin2node; /* int32 [n_pins], owner instance of each pin; an instance may own
+                              several pins of one net (its FDA difference, Eq. fda-grad, then
+                              moves all of them and counts once for that net)                 */
   const float* pin_off;    /* float32 [4][n_pins]: ox_bot, oy_bot, ox_top, oy_top offsets from
                               the owner's centre on each die                                  */
   const float* fixed_xyz;  /* float32 [3][n_inst]: positions used for the fixed instances'

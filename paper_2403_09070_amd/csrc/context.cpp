@@ -149,6 +149,7 @@ size_t layout(place3d_ctx* c, const place3d_problem& p, char* base) {
   c->node_slot_start = w.take<int32_t>(n + 1);
   c->slot_pos = w.take<int32_t>(P + 1);
   c->heavy_list = w.take<int32_t>(n);
+  c->shared_nets = w.take<int32_t>(m);
   c->wl_gzwa = w.take<float>(n);
   c->xyzp = w.take<float4>(n);
   c->gw = w.take<float>(3 * n);
@@ -194,13 +195,14 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     if (ns[e + 1] < ns[e]) return set_err(c, PLACE3D_ERR_NETLIST, "net_start is not monotone at net " + std::to_string(e));
   for (int q = 0; q < P; ++q)
     if (p2n[q] < 0 || p2n[q] >= n) return set_err(c, PLACE3D_ERR_NETLIST, "pin2node out of range at pin " + std::to_string(q));
+  // nets holding an instance on more than one pin (allowed; their FDA is redone per instance)
+  std::vector<char> shared(m, 0);
   {
     std::vector<int32_t> tmp;
     for (int e = 0; e < m; ++e) {
       tmp.assign(p2n.begin() + ns[e], p2n.begin() + ns[e + 1]);
       std::sort(tmp.begin(), tmp.end());
-      if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end())
-        return set_err(c, PLACE3D_ERR_NETLIST, "instance with two pins on net " + std::to_string(e));
+      shared[e] = std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end();
     }
   }
 
@@ -269,6 +271,14 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
     }
   }
   sns[ms] = slot;
+  {
+    std::vector<int32_t> sh;
+    for (int k = 0; k < ms; ++k)
+      if (shared[order[k]]) sh.push_back(k);
+    c->n_shared_nets = (int32_t)sh.size();
+    if (!sh.empty())
+      P3D_HIP(c, hipMemcpyAsync(c->shared_nets, sh.data(), sizeof(int32_t) * sh.size(), hipMemcpyHostToDevice, s));
+  }
 
   // node -> slot CSR, slots ascending per node (fixed summation order)
   std::vector<int32_t> nss(n + 1, 0), nsl(P > 0 ? P : 1);

@@ -153,6 +153,8 @@ struct place3d_ctx {
   float4* pin_out = nullptr;           // [n_pins] (gx, gy, gz_wa, fda) in node order
   int32_t* node_slot_start = nullptr;  // [n+1] node -> range of pin_out
   int32_t* slot_pos = nullptr;         // [n_pins] slot -> position in node order
+  int32_t* shared_nets = nullptr;      // [n_shared_nets] schedule nets holding an instance on
+  int32_t n_shared_nets = 0;           // more than one pin (their FDA is redone per instance)
   int32_t* heavy_list = nullptr;       // instances with more than 32 pins (summed per wavefront)
   int32_t n_heavy = 0;
   p3d::ClassTab classes = {};

@@ -585,15 +585,50 @@ __global__ void k_wl_finish_z(int n, const float* __restrict__ gz_wa, const floa
   }
 }
 
-// Vanilla FDA (the O(|P_e|^2) baseline of Sec. IV-B, selected by PLACE3D_OPT_FDA_VANILLA): one
-// thread per pin slot re-evaluates its net's exact bistratal wirelength with the owner on the top
-// die and on the bottom die from all |P_e| pins, and overwrites the FDA difference k_wl_nets
-// stored for the slot.  Coordinates are relative to the net's first owner, as in k_wl_nets.
 __device__ __forceinline__ void set_put(float& mx, float& mn, float u) {
   mx = fmaxf(mx, u);
   mn = fminf(mn, u);
 }
 
+// The FDA difference of the instance owning slot s on its net (slots [b, e)), re-evaluated from
+// all the net's pins: the exact bistratal wirelength with every pin of that instance on the top
+// die minus that with every one on the bottom die, times 4/d_z (Eq. fda-grad is per instance).
+// 0 when an earlier slot of the net has the same owner: the instance counts once per net.
+// Coordinates are relative to the net's first owner, as in k_wl_nets.
+__device__ float fda_owner(int s, int b, int e, float half_dz, float four_over_dz, const float4* __restrict__ xyzp,
+                           const int32_t* __restrict__ pin_node, const float4* __restrict__ off) {
+  const int own = pin_node[s];
+  for (int q = b; q < s; ++q)
+    if (pin_node[q] == own) return 0.f;
+  const float4 q0 = xyzp[pin_node[b]];
+  const float xa = q0.x, ya = q0.y;
+  float txM = kNegInf, txm = kPosInf, tyM = kNegInf, tym = kPosInf;   // other owners' pins, on
+  float bxM = kNegInf, bxm = kPosInf, byM = kNegInf, bym = kPosInf;   // their own dies
+  float otxM = kNegInf, otxm = kPosInf, otyM = kNegInf, otym = kPosInf;   // the owner's pins on top
+  float obxM = kNegInf, obxm = kPosInf, obyM = kNegInf, obym = kPosInf;   // and on the bottom
+  int ct = 0, cb = 0, co = 0;
+  for (int q = b; q < e; ++q) {
+    const PinRel p = load_pin(xyzp, pin_node, off, q, half_dz, xa, ya);
+    if (pin_node[q] == own) {
+      set_put(otxM, otxm, p.top ? p.ux : p.fx); set_put(otyM, otym, p.top ? p.uy : p.fy);
+      set_put(obxM, obxm, p.top ? p.fx : p.ux); set_put(obyM, obym, p.top ? p.fy : p.uy);
+      ++co;
+    } else if (p.top) {
+      set_put(txM, txm, p.ux); set_put(tyM, tym, p.uy); ++ct;
+    } else {
+      set_put(bxM, bxm, p.ux); set_put(byM, bym, p.uy); ++cb;
+    }
+  }
+  const float wx_top = w_exact(fmaxf(txM, otxM), fminf(txm, otxm), ct + co, bxM, bxm, cb);
+  const float wy_top = w_exact(fmaxf(tyM, otyM), fminf(tym, otym), ct + co, byM, bym, cb);
+  const float wx_bot = w_exact(txM, txm, ct, fmaxf(bxM, obxM), fminf(bxm, obxm), cb + co);
+  const float wy_bot = w_exact(tyM, tym, ct, fmaxf(byM, obyM), fminf(bym, obym), cb + co);
+  return four_over_dz * ((wx_top - wx_bot) + (wy_top - wy_bot));
+}
+
+// Vanilla FDA (the O(|P_e|^2) baseline of Sec. IV-B, selected by PLACE3D_OPT_FDA_VANILLA): one
+// thread per pin slot re-evaluates its owner's difference from all |P_e| pins (fda_owner) and
+// overwrites the FDA value k_wl_nets stored for the slot.
 __global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, float half_dz, float four_over_dz,
                                                      const float4* __restrict__ xyzp,
                                                      const int32_t* __restrict__ s_net_start,
@@ -608,26 +643,25 @@ __global__ __launch_bounds__(256) void k_fda_vanilla(int nslots, int nnets, floa
     const int mid = (lo + hi + 1) >> 1;
     if (s_net_start[mid] <= s) lo = mid; else hi = mid - 1;
   }
-  const int b = s_net_start[lo], e = s_net_start[lo + 1];
-  const float4 q0 = xyzp[pin_node[b]];
-  const float xa = q0.x, ya = q0.y;
-  float txM = kNegInf, txm = kPosInf, tyM = kNegInf, tym = kPosInf;
-  float bxM = kNegInf, bxm = kPosInf, byM = kNegInf, bym = kPosInf;
-  int ct = 0, cb = 0;                            // pins per die set
-  for (int q = b; q < e; ++q) {                  // every other pin, on its own die
-    if (q == s) continue;
-    const PinRel p = load_pin(xyzp, pin_node, off, q, half_dz, xa, ya);
-    if (p.top) { set_put(txM, txm, p.ux); set_put(tyM, tym, p.uy); ++ct; }
-    else       { set_put(bxM, bxm, p.ux); set_put(byM, bym, p.uy); ++cb; }
-  }
-  const PinRel me = load_pin(xyzp, pin_node, off, s, half_dz, xa, ya);
-  const float xt = me.top ? me.ux : me.fx, yt = me.top ? me.uy : me.fy;   // the owner's pin on top
-  const float xb = me.top ? me.fx : me.ux, yb = me.top ? me.fy : me.uy;   // and on the bottom
-  const float wx_top = w_exact(fmaxf(txM, xt), fminf(txm, xt), ct + 1, bxM, bxm, cb);
-  const float wy_top = w_exact(fmaxf(tyM, yt), fminf(tym, yt), ct + 1, byM, bym, cb);
-  const float wx_bot = w_exact(txM, txm, ct, fmaxf(bxM, xb), fminf(bxm, xb), cb + 1);
-  const float wy_bot = w_exact(tyM, tym, ct, fmaxf(byM, yb), fminf(bym, yb), cb + 1);
-  pin_out[slot_pos[s]].w = four_over_dz * ((wx_top - wx_bot) + (wy_top - wy_bot));
+  pin_out[slot_pos[s]].w =
+      fda_owner(s, s_net_start[lo], s_net_start[lo + 1], half_dz, four_over_dz, xyzp, pin_node, off);
+}
+
+// Nets holding an instance on more than one pin (listed at create, in schedule numbering): the
+// incremental FDA of k_wl_nets flips one pin at a time, so these nets' FDA values are redone per
+// instance, one wavefront per net.
+__global__ __launch_bounds__(256) void k_fda_shared(const int32_t* __restrict__ nets, int nnets, float half_dz,
+                                                    float four_over_dz, const float4* __restrict__ xyzp,
+                                                    const int32_t* __restrict__ s_net_start,
+                                                    const int32_t* __restrict__ pin_node,
+                                                    const float4* __restrict__ off,
+                                                    const int32_t* __restrict__ slot_pos,
+                                                    float4* __restrict__ pin_out) {
+  const int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (w >= nnets) return;
+  const int k = nets[w], b = s_net_start[k], e = s_net_start[k + 1];
+  for (int s = b + (int)(threadIdx.x & (kWave - 1)); s < e; s += kWave)
+    pin_out[slot_pos[s]].w = fda_owner(s, b, e, half_dz, four_over_dz, xyzp, pin_node, off);
 }
 
 }  // namespace
@@ -655,6 +689,11 @@ int wirelength_eval(place3d_ctx* c, const float* xyz, float* grad, int accumulat
       hipLaunchKernelGGL(k_fda_vanilla, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nslots, nnets, g.half_dz,
                          4.f / g.dz, c->xyzp, c->s_net_start, c->s_pin_node, c->s_off, c->slot_pos, c->pin_out);
       P3D_LAUNCH(c, "k_fda_vanilla");
+    } else if (c->n_shared_nets > 0) {
+      hipLaunchKernelGGL(k_fda_shared, dim3(blocks_for(c->n_shared_nets, 256 / kWave)), dim3(256), 0, s,
+                         c->shared_nets, c->n_shared_nets, g.half_dz, 4.f / g.dz, c->xyzp, c->s_net_start,
+                         c->s_pin_node, c->s_off, c->slot_pos, c->pin_out);
+      P3D_LAUNCH(c, "k_fda_shared");
     }
   }
   if ((rc = reduce_final(c, R_WA_BI, 5, c->n_wa_blocks, false, red + R_WA_BI, s))) return rc;

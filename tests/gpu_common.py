@@ -110,6 +110,25 @@ def one_die_case(seed=9):
     return dataclasses.replace(case, xyz0=xyz)
 
 
+def shared_pin_case(seed=14):
+    """Nets that hold one instance on two or three pins (different offsets): in about a third of
+    the nets of three or more pins the last pin goes to the first pin's owner, in some of those
+    the second-to-last too; the rest of the netlist as generated."""
+    cfg = synth.small_config(n_cells=700, n_nets=800, die=150.0, nx=32, ny=32, nz=4,
+                             macros=("uniform", 4, 0.01, 0.04), degree=("geo", 0.75, 12))
+    case = synth.make_case(config=cfg, seed=seed)
+    rng = np.random.default_rng(seed)
+    nets = []
+    for e in range(len(case.net_start) - 1):
+        m = case.pin2node[case.net_start[e]:case.net_start[e + 1]].astype(np.int64).copy()
+        if len(m) >= 3 and rng.random() < 0.35:
+            m[-1] = m[0]
+            if len(m) >= 5 and rng.random() < 0.5:
+                m[-2] = m[0]
+        nets.append(m)
+    return with_nets(case, nets, seed)
+
+
 def no_net_case(seed=10):
     """Instances and macros but an empty netlist."""
     return with_nets(tiny_case(seed), [], seed)
