@@ -15,7 +15,7 @@ re-evaluated, which makes thousands of probes affordable on the 200k-instance ne
 
 Each probe also reports its two one-sided differences; where they disagree (an edge crossing a
 bin face, the die switch at d_z/2, a bistratal branch switch inside the stencil) the probe sits on
-a kink and is reported rather than judged.
+a kink and is reported rather than assessed.
 """
 from __future__ import annotations
 
@@ -107,18 +107,18 @@ def jacobian_l1(case, geo, v, probes):
     return out + np.where(ax == 2, zsize, 0.0)
 
 
-def judge(g, central, up, down, kink_tol=1e-2, extra=0.0):
+def assess(g, central, up, down, kink_tol=1e-2, extra=0.0):
     """Bound |g - g_FD| <= 1e-4 |g_FD| + 1e-5 median|g| (+ extra, per probe) on the probes off
     kinks.  A kink turns the derivative by an amount of the order of the gradient inside the
     stencil, so the one-sided differences then disagree by more than kink_tol (|g_FD| +
-    median|g|); smooth curvature moves them apart by h |f''| only.  Returns (n_ok, n_judged,
+    median|g|); smooth curvature moves them apart by h |f''| only.  Returns (n_ok, n_assessed,
     n_kinks, worst ratio of error to bound)."""
     g = np.asarray(g, dtype=np.float64)
     med = float(np.median(np.abs(g))) if g.size else 0.0
     kink = np.abs(up - down) > kink_tol * (np.abs(central) + med)
     bound = 1e-4 * np.abs(central) + 1e-5 * med + extra
     err = np.abs(g - central)
-    judged = ~kink
-    ok = judged & (err <= bound)
-    worst = float(np.max(err[judged] / np.maximum(bound[judged], 1e-300))) if judged.any() else 0.0
-    return int(ok.sum()), int(judged.sum()), int(kink.sum()), worst
+    assessed = ~kink
+    ok = assessed & (err <= bound)
+    worst = float(np.max(err[assessed] / np.maximum(bound[assessed], 1e-300))) if assessed.any() else 0.0
+    return int(ok.sum()), int(assessed.sum()), int(kink.sum()), worst

@@ -189,13 +189,13 @@ def test_c3_gradients_match_fp64_finite_differences_on_the_200k_netlist():
     dphi = float(np.max(np.abs(phi32 - phi))) + 4.0 * 2.0 ** -24 * float(np.max(np.abs(phi)))
     l1 = fd_local.jacobian_l1(case, geo, v, probes)
     log(f"[autograd] c3 max|phi_32 - phi| = {dphi:.3e} (max|phi| {np.max(np.abs(phi)):.3e})")
-    ok, judged, kinks, worst = fd_local.judge(gu, c, up, dn, extra=dphi * l1)
-    log(f"[autograd] c3 U: {ok}/{judged} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
-    assert judged >= 0.9 * len(probes) and ok >= 0.99 * judged
+    ok, assessed, kinks, worst = fd_local.assess(gu, c, up, dn, extra=dphi * l1)
+    log(f"[autograd] c3 U: {ok}/{assessed} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
+    assert assessed >= 0.9 * len(probes) and ok >= 0.99 * assessed
     # W: skip z probes whose stencil crosses the die switch at d_z/2 (a step of the bistratal part)
     wprobes = [(i, a) for i, a in probes if not (a == 2 and abs(v[2, i] - 0.5 * geo.dz) < 2 * h)]
     c, up, dn = fd_local.wirelength_differences(pb, v, wprobes, h)
     gw = np.array([g_w[a, i] for i, a in wprobes])
-    ok, judged, kinks, worst = fd_local.judge(gw, c, up, dn)
-    log(f"[autograd] c3 W: {ok}/{judged} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
-    assert judged >= 0.9 * len(wprobes) and ok >= 0.99 * judged
+    ok, assessed, kinks, worst = fd_local.assess(gw, c, up, dn)
+    log(f"[autograd] c3 W: {ok}/{assessed} coordinates within the bound, {kinks} on kinks, worst error/bound {worst:.3f}")
+    assert assessed >= 0.9 * len(wprobes) and ok >= 0.99 * assessed
