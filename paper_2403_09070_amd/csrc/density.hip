@@ -360,10 +360,12 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(Geom g, TileGeo
 // wavefront q scans tile 64 g + l over the q-th of kScanParts ranges of blocks, so that a
 // wavefront reads 64 adjacent counts (256 bytes) of one block row at a time; each range is then
 // offset by the sums of the ranges before it.  A range of up to kScanHeld rows is loaded once into
-// registers (all its loads in flight together) and written back from them.
+// registers (all its loads in flight together) and written back from them; a longer range is
+// read twice, kScanChunk rows at a time.
 constexpr int kScanTiles = 64;
 constexpr int kScanParts = 16;
 constexpr int kScanHeld = 48;
+constexpr int kScanChunk = 16;
 __global__ __launch_bounds__(kScanTiles * kScanParts) void k_bucket_scan_cols(int nblk, int ntiles,
                                                                              int32_t* __restrict__ counts,
                                                                              int32_t* __restrict__ totals) {
@@ -381,8 +383,13 @@ __global__ __launch_bounds__(kScanTiles * kScanParts) void k_bucket_scan_cols(in
       for (int j = 0; j < kScanHeld; ++j) v[j] = b0 + j < b1 ? counts[(size_t)(b0 + j) * ntiles + tile] : 0;
 #pragma unroll
       for (int j = 0; j < kScanHeld; ++j) s += v[j];
-    } else {
-      for (int b = b0; b < b1; ++b) s += counts[(size_t)b * ntiles + tile];
+    } else {                    // longer ranges: kScanChunk rows at a time, each chunk's loads together
+      for (int c0 = b0; c0 < b1; c0 += kScanChunk) {
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < b1 ? counts[(size_t)(c0 + j) * ntiles + tile] : 0;
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j) s += v[j];
+      }
     }
   }
   part[q][l] = s;
@@ -398,11 +405,15 @@ __global__ __launch_bounds__(kScanTiles * kScanParts) void k_bucket_scan_cols(in
           run += v[j];
         }
     } else {
-      for (int b = b0; b < b1; ++b) {
-        const size_t o = (size_t)b * ntiles + tile;
-        const int c = counts[o];
-        counts[o] = run;
-        run += c;
+      for (int c0 = b0; c0 < b1; c0 += kScanChunk) {
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < b1 ? counts[(size_t)(c0 + j) * ntiles + tile] : 0;
+#pragma unroll
+        for (int j = 0; j < kScanChunk; ++j)
+          if (c0 + j < b1) {
+            counts[(size_t)(c0 + j) * ntiles + tile] = run;
+            run += v[j];
+          }
       }
     }
     if (q == kScanParts - 1) totals[tile] = run;
@@ -1208,6 +1219,49 @@ __device__ __forceinline__ AdjSums adjoint_sums(const Geom& g, const Foot& f, Ma
   return a;
 }
 
+// adjoint_sums of one bucketed cell (no size terms, one thread), as nested loops over z, y and x
+// with the x overlaps and edge indicators held in registers: the same bins in the same order as
+// the flat loop, so the same sums bit for bit, without its index divisions.  Boxes wider than
+// kAdjSpan bins take the flat loop.
+constexpr int kAdjSpan = 8;
+
+template <class MapAt>
+__device__ __forceinline__ AdjSums adjoint_sums_cell(const Geom& g, const Foot& f, MapAt map_at, int bx0, int bx1,
+                                                     int by0, int by1, int xl0, int xl1, int yl0, int yl1) {
+  const EdgeBins e = edge_bins(g, f);
+  int x0 = bx0, x1 = bx1, y0 = by0, y1 = by1, z0 = f.bz0, z1 = f.bz1;
+  widen(x0, x1, e.xl, xl0, xl1); widen(x0, x1, e.xh, xl0, xl1);
+  widen(y0, y1, e.yl, yl0, yl1); widen(y0, y1, e.yh, yl0, yl1);
+  widen(z0, z1, e.zl, 0, g.nz - 1); widen(z0, z1, e.zh, 0, g.nz - 1);
+  const int nbx = x1 - x0 + 1;
+  if (nbx > kAdjSpan) return adjoint_sums(g, f, map_at, bx0, bx1, by0, by1, xl0, xl1, yl0, yl1, 0, 1, false);
+  float lxs[kAdjSpan], dxs[kAdjSpan];
+#pragma unroll
+  for (int j = 0; j < kAdjSpan; ++j) {
+    const int bx = x0 + j;
+    lxs[j] = j < nbx ? len_x(g, f, bx) : 0.f;
+    dxs[j] = ((bx == e.xh) ? 1.f : 0.f) - ((bx == e.xl) ? 1.f : 0.f);
+  }
+  AdjSums a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int bz = z0; bz <= z1; ++bz) {
+    const float lz = len_z(g, f, bz);
+    const float dz = ((bz == e.zh) ? 1.f : 0.f) - ((bz == e.zl) ? 1.f : 0.f);
+    for (int by = y0; by <= y1; ++by) {
+      const float ly = len_y(g, f, by);
+      const float dy = ((by == e.yh) ? 1.f : 0.f) - ((by == e.yl) ? 1.f : 0.f);
+#pragma unroll
+      for (int j = 0; j < kAdjSpan; ++j)
+        if (j < nbx) {
+          const float mv = map_at(bz, by, x0 + j);
+          a.gx += dxs[j] * ly * lz * mv;
+          a.gy += lxs[j] * dy * lz * mv;
+          a.gz += lxs[j] * ly * dz * mv;
+        }
+    }
+  }
+  return a;
+}
+
 __device__ __forceinline__ float3 adjoint_finish(const Geom& g, const Foot& f, const AdjSums& a) {
   float3 r = make_float3(f.omega * a.gx, f.omega * a.gy, f.omega * a.gz);
   if (f.dw != 0.f || f.dh != 0.f) {
@@ -1262,8 +1316,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
       const int by0 = max(f.by0, tb.y0), by1 = min(f.by1, tb.y0 + tb.wy - 1);
       float3 r = make_float3(0.f, 0.f, 0.f);
       if (bx0 <= bx1 && by0 <= by1) {
-        const AdjSums a = adjoint_sums(g, f, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0,
-                                       tb.y0 + tb.wy - 1, 0, 1, false);
+        const AdjSums a = adjoint_sums_cell(g, f, at, bx0, bx1, by0, by1, tb.x0, tb.x0 + tb.wx - 1, tb.y0,
+                                            tb.y0 + tb.wy - 1);
         r = adjoint_finish(g, f, a);
       }
       out[oi] = make_float4(r.x, r.y, r.z, 0.f);
