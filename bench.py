@@ -29,6 +29,8 @@ O(|P_e|^2) FDA) against the default ones on the 1.2M-cell workload.  ``--ablatio
 global placement on the 4M-cell workload from a clustered start until the overflow is below 0.1,
 for the plain, mixed and autograd forms.  ``--ablation divergence`` records the per-iteration
 HPWL of plain, mixed, and plain from a start moved by one ulp (default workload c1).
+``--ablation md2d`` times multi-die 2D global placement (Sec. III-C) on the die split of a 3D
+placement of the 1.2M-cell workload.
 """
 from __future__ import annotations
 
@@ -431,6 +433,68 @@ def divergence_run(args, log):
                       "max_rel_mixed": float(d_mixed.max()), "max_rel_1ulp": float(d_ulp.max())}), flush=True)
 
 
+def md2d_run(args, log):
+    """Multi-die 2D global placement (Sec. III-C, Eq. 2d-place) after 3D global placement: the
+    workload placed by --md-3d-iters mixed 3D steps from its start, split by die with the
+    package's ``layers.split`` (one HBT per crossing net, started in its optimal region; the split
+    is timed on the host), then --warmup and --steps multi-die 2D steps in float32 and in
+    split-bf16 form from the same split: iterations/s, the partial nets' HPWL and the per-layer
+    overflow (bottom, top, HBT layer) after the timed steps.  Inputs are resident on the GPU before
+    timing; no host readback inside the timed loop."""
+    import numpy as np
+    import torch
+    from paper_2403_09070_amd import layers, place3d, synth
+    case = synth.make_case(args.config, args.seed)
+    params = place3d.Problem.case_params(case)
+    prob3 = place3d.Problem.from_case(case, precision=place3d.BF16X3)
+    st3 = prob3.gp_init(case.xyz0)
+    for _ in range(args.md_3d_iters):
+        prob3.step(st3)
+    torch.cuda.synchronize()
+    xyz = st3.v.cpu().numpy().astype(np.float64)
+    s3 = st3.read()
+    del prob3, st3
+    torch.cuda.empty_cache()
+    wb = case.die_x / case.nx
+    dz = case.nz * 0.5 * (wb + case.die_y / case.ny)
+    t0 = time.perf_counter()
+    lay, xy0 = layers.split(case.size, case.kind, xyz, case.net_start, case.pin2node, case.pin_off, dz,
+                            layers.Grid(case.die_x, case.die_y, case.nx, case.ny), params["gamma"],
+                            hbt_side=case.config.hbt_pitch, ramp=params["lambda_ramp"],
+                            target=params["target_density"])
+    t_split = time.perf_counter() - t0
+    xy0 = xy0.astype(np.float32)
+    log(f"[md2d] split after {args.md_3d_iters} 3D steps: {lay.n_hbt} HBTs, {len(lay.net_start) - 1} partial nets, "
+        f"{t_split:.2f} s")
+    out = {}
+    for name, precision in (("plain", place3d.FP32), ("mixed", place3d.BF16X3)):
+        prob = place3d.MultiDie2D.from_layered(lay, fixed_xy=xy0, precision=precision)
+        st = prob.gp_init(xy0)
+        for _ in range(args.warmup):
+            prob.step(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            prob.step(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = st.read()
+        out[name] = dict(iters_per_s=round(args.steps / dt, 1), ms_per_step=round(1e3 * dt / args.steps, 4),
+                         hpwl=s["hpwl"], ovfl=[s["ovfl_bot"], s["ovfl_top"], s["ovfl_hbt"]])
+        log(f"[md2d] {name}: {out[name]}")
+        del prob, st
+        torch.cuda.empty_cache()
+    print(json.dumps({"run": "multi-die 2D", "workload": f"{args.config} seed {args.seed}: {case.meta['n_cells']} "
+                      f"cells + {case.meta['n_macros']} macros, {case.n_nets} nets, {case.n_pins} pins, grid "
+                      f"{case.nx}x{case.ny}", "iterations_3d": args.md_3d_iters, "hpwl_3d_d2d": s3["hpwl"],
+                      "n_hbt": int(lay.n_hbt), "partial_nets": int(len(lay.net_start) - 1),
+                      "nodes": int(lay.w.shape[0]), "pins": int(lay.pin2node.shape[0]), "split_seconds": round(t_split, 3),
+                      "steps": args.steps, "warmup": args.warmup, "forms": out,
+                      "mixed_over_plain": round(out["mixed"]["iters_per_s"] / out["plain"]["iters_per_s"], 3),
+                      "hpwl_rel_diff": abs(out["mixed"]["hpwl"] - out["plain"]["hpwl"]) / out["plain"]["hpwl"]}),
+          flush=True)
+
+
 def converge_run(args, log):
     """Global placement from a clustered start until the larger per-die overflow falls below
     --converge-overflow (or --converge-max iterations), for the plain (float32, field gather),
@@ -495,12 +559,13 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a float32 buffer of this many MiB three times (a plain copy kernel of "
                          "known traffic, to scale hardware byte counters)")
-    ap.add_argument("--ablation", choices=["precond", "algo", "converge", "divergence"], default=None,
+    ap.add_argument("--ablation", choices=["precond", "algo", "converge", "divergence", "md2d"], default=None,
                     help="run an ablation or study instead of the timing benchmark")
     ap.add_argument("--ablation-iters", type=int, default=1000)
     ap.add_argument("--ablation-every", type=int, default=5)
     ap.add_argument("--ablation-spread", type=float, default=0.02)
     ap.add_argument("--ablation-stop", type=float, default=0.1)
+    ap.add_argument("--md-3d-iters", type=int, default=200, help="3D steps before the multi-die split (md2d)")
     ap.add_argument("--converge-overflow", type=float, default=0.1)
     ap.add_argument("--converge-max", type=int, default=3000)
     ap.add_argument("--ablation-util", type=float, default=0.8,
@@ -527,6 +592,10 @@ def main():
     if args.ablation == "converge":
         args.config = args.config or "c5"
         converge_run(args, log)
+        return
+    if args.ablation == "md2d":
+        args.config = args.config or "c4"
+        md2d_run(args, log)
         return
     if args.ablation == "divergence":
         args.config = args.config or "c1"
