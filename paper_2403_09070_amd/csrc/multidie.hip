@@ -53,9 +53,14 @@ struct place3d_md2d_ctx {
   int part_stride = 0;
   char* sub_ws[4] = {};
   size_t sub_bytes[4] = {};
+  // an evaluation forks the wirelength and the three layers onto the sub-contexts' side streams
+  hipEvent_t ev_fork = nullptr, ev_done[4] = {};
   ~place3d_md2d_ctx() {
     place3d_destroy(wl);
     for (auto* c : lay) place3d_destroy(c);
+    if (ev_fork) hipEventDestroy(ev_fork);
+    for (auto& ev : ev_done)
+      if (ev) hipEventDestroy(ev);
   }
 };
 
@@ -443,20 +448,31 @@ LayerRed layer_red(const place3d_md2d_ctx* c) {
 
 // both objective parts at xy: the wirelength context's gradient into g_wl, each layer's 2D
 // field-gather gradient into g_l; with energy, also phi and U_3 of each layer into en[3]
+// The partial nets' wirelength and the three layers' density chains share nothing but the packed
+// positions: after the pack on s they run concurrently, each on its sub-context's side stream
+// (default priority), and s waits for all four before anything reads their results.
 int md_evaluate(place3d_md2d_ctx* c, const float* xy, hipStream_t s, double* en = nullptr) {
   const place3d_md2d_problem& p = c->prob;
   const int n = p.n_nodes;
   hipLaunchKernelGGL(k_md_pack, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xy, p.layer, c->node_local, c->zmid,
                      c->xyz_wl, c->xyz_l[0], c->xyz_l[1], c->xyz_l[2], c->n_of[0], c->n_of[1], c->n_of[2]);
   MD_HIP(c, hipGetLastError());
-  MD_SUB(c, c->wl, wirelength_eval(c->wl, c->xyz_wl, c->g_wl, 0, c->wl->red, nullptr, s, false, nullptr, false));
+  MD_HIP(c, hipEventRecord(c->ev_fork, s));
+  hipStream_t ws = c->wl->side;
+  MD_HIP(c, hipStreamWaitEvent(ws, c->ev_fork, 0));
+  MD_SUB(c, c->wl, wirelength_eval(c->wl, c->xyz_wl, c->g_wl, 0, c->wl->red, nullptr, ws, false, nullptr, false));
+  MD_HIP(c, hipEventRecord(c->ev_done[0], ws));
   for (int L = 0; L < 3; ++L) {
     place3d_ctx* lc = c->lay[L];
-    MD_SUB(c, lc, density_forward(lc, c->xyz_l[L], lc->rho, s));
-    MD_SUB(c, lc, spectral_field(lc, lc->rho, en ? lc->phi : nullptr, lc->ex, lc->ey, nullptr, en ? en + L : nullptr, s));
+    hipStream_t ls = lc->side;
+    MD_HIP(c, hipStreamWaitEvent(ls, c->ev_fork, 0));
+    MD_SUB(c, lc, density_forward(lc, c->xyz_l[L], lc->rho, ls));
+    MD_SUB(c, lc, spectral_field(lc, lc->rho, en ? lc->phi : nullptr, lc->ex, lc->ey, nullptr, en ? en + L : nullptr, ls));
     // grad = (4/d_z) grad_3: the layer's 2D field-gather gradient; E_z is read from a zero map
-    MD_SUB(c, lc, gather_bucketed(lc, c->xyz_l[L], lc->ex, lc->ey, lc->ez, -4.f / c->dz, c->g_l[L], 0, s));
+    MD_SUB(c, lc, gather_bucketed(lc, c->xyz_l[L], lc->ex, lc->ey, lc->ez, -4.f / c->dz, c->g_l[L], 0, ls));
+    MD_HIP(c, hipEventRecord(c->ev_done[1 + L], ls));
   }
+  for (auto& ev : c->ev_done) MD_HIP(c, hipStreamWaitEvent(s, ev, 0));
   return PLACE3D_OK;
 }
 
@@ -599,7 +615,10 @@ int32_t place3d_md2d_create(const place3d_md2d_problem* prob, void* d_workspace,
     rc = launch_fill_f32(c->lay[L], c->lay[L]->ez, map, 0.f, s);
     if (rc != PLACE3D_OK) return fail(rc, place3d_last_error(c->lay[L]));
   }
-  e = hipStreamSynchronize(s);
+  e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  for (auto& ev : c->ev_done)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(PLACE3D_ERR_HIP, std::string("create: ") + hipGetErrorString(e));
   *out = c;
   return PLACE3D_OK;
