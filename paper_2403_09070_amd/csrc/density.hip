@@ -639,7 +639,8 @@ struct EntryStream {
 // one-chunk tiles occupancy).
 struct Chunks {
   const int32_t* __restrict__ tile_start;   // [ntiles + 1] entry ranges of the tiles
-  int32_t* plan;                            // the context's chunk plan (layout in plan_*)
+  int32_t* plan;                            // the context's chunk plan (written by chunk_plan;
+                                            // its layout is in the accessors below)
   int ntiles, max_extra;
   __device__ __forceinline__ int n_extra() const { return plan[0]; }
   __device__ __forceinline__ int slot(int tile) const { return plan[2 + tile]; }
