@@ -611,23 +611,35 @@ __device__ __forceinline__ unsigned long long to_fix_unit(float v) {   // 0 <= v
 // x bins of a bucketed entry whose overlap lengths are held in registers
 constexpr int kSpanX = 4;
 
-// A thread's entries of one tile (first, first + step, ... below last), read one entry ahead: the
-// next entry's two loads are issued before the current entry is processed, and the first entry's
-// before the tile's maps are staged, so that their latency overlaps work already in hand.
+// A thread's entries of one tile (first, first + step, ... below last), read D entries ahead: the
+// loads of the next D entries are in flight while the current one is processed, and the first D
+// entries' are issued before the tile's maps are staged, so that their latency overlaps work
+// already in hand (a thread holds ~2.5 entries of a tile at the 1.2M-cell workload, so D = 2
+// issues nearly all of them at once).  D costs 8 VGPRs per entry held.
+template <int D>
 struct EntryStream {
   const float4* __restrict__ entries;
   int e, last, step;
-  float4 na, nb;
+  float4 na[D], nb[D];
+  __device__ __forceinline__ void fetch(int k, int at) {
+    if (at < last) { na[k] = entries[2 * (size_t)at]; nb[k] = entries[2 * (size_t)at + 1]; }
+  }
   __device__ __forceinline__ EntryStream(const float4* __restrict__ en, int first, int last_, int step_)
-      : entries(en), e(first), last(last_), step(step_), na(make_float4(0.f, 0.f, 0.f, 0.f)), nb(na) {
-    if (e < last) { na = entries[2 * (size_t)e]; nb = entries[2 * (size_t)e + 1]; }
+      : entries(en), e(first), last(last_), step(step_) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      na[k] = nb[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      fetch(k, e + k * step);
+    }
   }
   __device__ __forceinline__ bool next(float4& a, float4& b) {
     if (e >= last) return false;
-    a = na;
-    b = nb;
+    a = na[0];
+    b = nb[0];
+#pragma unroll
+    for (int k = 0; k + 1 < D; ++k) { na[k] = na[k + 1]; nb[k] = nb[k + 1]; }
     e += step;
-    if (e < last) { na = entries[2 * (size_t)e]; nb = entries[2 * (size_t)e + 1]; }
+    fetch(D - 1, e + (D - 1) * step);
     return true;
   }
 };
@@ -742,7 +754,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
   {
     const ChunkRef ck = chunk_ref(ch, t, qc);
     const TileBox tb = tile_box(g, t, ck.tile);
-    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    EntryStream<1> es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
     for (int k = threadIdx.x; k < tsz; k += blockDim.x) {
       const int lx = k & (t.T - 1), ly = (k >> t.lgT) & (t.T - 1), bz = k >> (2 * t.lgT);
       // fixed_map is null when the problem has no fixed instances (the map is then all zero)
@@ -759,13 +771,21 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const Foot h = foot_record(g, lrec, hits[h_]);
         const int bx0 = max(h.bx0, tb.x0), bx1 = min(h.bx1, tb.x0 + tb.wx - 1);
         const int by0 = max(h.by0, tb.y0), by1 = min(h.by1, tb.y0 + tb.wy - 1);
-        const int nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1, nbz = h.bz1 - h.bz0 + 1;
-        const int total_bins = nbx * nby * nbz;
         const float wgt = h.omega * inv_vol;
-        for (int b = threadIdx.x; b < total_bins; b += blockDim.x) {
-          const int bx = bx0 + b % nbx, by = by0 + (b / nbx) % nby, bz = h.bz0 + b / (nbx * nby);
-          const float v = len_x(g, h, bx) * len_y(g, h, by) * len_z(g, h, bz) * wgt;
-          S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix_unit(v);   // one thread per bin within one instance
+        // thread (column lx, row ry) of the tile takes the instance's bins of column bx0 + lx in
+        // rows by0 + ry, by0 + ry + rows per pass, ... on every z layer: no index division, one
+        // thread per bin within one instance
+        const int lx = threadIdx.x & (t.T - 1), ry = threadIdx.x >> t.lgT, rstep = blockDim.x >> t.lgT;
+        const int bx = bx0 + lx;
+        if (bx <= bx1) {
+          const float lxv = len_x(g, h, bx);
+          for (int bz = h.bz0; bz <= h.bz1; ++bz) {
+            const float lz = len_z(g, h, bz);
+            for (int by = by0 + ry; by <= by1; by += rstep) {
+              const float v = lxv * len_y(g, h, by) * lz * wgt;
+              S64[lds_index(t, bz, by - tb.y0, bx - tb.x0)] += to_fix_unit(v);
+            }
+          }
         }
         __syncthreads();
       }
@@ -968,7 +988,7 @@ __global__ __launch_bounds__(kTileThreads) void k_gather_tiles(Geom g, TileGeom 
     const ChunkRef ck = chunk_ref(ch, t, qc);
     const int tile = ck.tile;
     const TileBox tb = tile_box(g, t, tile);
-    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    EntryStream<2> es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
     // natural-order maps whose rows and tile width are multiples of 4 bins: stage 4 bins per load
     // (the row start tb.x0 + lx is then a multiple of 4, so the 16-byte loads are aligned)
     const bool vec = !fx.on && (g.nx & 3) == 0 && (tb.wx & 3) == 0 &&
@@ -1294,7 +1314,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adjoint_tiles(Geom g, TileGeom
     const ChunkRef ck = chunk_ref(ch, t, qc);
     const int tile = ck.tile;
     const TileBox tb = tile_box(g, t, tile);
-    EntryStream es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
+    EntryStream<1> es(entries, ck.first + (int)threadIdx.x, ck.last, (int)blockDim.x);
     // rows and tile width multiples of 4 bins: stage 4 bins per load (aligned, as in the gather)
     const bool vec = (g.nx & 3) == 0 && (tb.wx & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0;
     for (int k = vec ? 4 * (int)threadIdx.x : tsz; k < tsz; k += 4 * (int)blockDim.x) {
