@@ -132,9 +132,14 @@ __device__ __forceinline__ void ext_merge(Ext2& e) {
   e.min1 = fminf(e.min1, b1);
 }
 
-// A float32 sum, compensated when C (Neumaier's variant of Kahan summation: the rounding error of
-// every addition is kept in c and added back at the end), plain otherwise.  merge<M> adds the
-// partner lane's sum; it is commutative, so both partners of a butterfly hold the same sum.
+// A float32 sum, compensated when C (the rounding error of every addition is kept in c and added
+// back at the end), plain otherwise.  add: Neumaier's variant of Kahan summation, for terms of
+// any size.  add_small: for a term no larger in magnitude than the running sum, whose rounding
+// error is then x - (t - s) exactly (Dekker's Fast2Sum) at half the cost; a lane's exponential
+// sums use it by starting from an offset of their terms' sign at least as large as any term (so
+// the running sum never falls below a term) and taking the offset off, exactly, before they are
+// merged or read.  merge<M> adds the partner lane's sum; it is commutative, so both partners of a
+// butterfly hold the same sum.
 template <bool C>
 struct Acc {
   float s, c;
@@ -142,6 +147,15 @@ struct Acc {
     if constexpr (C) {
       const float t = s + x;
       c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    } else {
+      s += x;
+    }
+  }
+  __device__ __forceinline__ void add_small(float x) {
+    if constexpr (C) {
+      const float t = s + x;
+      c += x - (t - s);
       s = t;
     } else {
       s += x;
@@ -182,12 +196,28 @@ __device__ __forceinline__ void sums_merge(Sums4<C>& s) {
 template <bool C>
 struct AxisSums { Sums4<C> t, b; };
 
+// Starting values of a lane's four sums and their removal.  The terms e^{(u-M)/g} and e^{-(u-m)/g}
+// lie in (0, 1] and (u-M) e^{(u-M)/g} in [-g/e, 0], (u-m) e^{-(u-m)/g} in [0, g/e]; with big a
+// power of two above gamma, the offsets 1, -big, 1, big bound every term, and s - offset is exact
+// (both are multiples of the sum's ulp and the difference is no larger than the sum).
+template <bool C>
+__device__ __forceinline__ Sums4<C> sums_start(float big) {
+  if constexpr (C) return {{1.f, 0.f}, {-big, 0.f}, {1.f, 0.f}, {big, 0.f}};
+  else return {};
+}
+template <bool C>
+__device__ __forceinline__ void sums_settle(Sums4<C>& s, float big) {
+  if constexpr (C) {
+    s.sp.s -= 1.f; s.tp.s += big; s.sm.s -= 1.f; s.tm.s -= big;
+  }
+}
+
 template <bool C>
 __device__ __forceinline__ void sums_add(Sums4<C>& s, bool in, float du, float dl, float ep, float em) {
-  s.sp.add(in ? ep : 0.f);
-  s.tp.add(in ? du * ep : 0.f);
-  s.sm.add(in ? em : 0.f);
-  s.tm.add(in ? dl * em : 0.f);
+  s.sp.add_small(in ? ep : 0.f);
+  s.tp.add_small(in ? du * ep : 0.f);
+  s.sm.add_small(in ? em : 0.f);
+  s.tm.add_small(in ? dl * em : 0.f);
 }
 
 // one pin's terms along one axis: u its coordinate, (M, m) the extremes of its own set
@@ -332,31 +362,45 @@ __device__ __forceinline__ void group_merge(T& v) {
 
 struct NetTotals { float wa_bi, wa_z, hpwl, hpwl3d, ncut; };
 
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over the wavefront in a fixed order: quad, half-row and row sums by DPP exchanges
-// (xor 1, xor 2, mirror 8, mirror 16), then the four row sums; compensated when C.
+// (xor 1, xor 2, mirror 8, mirror 16), then the four row sums; in float64 when C (at least as
+// accurate as a compensated float32 sum of these 64 values, and fewer instructions).
 template <bool C>
-__device__ __forceinline__ float wave_sum(float v) {
-  Acc<C> a{v, 0.f};
-  a.template merge<1>();     // quad_perm(1, 0, 3, 2)
-  a.template merge<2>();     // quad_perm(2, 3, 0, 1)
-  a.template merge<4>();     // row_half_mirror
-  a.template merge<8>();     // row_mirror
+__device__ __forceinline__ double wave_sum(float v) {
   if constexpr (!C) {
-    return (lane_value(a.s, 0) + lane_value(a.s, 16)) + (lane_value(a.s, 32) + lane_value(a.s, 48));
+    float a = v;
+    a += dpp<0xB1>(a);       // quad_perm(1, 0, 3, 2)
+    a += dpp<0x4E>(a);       // quad_perm(2, 3, 0, 1)
+    a += dpp<0x141>(a);      // row_half_mirror
+    a += dpp<0x140>(a);      // row_mirror
+    return (double)((lane_value(a, 0) + lane_value(a, 16)) + (lane_value(a, 32) + lane_value(a, 48)));
   } else {
-    Acc<C> r{lane_value(a.s, 0), lane_value(a.c, 0)};
-    for (int l = 16; l < kWave; l += 16) {
-      r.add(lane_value(a.s, l));
-      r.add(lane_value(a.c, l));
-    }
-    return r.value();
+    double a = (double)v;
+    a += dpp<0xB1>(a);
+    a += dpp<0x4E>(a);
+    a += dpp<0x141>(a);
+    a += dpp<0x140>(a);
+    return (lane_value(a, 0) + lane_value(a, 16)) + (lane_value(a, 32) + lane_value(a, 48));
   }
 }
 
 // one net per group of G lanes; lane lg of the group holds pins lg + G j.  kGrad: also write the
 // per-pin results (phase C); else only the net totals.  C: compensated exponential sums.
 template <int G, bool kGrad, bool C>
-__device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, float four_over_dz, float ig,
+__device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, float four_over_dz, float ig, float big,
                                               float alpha, const float4* __restrict__ xyzp,
                                               const int32_t* __restrict__ s_net_start,
                                               const int32_t* __restrict__ pin_node, const float4* __restrict__ off,
@@ -382,7 +426,7 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   // hold two floats each)
   NetCoef c;
   {
-    AxisSums<C> S = {};
+    AxisSums<C> S = {sums_start<C>(big), sums_start<C>(big)};
 #pragma unroll
     for (int j = 0; j < kPinsPerLane; ++j)
       if (lg + G * j < d)
@@ -391,11 +435,12 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
       const PinRel p = load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya);
       sums_axis(S, p.top, p.ux, p.top ? a.tx.max1 : a.bx.max1, p.top ? a.tx.min1 : a.bx.min1, ig);
     }
+    sums_settle(S.t, big); sums_settle(S.b, big);
     group_merge<G>(S);
     c.x = axis_coef(a.tx, val(S.t), a.ct, a.bx, val(S.b), a.cb, ig);
   }
   {
-    AxisSums<C> S = {};
+    AxisSums<C> S = {sums_start<C>(big), sums_start<C>(big)};
 #pragma unroll
     for (int j = 0; j < kPinsPerLane; ++j)
       if (lg + G * j < d)
@@ -404,15 +449,17 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
       const PinRel p = load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya);
       sums_axis(S, p.top, p.uy, p.top ? a.ty.max1 : a.by.max1, p.top ? a.ty.min1 : a.by.min1, ig);
     }
+    sums_settle(S.t, big); sums_settle(S.b, big);
     group_merge<G>(S);
     c.y = axis_coef(a.ty, val(S.t), a.ct, a.by, val(S.b), a.cb, ig);
   }
   {
-    Sums4<C> S = {};
+    Sums4<C> S = sums_start<C>(big);
 #pragma unroll
     for (int j = 0; j < kPinsPerLane; ++j)
       if (lg + G * j < d) sums_z(S, a, pc[j], ig);
     for (int k = lg + G * kPinsPerLane; k < d; k += G) sums_z(S, a, load_pin(xyzp, pin_node, off, s + k, half_dz, xa, ya), ig);
+    sums_settle(S, big);
     group_merge<G>(S);
     const Sums4v sz = val(S);
     c.az_p = rcp(sz.sp); c.Az_p = sz.tp * c.az_p;
@@ -460,10 +507,13 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const int net = tab.net_begin[pos] + (blk - tab.block_begin[pos]) * (kWaBlock >> lg2) + ((int)threadIdx.x >> lg2);
   const int lg = threadIdx.x & ((1 << lg2) - 1);
   const float ig = 1.f / gamma;
+  int ge;
+  (void)frexpf(gamma, &ge);
+  const float big = ldexpf(1.f, ge);               // a power of two above gamma
   NetTotals t = {0.f, 0.f, 0.f, 0.f, 0.f};
   if (net < tab.net_begin[pos + 1]) {
 #define P3D_GROUP(G) \
-  wl_group<G, kGrad, C>(net, lg, half_dz, four_over_dz, ig, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
+  wl_group<G, kGrad, C>(net, lg, half_dz, four_over_dz, ig, big, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
     switch (lg2) {
       case 0: t = P3D_GROUP(1); break;
       case 1: t = P3D_GROUP(2); break;
@@ -479,8 +529,8 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const float v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    const float x = wave_sum<C>(v[q]);
-    if ((threadIdx.x & (kWave - 1)) == 0) shred[q][threadIdx.x / kWave] = (double)x;
+    const double x = wave_sum<C>(v[q]);
+    if ((threadIdx.x & (kWave - 1)) == 0) shred[q][threadIdx.x / kWave] = x;
   }
   __syncthreads();
   if (threadIdx.x < 5) {
