@@ -207,32 +207,35 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   }
 
   // nets by lane-group class: a net of degree d takes G = 2^c lanes, the smallest with
-  // d <= kPinsPerLane * G (64 lanes for larger nets, which then loop).  Classes are laid out
-  // from the widest groups down, nets in netlist order within a class; empty nets are dropped.
-  // The workgroups of all classes then run in the order of their first net (block_order), so
-  // the whole sweep walks the netlist once and the owners it gathers stay cache-resident.
-  auto net_class = [](int d) {
+  // d <= kPinsPerLane * G (64 lanes for larger nets, which then loop), except that two-pin nets
+  // form a class of their own (one lane each, in closed form), so that no wavefront mixes them
+  // with the general single-lane nets.  Classes are laid out from the widest groups down, then
+  // the two-pin nets, nets in netlist order within a class; empty nets are dropped.  The
+  // workgroups of all classes then run in the order of their first net (block_order), so the
+  // whole sweep walks the netlist once and the owners it gathers stay cache-resident.
+  auto net_pos = [](int d) {          // layout position of a net of degree d
+    if (d == 2) return p3d::kNumClasses - 1;
     int cl = 0;
-    while (p3d::kPinsPerLane * (1 << cl) < d && cl < p3d::kNumClasses - 1) ++cl;
-    return cl;
+    while (p3d::kPinsPerLane * (1 << cl) < d && cl < p3d::kNumGroups - 1) ++cl;
+    return p3d::kNumGroups - 1 - cl;
   };
+  auto pos_lanes_log2 = [](int i) { return i < p3d::kNumGroups ? p3d::kNumGroups - 1 - i : 0; };
   std::vector<int32_t> order;
   order.reserve(m);
   for (int e = 0; e < m; ++e)
     if (ns[e + 1] > ns[e]) order.push_back(e);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return net_class(ns[a + 1] - ns[a]) > net_class(ns[b + 1] - ns[b]);
+    return net_pos(ns[a + 1] - ns[a]) < net_pos(ns[b + 1] - ns[b]);
   });
   {
     int nb = 0;
     size_t k = 0;
-    for (int i = 0; i < p3d::kNumClasses; ++i) {     // layout position i: G = 2^(kNumClasses-1-i)
-      const int cl = p3d::kNumClasses - 1 - i;
+    for (int i = 0; i < p3d::kNumClasses; ++i) {
       c->classes.net_begin[i] = (int32_t)k;
       c->classes.block_begin[i] = nb;
       size_t k1 = k;
-      while (k1 < order.size() && net_class(ns[order[k1] + 1] - ns[order[k1]]) == cl) ++k1;
-      const int per_block = p3d::kWaBlock >> cl;
+      while (k1 < order.size() && net_pos(ns[order[k1] + 1] - ns[order[k1]]) == i) ++k1;
+      const int per_block = p3d::kWaBlock >> pos_lanes_log2(i);
       nb += (int)((k1 - k + per_block - 1) / per_block);
       k = k1;
     }
@@ -246,7 +249,7 @@ int build_schedule(place3d_ctx* c, hipStream_t s) {
   {
     std::vector<int32_t> first(c->n_wa_blocks);
     for (int i = 0; i < p3d::kNumClasses; ++i) {
-      const int per_block = p3d::kWaBlock >> (p3d::kNumClasses - 1 - i);
+      const int per_block = p3d::kWaBlock >> pos_lanes_log2(i);
       for (int b = c->classes.block_begin[i]; b < c->classes.block_begin[i + 1]; ++b)
         first[b] = order[c->classes.net_begin[i] + (size_t)(b - c->classes.block_begin[i]) * per_block];
     }

@@ -17,7 +17,8 @@ constexpr int kMaxNz = 16;
 constexpr int kNumXcd = 8;              // accelerator dies; workgroups go to them round-robin
 constexpr int kWaBlock = 256;           // threads per wirelength block
 constexpr int kPinsPerLane = 4;         // net pins a wirelength lane keeps in registers
-constexpr int kNumClasses = 7;          // nets by lane group: 1, 2, 4, ..., 64 lanes
+constexpr int kNumGroups = 7;           // nets by lane group: 1, 2, 4, ..., 64 lanes
+constexpr int kNumClasses = kNumGroups + 1;   // the groups, then two-pin nets (one lane each)
 constexpr int kChunkEntries = 16384;    // (cell, tile) entries one tile workgroup takes at a time
 
 // Reduction slots (float64, device) inside the workspace.
@@ -29,7 +30,8 @@ enum RedSlot {
 };
 
 
-struct ClassTab {       // net schedule in layout order: position i holds groups of 2^(kNumClasses-1-i) lanes
+struct ClassTab {       // net schedule in layout order: position i < kNumGroups holds groups of
+                        // 2^(kNumGroups-1-i) lanes, the last position the two-pin nets
   int32_t net_begin[kNumClasses + 1];
   int32_t block_begin[kNumClasses + 1];
 };

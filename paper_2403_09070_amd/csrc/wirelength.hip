@@ -492,6 +492,54 @@ __device__ __forceinline__ NetTotals wl_group(int net, int lg, float half_dz, fl
   return t;
 }
 
+// tanh(x/2) for x >= 0: below x = 1/2 its Taylor series to the y^9 term (y = x/2; the first term
+// left out is under 1e-8 of the value there), else (1 - e^{-x}) / (1 + e^{-x}), which no longer
+// cancels badly
+__device__ __forceinline__ float tanh_half(float x) {
+  const float y = 0.5f * x, y2 = y * y;
+  const float ser = y * (1.f + y2 * (-1.f / 3.f + y2 * (2.f / 15.f + y2 * (-17.f / 315.f + y2 * (62.f / 2835.f)))));
+  const float e = __expf(-x);
+  return x < 0.5f ? ser : (1.f - e) * rcp(1.f + e);
+}
+
+// A two-pin net in closed form.  With D = u_p - u_q, a = |D| and x = a/gamma every exponential sum
+// above is 1 + e^{-x}, so the smoothed extent is W = a tanh(x/2) and dW/du_p = sign(D) (tanh(x/2) +
+// x (1 - tanh^2(x/2)) / 2) = -dW/du_q.  A crossing two-pin net has one pin per set, each set's
+// extent is 0, and W^ is the whole-net W, as for a net on one die; moving either pin to the other
+// die gives the exact extent |f - u_other| in both cases.
+struct PairAxis { float W, g; };
+__device__ __forceinline__ PairAxis pair_axis(float D, float ig) {
+  const float a = fabsf(D), x = a * ig, th = tanh_half(x);
+  const float g = th + 0.5f * x * (1.f - th * th);
+  return {a * th, D >= 0.f ? g : -g};
+}
+
+template <bool kGrad>
+__device__ __forceinline__ NetTotals wl_pair(int s, float half_dz, float four_over_dz, float ig, float alpha,
+                                             const float4* __restrict__ xyzp, const int32_t* __restrict__ pin_node,
+                                             const float4* __restrict__ off, const int32_t* __restrict__ slot_pos,
+                                             float4* __restrict__ pin_out) {
+  const float4 q0 = xyzp[pin_node[s]];
+  const PinRel p = load_pin(xyzp, pin_node, off, s, half_dz, q0.x, q0.y);
+  const PinRel q = load_pin(xyzp, pin_node, off, s + 1, half_dz, q0.x, q0.y);
+  const float dx = p.ux - q.ux, dy = p.uy - q.uy, dz = p.z - q.z;
+  const PairAxis ax = pair_axis(dx, ig), ay = pair_axis(dy, ig), az = pair_axis(dz, ig);
+  const float hx = fabsf(dx), hy = fabsf(dy);
+  if constexpr (kGrad) {
+    const float dwp = (fabsf(p.fx - q.ux) - hx) + (fabsf(p.fy - q.uy) - hy);
+    const float dwq = (fabsf(q.fx - p.ux) - hx) + (fabsf(q.fy - p.uy) - hy);
+    pin_out[slot_pos[s]] = make_float4(ax.g, ay.g, alpha * az.g, four_over_dz * (p.top ? -dwp : dwp));
+    pin_out[slot_pos[s + 1]] = make_float4(-ax.g, -ay.g, -(alpha * az.g), four_over_dz * (q.top ? -dwq : dwq));
+  }
+  NetTotals t;
+  t.wa_bi = ax.W + ay.W;
+  t.wa_z = alpha * az.W;
+  t.hpwl = hx + hy;
+  t.hpwl3d = (hx + hy) + alpha * fabsf(dz);
+  t.ncut = p.top != q.top ? 1.f : 0.f;
+  return t;
+}
+
 template <bool kGrad, bool C>
 __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     float half_dz, float four_over_dz, float gamma, float alpha, const float4* __restrict__ xyzp,
@@ -503,7 +551,7 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   const int blk = block_order[xcd_swizzle((int)blockIdx.x, (int)gridDim.x)];
   int pos = 0;                                     // layout position of this block's class
   while (pos + 1 < kNumClasses && blk >= tab.block_begin[pos + 1]) ++pos;
-  const int lg2 = kNumClasses - 1 - pos;           // log2 of the group width
+  const int lg2 = pos < kNumGroups ? kNumGroups - 1 - pos : 0;   // log2 of the group width
   const int net = tab.net_begin[pos] + (blk - tab.block_begin[pos]) * (kWaBlock >> lg2) + ((int)threadIdx.x >> lg2);
   const int lg = threadIdx.x & ((1 << lg2) - 1);
   const float ig = 1.f / gamma;
@@ -514,7 +562,9 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
   if (net < tab.net_begin[pos + 1]) {
 #define P3D_GROUP(G) \
   wl_group<G, kGrad, C>(net, lg, half_dz, four_over_dz, ig, big, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
-    switch (lg2) {
+    if (pos == kNumClasses - 1) {
+      t = wl_pair<kGrad>(s_net_start[net], half_dz, four_over_dz, ig, alpha, xyzp, pin_node, off, slot_pos, pin_out);
+    } else switch (lg2) {
       case 0: t = P3D_GROUP(1); break;
       case 1: t = P3D_GROUP(2); break;
       case 2: t = P3D_GROUP(4); break;
@@ -525,7 +575,8 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
     }
 #undef P3D_GROUP
   }
-  // net totals: float within the wavefront (at most 64 nets), float64 across wavefronts
+  // net totals: summed over the wavefront (at most 64 nets; in float64 when compensated), float64
+  // across wavefronts
   const float v[5] = {t.wa_bi, t.wa_z, t.hpwl, t.hpwl3d, t.ncut};
 #pragma unroll
   for (int q = 0; q < 5; ++q) {

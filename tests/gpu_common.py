@@ -129,6 +129,44 @@ def shared_pin_case(seed=14):
     return with_nets(case, nets, seed)
 
 
+def pair_case(seed=15):
+    """Two-pin nets only: random pairs of instances, pairs whose pins coincide (one position, zero
+    offsets), pairs closer than half the smoothing length gamma (on one die and across the dies),
+    pairs on one instance, and pairs of the two dies at one position."""
+    import dataclasses
+    case = tiny_case(seed)
+    rng = np.random.default_rng(seed)
+    n, gamma = case.n_inst, case.gamma
+    mov = np.nonzero((case.kind & 2) == 0)[0]
+    xyz = case.xyz0.astype(np.float64).copy()
+    dz = case.nz * 0.5 * (case.die_x / case.nx + case.die_y / case.ny)
+    nets = [rng.choice(n, size=2, replace=False) for _ in range(200)]
+    zero = []                                   # nets whose pin offsets are set to 0
+    pairs = rng.choice(mov, size=(4, 12, 2), replace=False)
+    for i, j in pairs[0]:                       # coincident pins
+        xyz[:, j] = xyz[:, i]
+        nets.append(np.array([i, j])); zero.append(len(nets) - 1)
+    for k, (i, j) in enumerate(pairs[1]):       # closer than gamma / 2, x or y or both
+        step = rng.uniform(0.02, 0.45, size=2) * gamma * np.array([k % 3 != 1, k % 3 != 0])
+        xyz[:2, j] = xyz[:2, i] + step
+        nets.append(np.array([i, j])); zero.append(len(nets) - 1)
+    for k, (i, j) in enumerate(pairs[2]):       # the same, across the dies
+        xyz[:2, j] = xyz[:2, i] + rng.uniform(0.02, 0.45, size=2) * gamma
+        xyz[2, i], xyz[2, j] = 0.25 * dz, 0.75 * dz
+        nets.append(np.array([i, j])); zero.append(len(nets) - 1)
+    for i, j in pairs[3]:                       # one position, the two dies
+        xyz[:2, j] = xyz[:2, i]
+        xyz[2, i], xyz[2, j] = 0.25 * dz, 0.75 * dz
+        nets.append(np.array([i, j]))
+    for i in rng.choice(mov, size=8, replace=False):   # both pins on one instance
+        nets.append(np.array([i, i]))
+    case = with_nets(dataclasses.replace(case, xyz0=xyz.astype(np.float32)), nets, seed)
+    off = case.pin_off.copy()
+    for e in zero:
+        off[:, case.net_start[e]:case.net_start[e + 1]] = 0.0
+    return dataclasses.replace(case, pin_off=off)
+
+
 def no_net_case(seed=10):
     """Instances and macros but an empty netlist."""
     return with_nets(tiny_case(seed), [], seed)

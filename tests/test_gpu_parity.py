@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from gpu_common import (filler_case, gpu_problem, log, need_gpu, no_net_case, one_die_case, oracle_problem,
-                        ragged_case, rel_l2, shared_pin_case, tiny_case, wide_net_case)
+                        pair_case, ragged_case, rel_l2, shared_pin_case, tiny_case, wide_net_case)
 from oracle import density as oden
 from oracle import density_grad as odg
 from oracle import poisson as opois
@@ -34,6 +34,7 @@ CASES = {
     "one_die": lambda: one_die_case(9),
     "no_nets": lambda: no_net_case(10),
     "shared_pins": lambda: shared_pin_case(14),
+    "pairs": lambda: pair_case(15),
     "fillers": lambda: filler_case(11),
     "c1": lambda: synth.make_case("c1", 2403),
     "c2": lambda: synth.make_case("c2", 2403),
