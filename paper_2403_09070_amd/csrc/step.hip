@@ -16,10 +16,14 @@
 namespace p3d {
 namespace {
 
-__device__ __forceinline__ void inst_wh(const Geom& g, const float* __restrict__ size, uint8_t kind, int i, float z,
-                                        float& w, float& h) {
-  const int n = g.n;
-  const float wbot = size[i], hbot = size[n + i], wtop = size[2 * n + i], htop = size[3 * n + i];
+// an instance's four sizes (bottom w, h, top w, h), loaded together
+struct Sizes { float wbot, hbot, wtop, htop; };
+__device__ __forceinline__ Sizes sizes_of(const float* __restrict__ size, int n, int i) {
+  return {size[i], size[n + i], size[2 * n + i], size[3 * n + i]};
+}
+
+__device__ __forceinline__ void inst_wh(const Geom& g, const Sizes& sz, uint8_t kind, float z, float& w, float& h) {
+  const float wbot = sz.wbot, hbot = sz.hbot, wtop = sz.wtop, htop = sz.htop;
   if (kind & PLACE3D_KIND_MACRO) {
     const float zc = fminf(fmaxf(z, 0.25f * g.dz), 0.75f * g.dz);
     const float t = 2.f * zc / g.dz;
@@ -31,26 +35,35 @@ __device__ __forceinline__ void inst_wh(const Geom& g, const float* __restrict__
     h = top ? htop : hbot;
   }
 }
+__device__ __forceinline__ void inst_wh(const Geom& g, const float* __restrict__ size, uint8_t kind, int i, float z,
+                                        float& w, float& h) {
+  inst_wh(g, sizes_of(size, g.n, i), kind, z, w, h);
+}
 
-__device__ __forceinline__ void clamp_point(const Geom& g, const float* __restrict__ size, uint8_t kind, int i,
-                                            float& x, float& y, float& z) {
+__device__ __forceinline__ void clamp_point(const Geom& g, const Sizes& sz, uint8_t kind, float& x, float& y,
+                                            float& z) {
   z = fminf(fmaxf(z, 0.25f * g.dz), 0.75f * g.dz);
   float w, h;
-  inst_wh(g, size, kind, i, z, w, h);
+  inst_wh(g, sz, kind, z, w, h);
   x = fminf(fmaxf(x, 0.5f * w), g.dx - 0.5f * w);
   y = fminf(fmaxf(y, 0.5f * h), g.dy - 0.5f * h);
 }
+__device__ __forceinline__ void clamp_point(const Geom& g, const float* __restrict__ size, uint8_t kind, int i,
+                                            float& x, float& y, float& z) {
+  clamp_point(g, sizes_of(size, g.n, i), kind, x, y, z);
+}
 
-__device__ __forceinline__ float precond(const Geom& g, const float* __restrict__ size, const float* __restrict__ npins,
-                                         uint8_t kind, int i, float z, double lam, int mode) {
+// np: the instance's pin count (read only where the form uses it)
+__device__ __forceinline__ float precond(const Geom& g, const Sizes& sz, float np, uint8_t kind, float z, double lam,
+                                         int mode) {
   float w, h;
-  inst_wh(g, size, kind, i, z, w, h);
+  inst_wh(g, sz, kind, z, w, h);
   const double lq = lam * (double)w * (double)h * (double)(0.5f * g.dz);
   double H;
   if (mode == PLACE3D_PRECOND_MIXED)
-    H = (kind & PLACE3D_KIND_MACRO) ? fmax(1.0, (double)npins[i] + lq) : fmax(1.0, lq);
+    H = (kind & PLACE3D_KIND_MACRO) ? fmax(1.0, (double)np + lq) : fmax(1.0, lq);
   else if (mode == PLACE3D_PRECOND_EPLACE)
-    H = (double)npins[i] + lq;
+    H = (double)np + lq;
   else
     H = lq;
   return (float)H;
@@ -115,23 +128,31 @@ struct CellShares {
   float scale;
 };
 
+// cls and packed: the instance's density class and packed tile range (loaded by the caller with
+// its other operands); a cell's up to four shares are loaded together and summed in q order
 __device__ __forceinline__ void density_grad_of(const CellShares& cs, const float* __restrict__ gd, int n, int i,
-                                                float (&d)[3]) {
-  if (!cs.entry) {
-    for (int a = 0; a < 3; ++a) d[a] = gd[a * n + i];
-    return;
-  }
-  const uint8_t c = cs.cls[i];
-  if (c == kClsLarge) {
+                                                uint8_t cls, int packed, float (&d)[3]) {
+  if (!cs.entry || cls == kClsLarge) {
     for (int a = 0; a < 3; ++a) d[a] = gd[a * n + i];
     return;
   }
   float sx = 0.f, sy = 0.f, sz = 0.f;
-  if (c == kClsCell) {
+  if (cls == kClsCell) {
     // the cell's entry count from its packed tile range; its shares are cell-major [q][n]
-    const int packed = cs.cell_entry[i];
+    // (a bucketed cell has 1, 2 or 4 entries: its tile range is 1 or 2 tiles per axis)
     const int cnt = packed < 0 ? 0 : (1 + ((packed >> 24) & 1)) * (1 + ((packed >> 25) & 1));
-    for (int q = 0; q < cnt; ++q) { const float4 v = cs.entry[(size_t)q * n + i]; sx += v.x; sy += v.y; sz += v.z; }
+    // All four loads are issued together: an absent share's load re-reads share 0 (the same
+    // cache line) and counts as zero, which leaves the sum in q order unchanged.
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const size_t i1 = cnt > 1 ? (size_t)n + i : (size_t)i;
+    const size_t i2 = cnt > 2 ? 2 * (size_t)n + i : (size_t)i, i3 = cnt > 2 ? 3 * (size_t)n + i : (size_t)i;
+    const float4 r0 = cs.entry[i], r1 = cs.entry[i1], r2 = cs.entry[i2], r3 = cs.entry[i3];
+    const float4 v0 = r0, v1 = cnt > 1 ? r1 : z4, v2 = cnt > 2 ? r2 : z4, v3 = cnt > 2 ? r3 : z4;
+    if (cnt > 0) {
+      sx = ((v0.x + v1.x) + v2.x) + v3.x;
+      sy = ((v0.y + v1.y) + v2.y) + v3.y;
+      sz = ((v0.z + v1.z) + v2.z) + v3.z;
+    }
     sx *= cs.scale; sy *= cs.scale; sz *= cs.scale;
   }
   d[0] = sx; d[1] = sy; d[2] = sz;
@@ -147,25 +168,44 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
   const double lam = lam_ptr[lam_slot];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < n) {
+    // the instance's operands are all loaded before any is used (one round of loads in flight,
+    // then the cell's shares), whatever its kind
     const uint8_t k = kind[i];
+    const Sizes sz = sizes_of(size, n, i);
+    float wv[3], vv[3], vp[3] = {0.f, 0.f, 0.f}, go[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      wv[a] = gw[a * n + i];
+      vv[a] = v[a * n + i];
+    }
+    if (mode == 1) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        vp[a] = v_prev[a * n + i];
+        go[a] = gout[a * n + i];
+      }
+    }
+    const uint8_t dcls = cs.entry ? cs.cls[i] : kClsLarge;
+    const int packed = cs.entry ? cs.cell_entry[i] : -1;
     float gv[3] = {0.f, 0.f, 0.f};
-    const float z = v[2 * n + i];
+    const float z = vv[2];
     if (!(k & PLACE3D_KIND_FIXED)) {
-      const float H = precond(g, size, npins, k, i, z, lam, mode_pre);
+      const bool need_np = mode_pre == PLACE3D_PRECOND_EPLACE || (mode_pre == PLACE3D_PRECOND_MIXED && (k & PLACE3D_KIND_MACRO));
+      const float H = precond(g, sz, need_np ? npins[i] : 0.f, k, z, lam, mode_pre);
       float d[3];
-      density_grad_of(cs, gd, n, i, d);
+      density_grad_of(cs, gd, n, i, dcls, packed, d);
       for (int a = 0; a < 3; ++a)
-        gv[a] = (float)(((double)gw[a * n + i] + lam * (double)d[a]) / (double)H);
+        gv[a] = (float)(((double)wv[a] + lam * (double)d[a]) / (double)H);
       if (k & PLACE3D_KIND_ZFIXED) gv[2] = 0.f;               // z held (z-fixed fillers)
       if (mode == 1) {
         for (int a = 0; a < 3; ++a) {
-          const double dv = (double)v[a * n + i] - (double)v_prev[a * n + i];
-          const double dg = (double)gv[a] - (double)gout[a * n + i];
+          const double dv = (double)vv[a] - (double)vp[a];
+          const double dg = (double)gv[a] - (double)go[a];
           acc[0] += dv * dv;
           acc[1] += dg * dg;
         }
         float w, h;
-        inst_wh(g, size, k, i, z, w, h);
+        inst_wh(g, sz, k, z, w, h);
         const double q = (k & PLACE3D_KIND_FILLER) ? 0.0 : (double)w * (double)h * (double)(0.5f * g.dz);
         if (z > g.half_dz) acc[3] += q; else acc[2] += q;
       } else {
@@ -230,13 +270,20 @@ __global__ void k_nesterov(Geom g, const float* __restrict__ size, const uint8_t
   const double a1 = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
   const float coef = (float)((a - 1.0) / a1);
   const float st = (float)step;
+  // every operand loaded before any is used
+  const uint8_t kd = kind[i];
   const float vx = v[i], vy = v[n + i], vz = v[2 * n + i];
+  const float gx = gk[i], gy = gk[n + i], gz = gk[2 * n + i];
+  const float ox = u[i], oy = u[n + i], oz = u[2 * n + i];
+  const Sizes sz = sizes_of(size, n, i);
+  // the move is computed for every instance (a fixed one's is not stored), so that no load waits
+  // behind the branch
+  float ux = vx - st * gx, uy = vy - st * gy, uz = vz - st * gz;
+  clamp_point(g, sz, kd, ux, uy, uz);
+  float nx = ux + coef * (ux - ox), ny = uy + coef * (uy - oy), nz = uz + coef * (uz - oz);
+  clamp_point(g, sz, kd, nx, ny, nz);
   v_prev[i] = vx; v_prev[n + i] = vy; v_prev[2 * n + i] = vz;
-  if (kind[i] & PLACE3D_KIND_FIXED) return;
-  float ux = vx - st * gk[i], uy = vy - st * gk[n + i], uz = vz - st * gk[2 * n + i];
-  clamp_point(g, size, kind[i], i, ux, uy, uz);
-  float nx = ux + coef * (ux - u[i]), ny = uy + coef * (uy - u[n + i]), nz = uz + coef * (uz - u[2 * n + i]);
-  clamp_point(g, size, kind[i], i, nx, ny, nz);
+  if (kd & PLACE3D_KIND_FIXED) return;
   u[i] = ux; u[n + i] = uy; u[2 * n + i] = uz;
   v[i] = nx; v[n + i] = ny; v[2 * n + i] = nz;
 }

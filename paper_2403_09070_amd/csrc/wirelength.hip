@@ -613,12 +613,18 @@ __global__ void k_wl_gather(int n, int nlight, const int32_t* __restrict__ heavy
   if ((int)blockIdx.x < nlight) {
     i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
+      // the kind with the slot range, and the shares four at a time, so that loads overlap
       const int q0 = node_slot_start[i], q1 = node_slot_start[i + 1];
+      const uint8_t kd = kind[i];
       writer = q1 - q0 <= kHeavyPins;
-      if (writer && !(kind[i] & PLACE3D_KIND_FIXED))
-        for (int q = q0; q < q1; ++q) {
-          const float4 v = pin_out[q];
-          gx += v.x; gy += v.y; gz += v.z; gf += v.w;
+      if (writer & !(kd & PLACE3D_KIND_FIXED))
+        for (int q = q0; q < q1; q += 4) {
+          float4 v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = q + u < q1 ? pin_out[q + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (q + u < q1) { gx += v[u].x; gy += v[u].y; gz += v[u].z; gf += v[u].w; }
         }
     }
   } else {
