@@ -563,7 +563,11 @@ __global__ __launch_bounds__(kWaBlock) void k_wl_nets(
 #define P3D_GROUP(G) \
   wl_group<G, kGrad, C>(net, lg, half_dz, four_over_dz, ig, big, alpha, xyzp, s_net_start, pin_node, off, slot_pos, pin_out)
     if (pos == kNumClasses - 1) {
-      t = wl_pair<kGrad>(s_net_start[net], half_dz, four_over_dz, ig, alpha, xyzp, pin_node, off, slot_pos, pin_out);
+      // the class's slots are consecutive, two per net: the first pin's slot follows from the
+      // class's first slot (one uniform load) without a per-net load
+      const int c0 = tab.net_begin[pos];
+      const int s = __builtin_amdgcn_readfirstlane(s_net_start[c0]) + 2 * (net - c0);
+      t = wl_pair<kGrad>(s, half_dz, four_over_dz, ig, alpha, xyzp, pin_node, off, slot_pos, pin_out);
     } else switch (lg2) {
       case 0: t = P3D_GROUP(1); break;
       case 1: t = P3D_GROUP(2); break;
