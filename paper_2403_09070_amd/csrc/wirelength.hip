@@ -133,25 +133,16 @@ __device__ __forceinline__ void ext_merge(Ext2& e) {
 }
 
 // A float32 sum, compensated when C (the rounding error of every addition is kept in c and added
-// back at the end), plain otherwise.  add: Neumaier's variant of Kahan summation, for terms of
-// any size.  add_small: for a term no larger in magnitude than the running sum, whose rounding
-// error is then x - (t - s) exactly (Dekker's Fast2Sum) at half the cost; a lane's exponential
-// sums use it by starting from an offset of their terms' sign at least as large as any term (so
-// the running sum never falls below a term) and taking the offset off, exactly, before they are
-// merged or read.  merge<M> adds the partner lane's sum; it is commutative, so both partners of a
-// butterfly hold the same sum.
+// back at the end), plain otherwise.  add_small: for a term no larger in magnitude than the
+// running sum, whose rounding error is then x - (t - s) exactly (Dekker's Fast2Sum); a lane's
+// exponential sums use it by starting from an offset of their terms' sign at least as large as
+// any term (so the running sum never falls below a term) and taking the offset off, exactly,
+// before they are merged or read.  merge<M> adds the partner lane's sum with Neumaier's variant
+// of Kahan summation (terms of any size); it is commutative, so both partners of a butterfly hold
+// the same sum.
 template <bool C>
 struct Acc {
   float s, c;
-  __device__ __forceinline__ void add(float x) {
-    if constexpr (C) {
-      const float t = s + x;
-      c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
-      s = t;
-    } else {
-      s += x;
-    }
-  }
   __device__ __forceinline__ void add_small(float x) {
     if constexpr (C) {
       const float t = s + x;
