@@ -30,6 +30,9 @@ CASES = {
     "ragged": lambda: ragged_case(6),
     "ragged_even": lambda: ragged_case(7, nx=38, ny=30),
     "multi_tile": lambda: ragged_case(13, nx=280, ny=264, nz=4),
+    # more than four layers: 16 x 16 bin tiles, and the float32 contractions in both forms
+    "layers6": lambda: ragged_case(16, nx=40, ny=34, nz=6),
+    "layers16": lambda: ragged_case(17, nx=24, ny=20, nz=16),
     "wide_nets": lambda: wide_net_case(8),
     "one_die": lambda: one_die_case(9),
     "no_nets": lambda: no_net_case(10),

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import gpu_problem, log, need_gpu, oracle_problem, rel_l2, tiny_case
+from gpu_common import gpu_problem, log, need_gpu, oracle_problem, ragged_case, rel_l2, tiny_case
 from oracle import optimizer as opt
 from paper_2403_09070_amd import place3d, synth
 
@@ -239,3 +239,35 @@ def test_nonfinite_iteration_is_flagged_and_reported():
         prob.read_scalars(st)
     assert e.value.code == -4 and "iteration 1" in str(e.value)
     assert torch.isfinite(st.v).all()
+
+
+@pytest.mark.parametrize("form", ["field-bf16x3", "adjoint-bf16x3"])
+def test_init_and_one_step_with_eight_layers(form):
+    """Eight layers (16 x 16 bin tiles, float32 contractions in the split form, four layers per
+    die in the overflow): gp_init and one step from the oracle's state three steps on, to the bars
+    of the two-layer-per-die tests."""
+    need_gpu()
+    log(f"[step] eight layers {form}")
+    case = ragged_case(18, nx=48, ny=40, nz=8)
+    prob = gpu_problem(case, **FORMS[form])
+    pb = oracle_problem(case)
+    st = prob.gp_init(case.xyz0)
+    ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form), precond=_oracle_precond(form))
+    s = st.read()
+    assert abs(s["lam"] - ref.lam) <= 1e-5 * ref.lam
+    assert rel_l2(st.g_prev.cpu().numpy(), ref.g_prev) <= 1e-4
+    for _ in range(3):
+        opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
+    ref = _round_state(ref)
+    st = _load_state(prob, ref)
+    v0 = ref.v.copy()
+    prob.step(st)
+    m = opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
+    s = st.read()
+    for key, rkey in (("hpwl", "hpwl_d2d"), ("wa_bi", "wa_bi"), ("wa_z", "wa_z")):
+        assert abs(s[key] - m[rkey]) <= 1e-5 * abs(m[rkey]), key
+    assert abs(s["ovfl_bot"] - m["ovfl_bot"]) <= 1e-6 and abs(s["ovfl_top"] - m["ovfl_top"]) <= 1e-6
+    step_err = abs(s["step"] - m["step"]) / m["step"]
+    disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
+    log(f"[step] eight layers {form} step rel={step_err:.3e} displacement rel_l2={disp:.3e}")
+    assert step_err <= STEP_BAR and disp <= DISP_BAR[form]
