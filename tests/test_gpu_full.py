@@ -2,8 +2,9 @@
 form the benchmark times -- split-bf16 and float32 contractions, compensated and plain
 exponential sums, field-gather and exact-adjoint density gradients -- launched exactly as
 place3d_step launches them (folded contractions, the net schedule and the tile bucketing of that
-size).  Every output is compared in full against the oracle on the same seeded inputs, with the
-tolerances of the small-case parity tests:
+size); and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
+density map and the wirelength sweep.  Every output is compared in full against the oracle on the
+same seeded inputs, with the tolerances of the small-case parity tests:
   density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
   many overlapping cells), field rel L2 <= 1e-4, wirelength totals rel <= 1e-5, WA x/y gradient
   rel L2 <= 1e-5, FDA z-gradient within (4/d_z) npins 8 ulp(d_x) per instance, field gather and
@@ -162,3 +163,50 @@ def test_density_many_bucket_blocks(where):
     log(f"[full] density, {case.n_inst} instances, {where}: rel_l2={err:.3e} max bin {ref.max():.2f}")
     assert err <= 1e-6
     assert abs(got.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
+
+
+def test_largest_workload_density_and_wirelength():
+    """The largest workload (4M cells, 200 macros up to 5 % of the die, 4.4M nets of up to 100
+    pins, 15M pins, grid 2048 x 2048 x 4) at the clustered start its run to overflow takes (x, y
+    normal around the centre with sigma 0.02 of the die: most cells in a few dozen of the 4096
+    tiles, which are split into many chunks): the density map and its total volume, and the
+    precision form's wirelength sweep (totals, x/y gradient, FDA z-gradient), against the oracle
+    with the bars above."""
+    need_gpu()
+    from paper_2403_09070_amd import place3d
+    log("[full] generating the 4M-cell workload")
+    case = synth.centre_start(synth.make_case("c5", 2403), sigma=0.02, seed=2404)
+    geo = geometry_of(case)
+    prob = gpu_problem(case, precision=place3d.BF16X3, dgrad=place3d.DGRAD_FIELD)
+    log("[full] 4M: oracle density map")
+    ref = oden.density_map(case.size, case.kind, case.xyz0, geo)
+    got = prob.density(case.xyz0).cpu().numpy()
+    err = rel_l2(got, ref)
+    log(f"[full] 4M density rel_l2={err:.3e} max bin {ref.max():.2f}")
+    assert err <= 1e-6
+    assert abs(got.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
+    pb = oracle_problem(case)
+    log("[full] 4M: oracle wirelength")
+    with np.errstate(over="ignore"):        # exponentials of padded slots, masked out
+        wl = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma,
+                            pb.alpha)
+    g, met = prob.wl_grad(case.xyz0)
+    g = g.cpu().numpy()
+    met = met.cpu().numpy()
+    for key, slot in (("wa_bi", 0), ("wa_z", 1), ("hpwl_d2d", 2), ("hpwl_3d", 3)):
+        e = abs(met[slot] - wl[key]) / abs(wl[key])
+        log(f"[full] 4M {key} gpu={met[slot]:.10g} ref={wl[key]:.10g} rel={e:.2e}")
+        assert e <= 1e-5, key
+    assert int(round(met[4])) == wl["ncut"]
+    ex, ey = rel_l2(g[0], wl["grad_x"]), rel_l2(g[1], wl["grad_y"])
+    log(f"[full] 4M wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
+    assert ex <= 1e-5 and ey <= 1e-5
+    scale = met[8]
+    assert abs(scale - wl["fda_scale"]) <= 1e-5 * wl["fda_scale"]
+    ulp = float(np.spacing(np.float32(geo.die_x)))
+    npins = np.bincount(case.pin2node, minlength=case.n_inst)
+    want = scale * wl["fda"] + wl["grad_zwa"]
+    bound = scale * 4.0 / geo.dz * npins * 8 * ulp + 1e-5 * np.abs(wl["grad_zwa"]).max() + 1e-6 * np.abs(want)
+    diff = np.abs(g[2] - want)
+    log(f"[full] 4M z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e}")
+    assert np.all(diff <= bound)
