@@ -3,7 +3,7 @@ form the benchmark times -- split-bf16 and float32 contractions, compensated and
 exponential sums, field-gather and exact-adjoint density gradients -- launched exactly as
 place3d_step launches them (folded contractions, the net schedule and the tile bucketing of that
 size); and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
-density map and the wirelength sweep.  Every output is compared in full against the oracle on the
+density map, the split-bf16 spectral solve and the wirelength sweep.  Every output is compared in full against the oracle on the
 same seeded inputs, with the tolerances of the small-case parity tests:
   density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
   many overlapping cells), field rel L2 <= 1e-4, wirelength totals rel <= 1e-5, WA x/y gradient
@@ -169,9 +169,9 @@ def test_largest_workload_density_and_wirelength():
     """The largest workload (4M cells, 200 macros up to 5 % of the die, 4.4M nets of up to 100
     pins, 15M pins, grid 2048 x 2048 x 4) at the clustered start its run to overflow takes (x, y
     normal around the centre with sigma 0.02 of the die: most cells in a few dozen of the 4096
-    tiles, which are split into many chunks): the density map and its total volume, and the
-    precision form's wirelength sweep (totals, x/y gradient, FDA z-gradient), against the oracle
-    with the bars above."""
+    tiles, which are split into many chunks): the density map and its total volume, the split-bf16
+    spectral solve of that map, and the precision form's wirelength sweep (totals, x/y gradient,
+    FDA z-gradient), against the oracle with the bars above."""
     need_gpu()
     from paper_2403_09070_amd import place3d
     log("[full] generating the 4M-cell workload")
@@ -185,6 +185,20 @@ def test_largest_workload_density_and_wirelength():
     log(f"[full] 4M density rel_l2={err:.3e} max bin {ref.max():.2f}")
     assert err <= 1e-6
     assert abs(got.astype(np.float64).sum() - ref.sum()) <= 1e-6 * ref.sum()
+    # the split-bf16 solve of the oracle's map (rounded to float32 on both sides); the split form's
+    # E components against |(Ex, Ey, Ez)|, as in the small cases
+    import torch
+    rho32 = ref.astype(np.float32)
+    log("[full] 4M: oracle spectral solve")
+    sol = opois.solve(rho32.astype(np.float64), geo)
+    out = prob.field(torch.from_numpy(rho32).cuda())
+    enorm = float(np.sqrt(sum(np.linalg.norm(sol[k]) ** 2 for k in ("ex", "ey", "ez"))))
+    for k in ("phi", "ex", "ey", "ez"):
+        got_k = out[k].cpu().numpy().astype(np.float64)
+        e = rel_l2(got_k, sol[k]) if k == "phi" else float(np.linalg.norm(got_k - sol[k]) / enorm)
+        log(f"[full] 4M bf16x3 {k} rel_l2={e:.3e}")
+        assert e <= 1e-4, k
+    del sol, out
     pb = oracle_problem(case)
     log("[full] 4M: oracle wirelength")
     with np.errstate(over="ignore"):        # exponentials of padded slots, masked out
