@@ -25,7 +25,7 @@ constexpr int kChunkEntries = 16384;    // (cell, tile) entries one tile workgro
 enum RedSlot {
   R_WA_BI = 0, R_WA_Z, R_HPWL, R_HPWL3D, R_NCUT, R_NORM_X, R_NORM_Y, R_NORM_FDA,
   R_DV2, R_DG2, R_Q_BOT, R_Q_TOP, R_EXCESS_BOT, R_EXCESS_TOP, R_ENERGY,
-  R_L1_WL, R_L1_DEN, R_GMAX, R_NONFINITE,
+  R_L1_WL, R_L1_DEN, R_GMAX, R_NONFINITE, R_A_PREV,
   R_COUNT = 32
 };
 

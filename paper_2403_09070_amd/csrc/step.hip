@@ -162,10 +162,14 @@ __global__ void k_combine(Geom g, const float* __restrict__ size, const uint8_t*
                           const float* __restrict__ npins, const float* __restrict__ v,
                           const float* __restrict__ v_prev, const float* __restrict__ gw,
                           const float* __restrict__ gd, CellShares cs, const double* __restrict__ lam_ptr, int lam_slot,
-                          int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ part, int stride) {
+                          int mode_pre, int mode, float* __restrict__ gout, double* __restrict__ part, int stride,
+                          const double* __restrict__ a_src, double* __restrict__ a_copy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
   const double lam = lam_ptr[lam_slot];
+  // the step's Nesterov coefficient a_k, copied where the move reads it, so that the move can
+  // update the scalars while its other workgroups still run
+  if (a_copy && i == 0) *a_copy = *a_src;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < n) {
     // the instance's operands are all loaded before any is used (one round of loads in flight,
@@ -257,16 +261,42 @@ __global__ void k_init_scalars(double* __restrict__ sc, const double* __restrict
     sc[PLACE3D_S_NONFINITE] = 1.0;
 }
 
+// The step's scalars: step size, a_{k+1}, lambda ramp, iteration, overflow, energy, wirelength
+// metrics and the non-finite flag, from the reductions (all complete before the move starts) and
+// a = a_k.  Run by one thread of the move.
+__device__ void finish_scalars(double* __restrict__ sc, const double* __restrict__ red, double ramp, double a) {
+  const double dv2 = red[R_DV2], dg2 = red[R_DG2];
+  sc[PLACE3D_S_STEP] = dg2 > 0.0 ? sqrt(dv2 / dg2) : 0.0;
+  sc[PLACE3D_S_A] = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
+  sc[PLACE3D_S_LAMBDA] *= ramp;
+  sc[PLACE3D_S_ITER] += 1.0;
+  sc[PLACE3D_S_OVFL_BOT] = red[R_Q_BOT] > 0.0 ? red[R_EXCESS_BOT] / red[R_Q_BOT] : 0.0;
+  sc[PLACE3D_S_OVFL_TOP] = red[R_Q_TOP] > 0.0 ? red[R_EXCESS_TOP] / red[R_Q_TOP] : 0.0;
+  sc[PLACE3D_S_ENERGY] = red[R_ENERGY];
+  for (int q = 0; q <= PLACE3D_M_NORM_FDA; ++q) sc[PLACE3D_S_WL + q] = red[R_WA_BI + q];
+  const double nf = red[R_NORM_FDA];
+  sc[PLACE3D_S_WL + PLACE3D_M_FDA_SCALE] = nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
+  // the step's float64 reductions: any NaN or infinity in a position, a gradient or a map shows in
+  // one of them; the first iteration that saw one is kept (1 + its index)
+  bool finite = isfinite(dv2) && isfinite(dg2) && isfinite(sc[PLACE3D_S_LAMBDA]) && isfinite(red[R_EXCESS_BOT]) &&
+                isfinite(red[R_EXCESS_TOP]) && isfinite(red[R_ENERGY]);
+  for (int q = R_WA_BI; q <= R_NORM_FDA; ++q) finite = finite && isfinite(red[q]);
+  if (!finite && sc[PLACE3D_S_NONFINITE] == 0.0) sc[PLACE3D_S_NONFINITE] = sc[PLACE3D_S_ITER];
+}
+
 // the Nesterov move; g (the new preconditioned gradient) sits in g_prev
 __global__ void k_nesterov(Geom g, const float* __restrict__ size, const uint8_t* __restrict__ kind,
-                           const double* __restrict__ sc, const double* __restrict__ red, float* __restrict__ u,
-                           float* __restrict__ v, float* __restrict__ v_prev, const float* __restrict__ gk) {
+                           double* __restrict__ sc, const double* __restrict__ red, double ramp,
+                           float* __restrict__ u, float* __restrict__ v, float* __restrict__ v_prev,
+                           const float* __restrict__ gk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // a_k from the combine's copy: thread 0 writes a_{k+1} (and the other scalars) meanwhile
+  const double a = red[R_A_PREV];
+  if (i == 0) finish_scalars(sc, red, ramp, a);
   if (i >= g.n) return;
   const int n = g.n;
   const double dv2 = red[R_DV2], dg2 = red[R_DG2];
   const double step = dg2 > 0.0 ? sqrt(dv2 / dg2) : 0.0;
-  const double a = sc[PLACE3D_S_A];
   const double a1 = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
   const float coef = (float)((a - 1.0) / a1);
   const float st = (float)step;
@@ -288,27 +318,6 @@ __global__ void k_nesterov(Geom g, const float* __restrict__ size, const uint8_t
   v[i] = nx; v[n + i] = ny; v[2 * n + i] = nz;
 }
 
-__global__ void k_step_finish(double* __restrict__ sc, const double* __restrict__ red, double ramp) {
-  if (threadIdx.x != 0) return;
-  const double dv2 = red[R_DV2], dg2 = red[R_DG2];
-  const double a = sc[PLACE3D_S_A];
-  sc[PLACE3D_S_STEP] = dg2 > 0.0 ? sqrt(dv2 / dg2) : 0.0;
-  sc[PLACE3D_S_A] = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
-  sc[PLACE3D_S_LAMBDA] *= ramp;
-  sc[PLACE3D_S_ITER] += 1.0;
-  sc[PLACE3D_S_OVFL_BOT] = red[R_Q_BOT] > 0.0 ? red[R_EXCESS_BOT] / red[R_Q_BOT] : 0.0;
-  sc[PLACE3D_S_OVFL_TOP] = red[R_Q_TOP] > 0.0 ? red[R_EXCESS_TOP] / red[R_Q_TOP] : 0.0;
-  sc[PLACE3D_S_ENERGY] = red[R_ENERGY];
-  for (int q = 0; q <= PLACE3D_M_NORM_FDA; ++q) sc[PLACE3D_S_WL + q] = red[R_WA_BI + q];
-  const double nf = red[R_NORM_FDA];
-  sc[PLACE3D_S_WL + PLACE3D_M_FDA_SCALE] = nf > 0.0 ? (red[R_NORM_X] + red[R_NORM_Y]) / (2.0 * nf) : 0.0;
-  // the step's float64 reductions: any NaN or infinity in a position, a gradient or a map shows in
-  // one of them; the first iteration that saw one is kept (1 + its index)
-  bool finite = isfinite(dv2) && isfinite(dg2) && isfinite(sc[PLACE3D_S_LAMBDA]) && isfinite(red[R_EXCESS_BOT]) &&
-                isfinite(red[R_EXCESS_TOP]) && isfinite(red[R_ENERGY]);
-  for (int q = R_WA_BI; q <= R_NORM_FDA; ++q) finite = finite && isfinite(red[q]);
-  if (!finite && sc[PLACE3D_S_NONFINITE] == 0.0) sc[PLACE3D_S_NONFINITE] = sc[PLACE3D_S_ITER];
-}
 
 // wirelength and density gradients at xyz into gw and gd (both [3][n]); reductions into red.
 // The cells are bucketed once and the buckets serve the density map and its gradient.
@@ -390,7 +399,7 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
                      c->gw, c->den_grad, CellShares{}, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
-                     c->part, c->part_stride);
+                     c->part, c->part_stride, nullptr, nullptr);
     P3D_LAUNCH(c, "k_combine(init)");
   }
   if ((rc = reduce_final(c, R_GMAX, 1, (int)nb, true, c->red2 + R_GMAX, s))) return rc;
@@ -406,7 +415,7 @@ extern "C" int32_t place3d_gp_init(place3d_ctx* c, place3d_state* st, const floa
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v_prev, st->v_prev,
                      c->gw, c->den_grad, CellShares{}, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 0, st->g_prev,
-                     c->part, c->part_stride);
+                     c->part, c->part_stride, nullptr, nullptr);
     P3D_LAUNCH(c, "k_combine(init2)");
   }
   return PLACE3D_OK;
@@ -426,7 +435,7 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
     const CellShares cs{c->cls, c->cell_entry, c->entry_out, c->cell_scale};
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, c->npins, st->v, st->v_prev,
                      c->gw, c->den_grad, cs, st->scalars, (int)PLACE3D_S_LAMBDA, p.precond, 1, st->g_prev,
-                     c->part, c->part_stride);
+                     c->part, c->part_stride, st->scalars + PLACE3D_S_A, c->red + R_A_PREV);
     P3D_LAUNCH(c, "k_combine");
   }
   // the step's partials and the density pass's overflow partials, in one launch
@@ -434,15 +443,11 @@ extern "C" int32_t place3d_step(place3d_ctx* c, place3d_state* st, void* stream)
                           s)))
     return rc;
   {
+    // the move, and the step's scalars from its first thread
     ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
-    hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, st->u, st->v,
-                     st->v_prev, st->g_prev);
+    hipLaunchKernelGGL(k_nesterov, dim3(nb), dim3(256), 0, s, g, p.size, p.kind, st->scalars, c->red, p.lambda_ramp,
+                     st->u, st->v, st->v_prev, st->g_prev);
     P3D_LAUNCH(c, "k_nesterov");
-  }
-  {
-    ProfScope prof_(c, PLACE3D_STAGE_UPDATE, s);
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64), 0, s, st->scalars, c->red, p.lambda_ramp);
-    P3D_LAUNCH(c, "k_step_finish");
   }
   return PLACE3D_OK;
 }
