@@ -71,7 +71,7 @@ typedef enum place3d_status {
   PLACE3D_ERR_SIZE = -2,        /* sizes out of range or inconsistent (grid, CSR, workspace) */
   PLACE3D_ERR_HIP = -3,         /* a HIP runtime call failed; the HIP code is in last_error  */
   PLACE3D_ERR_NONFINITE = -4,   /* place3d_read_scalars: a GP iteration met a NaN or infinity  */
-  PLACE3D_ERR_UNSUPPORTED = -5, /* valid request this build does not implement               */
+  PLACE3D_ERR_UNSUPPORTED = -5, /* valid request the library does not implement             */
   PLACE3D_ERR_NETLIST = -6      /* CSR not monotone, pin owner out of range, or a filler
                                    with a pin                                                */
 } place3d_status;
