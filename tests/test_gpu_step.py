@@ -271,3 +271,36 @@ def test_init_and_one_step_with_eight_layers(form):
     disp = rel_l2(st.v.cpu().numpy() - v0, ref.v - v0)
     log(f"[step] eight layers {form} step rel={step_err:.3e} displacement rel_l2={disp:.3e}")
     assert step_err <= STEP_BAR and disp <= DISP_BAR[form]
+
+
+def test_captured_step_replays_match_eager_steps():
+    """place3d_step under stream capture (it allocates, fills and synchronises nothing; its side
+    stream forks from and joins the captured stream): one captured step replayed five times, with
+    eager steps, an eager density call and host synchronisations between the replays, gives the
+    eager steps' iterates and scalars bit for bit after every replay."""
+    need_gpu()
+    log("[step] captured step, c1")
+    case = synth.make_case("c1", 2403)
+    prob = gpu_problem(case, precision=place3d.BF16X3)
+    work = torch.cuda.Stream()
+    with torch.cuda.stream(work):
+        sa = prob.gp_init(case.xyz0)
+        sb = prob.new_state()
+        for k in ("u", "v", "v_prev", "g_prev", "scalars"):
+            getattr(sb, k).copy_(getattr(sa, k))
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(work)
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                prob.step(sb)
+        torch.cuda.synchronize()
+        for r in range(5):
+            prob.step(sa)
+            graph.replay()
+            prob.density(case.xyz0)
+            torch.cuda.synchronize()
+            for k in ("u", "v", "v_prev", "g_prev", "scalars"):
+                assert torch.equal(getattr(sa, k), getattr(sb, k)), (r, k)
+    log(f"[step] captured step: 5 replays equal to the eager steps, hpwl {sb.read()['hpwl']:.6g}")
