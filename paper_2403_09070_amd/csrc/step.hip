@@ -330,12 +330,17 @@ int eval_parts(place3d_ctx* c, const float* xyz, float* gw, float* gd, double* r
   // for the scalars, stays as gp_init zeroed it in the field-gather form)
   if ((rc = bucket_cells(c, xyz, s, 1))) return rc;  // the count pass packs xyz for the wirelength sweep
   // fork: the wirelength sweep (its own reduction slots, pin and instance scratch) runs on the
-  // side stream while the bucketing, density, spectral and gather chain runs on s; joined below
+  // side stream while the bucketing, density, spectral and gather chain runs on s; joined below.
+  // With the float32 contractions (2.6 times as long as the split ones) the sweep forks after
+  // the scatter pass, which then runs alone, and overlaps the contractions; with the split ones
+  // it forks right after the count pass, so that it is mostly done before they start.
+  const bool fork_after_scatter = !c->sc.on;
+  if (fork_after_scatter && (rc = bucket_cells(c, xyz, s, 2))) return rc;
   P3D_HIP(c, hipEventRecord(c->ev_fork, s));
   P3D_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
   if ((rc = wirelength_eval(c, xyz, gw, 0, red, nullptr, c->side, true))) return rc;
   P3D_HIP(c, hipEventRecord(c->ev_join, c->side));
-  if ((rc = bucket_cells(c, xyz, s, 2))) return rc;
+  if (!fork_after_scatter && (rc = bucket_cells(c, xyz, s, 2))) return rc;
   if ((rc = density_tiles(c, xyz, c->rho, red, s, !defer_excess))) return rc;
   if (c->prob.dgrad == PLACE3D_DGRAD_FIELD) {
     // the float32 form's field stays x-folded for the gather, which unfolds it while staging its
