@@ -18,7 +18,9 @@ Modules
     wirelength   WA model, bistratal wirelength, vanilla FDA z-gradient      (Sec. III-A, IV-B)
     optimizer    mixed-size preconditioner, Nesterov step, clamp, metrics, GP loop
 
-Parity status: the Nesterov optimiser (the paper does not describe it) and the field-gather
-gradient (not the derivative of any discrete objective) are "parity unpinned": beyond the
-properties their tests check, they are pinned only by GPU-vs-oracle parity of the same formula.
+Parity status: the Nesterov optimiser (the paper does not describe it) is "parity unpinned":
+beyond the quadratic cases its tests solve in closed form, it is pinned only by GPU-vs-oracle
+parity of the same formula.  The field-gather gradient (not the derivative of any discrete
+objective) is pinned by closed forms: a uniform field, and cells centred in a bin whose overlaps
+are written out by hand.
 """

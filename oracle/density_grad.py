@@ -8,7 +8,9 @@ from the overlapped bins in the backward phase of Sec. IV-A):
 Reading of the sign: the paper names q_i E_i both the force and the gradient; the force is
 +q_i E_i, so the gradient is its negative, and gradient descent spreads the charges.  For macros
 the change of size with z is ignored here (force = charge x field).  This is not the derivative
-of any discrete objective: parity unpinned beyond the properties its tests check.
+of any discrete objective; its tests pin it by closed forms (a uniform field gives the charge
+times the field; a bin-centred cell gathers its bins with overlaps worked by hand) and by its
+properties (mirror symmetry, convergence to the exact adjoint under refinement).
 
 Exact adjoint (the differentiation form): sum_b g_b d rho_b / d v_i for a map g, including the
 z-dependence of the macro size transition and of the local-smoothness weight.  With

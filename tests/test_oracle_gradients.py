@@ -100,6 +100,75 @@ def test_field_gather_mirror_symmetry():
     np.testing.assert_allclose(out[1][1:], out[0][1:], atol=1e-9 * np.abs(out[0]).max())
 
 
+def _cell_die_size(c, i, z, dz):
+    """A standard cell's (w, h) on the die its z puts it on (top above the mid-plane)."""
+    top = z > 0.5 * dz
+    return (float(c.size[2, i]), float(c.size[3, i])) if top else (float(c.size[0, i]), float(c.size[1, i]))
+
+
+def test_field_gather_of_a_constant_field_is_the_charge_times_the_field():
+    """Closed form of -omega sum_b vol(D ∩ b) E_b under a uniform field E = (c_x, c_y, c_z): for an
+    instance whose stretched footprint lies inside the die, omega times the stretched volume is the
+    true volume w h d_z/2, so the gather is -(w h d_z / 2) c per axis.  A lost omega, a dropped
+    depth factor, an overlap that does not sum to the box, or swapped field axes fails it."""
+    c = _case(31, nz=4)
+    geo = geometry_of(c)
+    shape = (geo.nz, geo.ny, geo.nx)
+    cx, cy, cz = 0.7, -1.9, 2.6
+    v = c.xyz0.astype(np.float64)
+    g = dg.field_gather(c.size, c.kind, v, np.full(shape, cx), np.full(shape, cy), np.full(shape, cz), geo)
+    r2 = np.sqrt(2.0)
+    checked = 0
+    for i in range(c.meta["n_cells"]):
+        if c.kind[i] & 2:
+            continue
+        w, h = _cell_die_size(c, i, v[2, i], geo.dz)
+        hw, hh = 0.5 * max(w, r2 * geo.wb), 0.5 * max(h, r2 * geo.hb)
+        if not (hw <= v[0, i] <= geo.die_x - hw and hh <= v[1, i] <= geo.die_y - hh):
+            continue
+        q = w * h * 0.5 * geo.dz
+        np.testing.assert_allclose(g[:, i], [-q * cx, -q * cy, -q * cz], rtol=1e-12)
+        checked += 1
+    assert checked >= 100
+
+
+def test_field_gather_of_a_bin_centred_cell_weights_its_bins_by_hand():
+    """A cell smaller than sqrt2 bins, centred in bin (b_x, b_y) at z = d_z/4 (or 3 d_z/4), has the
+    stretched footprint [centre -+ bin/sqrt2] per planar axis: the whole centre bin and
+    (sqrt2 - 1)/2 of each neighbour, and the full depth of z-bins 0 and 1 (2 and 3), N_z = 4.  With
+    a random field the gather is -omega sum of those overlap volumes times E, omega =
+    w h / (2 w_b h_b).  A transposed map index, a wrong z-bin or stretch fails it."""
+    c = _case(32, nz=4)
+    geo = geometry_of(c)
+    rng = np.random.default_rng(8)
+    shape = (geo.nz, geo.ny, geo.nx)
+    fields = [rng.normal(size=shape) for _ in range(3)]
+    v = c.xyz0.astype(np.float64)
+    cells = [i for i in range(c.meta["n_cells"]) if not c.kind[i] & 2][:40]
+    place = {}
+    for k, i in enumerate(cells):
+        bx, by = 1 + rng.integers(geo.nx - 2), 1 + rng.integers(geo.ny - 2)
+        top = k % 2 == 1
+        v[0, i], v[1, i] = (bx + 0.5) * geo.wb, (by + 0.5) * geo.hb
+        v[2, i] = (0.75 if top else 0.25) * geo.dz
+        place[i] = (bx, by, (2, 3) if top else (0, 1))
+    g = dg.field_gather(c.size, c.kind, v, *fields, geo)
+    side = 0.5 * (np.sqrt(2.0) - 1.0)
+    wx = {-1: side * geo.wb, 0: geo.wb, 1: side * geo.wb}
+    wy = {-1: side * geo.hb, 0: geo.hb, 1: side * geo.hb}
+    for i, (bx, by, zbins) in place.items():
+        w, h = _cell_die_size(c, i, v[2, i], geo.dz)
+        assert w < np.sqrt(2.0) * geo.wb and h < np.sqrt(2.0) * geo.hb
+        omega = (w / (np.sqrt(2.0) * geo.wb)) * (h / (np.sqrt(2.0) * geo.hb))
+        for a in range(3):
+            want = 0.0
+            for ox in (-1, 0, 1):
+                for oy in (-1, 0, 1):
+                    for zb in zbins:
+                        want += wx[ox] * wy[oy] * geo.db * fields[a][zb, by + oy, bx + ox]
+            assert abs(g[a, i] - (-omega * want)) <= 1e-12 * max(1.0, abs(omega * want)), (i, a, g[a, i], -omega * want)
+
+
 def test_preconditioner_follows_mixed_size_rule():
     c = _case(2)
     pb = opt.problem_of(c)
