@@ -2,7 +2,7 @@
 form the benchmark times -- split-bf16 and float32 contractions, compensated and plain
 exponential sums, field-gather and exact-adjoint density gradients -- launched exactly as
 place3d_step launches them (folded contractions, the net schedule and the tile bucketing of that
-size); and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
+size), the wirelength sweep also on the no-locality netlist of that size; and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
 density map, the split-bf16 spectral solve and the wirelength sweep.  Every output is compared in full against the oracle on the
 same seeded inputs, with the tolerances of the small-case parity tests:
   density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
@@ -102,20 +102,18 @@ def wl_ref(full):
     return owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
 
 
-@pytest.mark.parametrize("precision", PRECISIONS)
-def test_wirelength_full(full, wl_ref, precision):
-    case, probs, geo, rho = full
-    g, met = probs[precision].wl_grad(case.xyz0)
+def _check_wirelength(case, geo, prob, ref, tag):
+    """The sweep's totals, #cut, WA x/y gradient and FDA z-gradient against the oracle's."""
+    g, met = prob.wl_grad(case.xyz0)
     g = g.cpu().numpy()
     met = met.cpu().numpy()
-    ref = wl_ref
     for key, slot in (("wa_bi", 0), ("wa_z", 1), ("hpwl_d2d", 2), ("hpwl_3d", 3)):
         err = abs(met[slot] - ref[key]) / abs(ref[key])
-        log(f"[full] {precision} {key} gpu={met[slot]:.10g} ref={ref[key]:.10g} rel={err:.2e}")
+        log(f"[full] {tag} {key} gpu={met[slot]:.10g} ref={ref[key]:.10g} rel={err:.2e}")
         assert err <= 1e-5, key
     assert int(round(met[4])) == ref["ncut"]
     ex, ey = rel_l2(g[0], ref["grad_x"]), rel_l2(g[1], ref["grad_y"])
-    log(f"[full] {precision} wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
+    log(f"[full] {tag} wa grad rel_l2 x={ex:.3e} y={ey:.3e}")
     assert ex <= 1e-5 and ey <= 1e-5
     scale = met[8]
     assert abs(scale - ref["fda_scale"]) <= 1e-5 * ref["fda_scale"]
@@ -124,8 +122,36 @@ def test_wirelength_full(full, wl_ref, precision):
     want = scale * ref["fda"] + ref["grad_zwa"]
     bound = scale * 4.0 / geo.dz * npins * 8 * ulp + 1e-5 * np.abs(ref["grad_zwa"]).max() + 1e-6 * np.abs(want)
     diff = np.abs(g[2] - want)
-    log(f"[full] z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e}")
+    log(f"[full] {tag} z-grad max|diff|/bound={np.max(diff / np.maximum(bound, 1e-30)):.3e}")
     assert np.all(diff <= bound)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_wirelength_full(full, wl_ref, precision):
+    case, probs, geo, rho = full
+    _check_wirelength(case, geo, probs[precision], wl_ref, precision)
+
+
+@pytest.fixture(scope="module")
+def no_locality():
+    need_gpu()
+    log("[full] generating the no-locality 1.2M-cell netlist; oracle wirelength")
+    case = synth.make_case("c4u", 2403)
+    geo = geometry_of(case)
+    pb = oracle_problem(case)
+    ref = owl.wirelength(pb.size, pb.kind, case.xyz0, pb.net_start, pb.pin2node, pb.pin_off, geo, pb.gamma, pb.alpha)
+    return case, geo, ref
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_wirelength_no_locality_netlist(no_locality, precision):
+    """The 1.2M-cell workload with every net drawing its members uniformly over the instances (no
+    index window): the sweep's owner gathers touch a different cache line per pin."""
+    from paper_2403_09070_amd import place3d
+    case, geo, ref = no_locality
+    prob = gpu_problem(case, precision=place3d.BF16X3 if precision == "bf16x3" else place3d.FP32,
+                       dgrad=place3d.DGRAD_FIELD)
+    _check_wirelength(case, geo, prob, ref, "c4u " + precision)
 
 
 def test_density_vjp_full(full):
