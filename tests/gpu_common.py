@@ -60,6 +60,27 @@ def oracle_problem(case):
     return opt.problem_of(case)
 
 
+def load_state(prob, ref):
+    """A GPU state holding the oracle state's arrays (float32) and its a and lambda."""
+    import torch
+    from paper_2403_09070_amd import place3d
+    st = prob.new_state()
+    for name in ("u", "v", "v_prev", "g_prev"):
+        getattr(st, name).copy_(torch.from_numpy(np.asarray(getattr(ref, name), dtype=np.float32)))
+    sc = np.zeros(place3d.NSCALARS)
+    sc[place3d.S["a"]] = ref.a
+    sc[place3d.S["lam"]] = ref.lam
+    st.scalars.copy_(torch.from_numpy(sc))
+    return st
+
+
+def round_state(ref):
+    """The oracle state's arrays rounded to float32 (both sides then start from the same values)."""
+    for name in ("u", "v", "v_prev", "g_prev"):
+        setattr(ref, name, np.asarray(getattr(ref, name), dtype=np.float32).astype(np.float64))
+    return ref
+
+
 def log(msg):
     print(msg, flush=True)
 

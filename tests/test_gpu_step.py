@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import gpu_problem, log, need_gpu, oracle_problem, ragged_case, rel_l2, tiny_case
+from gpu_common import (gpu_problem, load_state, log, need_gpu, oracle_problem, ragged_case, rel_l2, round_state,
+                        tiny_case)
 from oracle import optimizer as opt
 from paper_2403_09070_amd import place3d, synth
 
@@ -68,23 +69,6 @@ def test_gp_init(which, form):
     assert err <= 1e-4
 
 
-def _load_state(prob, ref):
-    st = prob.new_state()
-    for name in ("u", "v", "v_prev", "g_prev"):
-        getattr(st, name).copy_(torch.from_numpy(np.asarray(getattr(ref, name), dtype=np.float32)))
-    sc = np.zeros(place3d.NSCALARS)
-    sc[place3d.S["a"]] = ref.a
-    sc[place3d.S["lam"]] = ref.lam
-    st.scalars.copy_(torch.from_numpy(sc))
-    return st
-
-
-def _round_state(ref):
-    for name in ("u", "v", "v_prev", "g_prev"):
-        setattr(ref, name, np.asarray(getattr(ref, name), dtype=np.float32).astype(np.float64))
-    return ref
-
-
 @pytest.mark.parametrize("form", list(FORMS))
 def test_one_step_from_the_same_state(form):
     need_gpu()
@@ -95,8 +79,8 @@ def test_one_step_from_the_same_state(form):
     ref = opt.gp_init(pb, case.xyz0, dgrad=_oracle_form(form), precond=_oracle_precond(form))
     for _ in range(3):                                   # move away from the bootstrap point
         opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
-    ref = _round_state(ref)
-    st = _load_state(prob, ref)
+    ref = round_state(ref)
+    st = load_state(prob, ref)
     v0 = ref.v.copy()
     prob.step(st)
     m = opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
@@ -185,8 +169,8 @@ def test_fillers_one_step_from_the_same_state():
     ref = opt.gp_init(pb, case.xyz0)
     for _ in range(3):
         opt.gp_step(pb, ref)
-    ref = _round_state(ref)
-    st = _load_state(prob, ref)
+    ref = round_state(ref)
+    st = load_state(prob, ref)
     v0 = ref.v.copy()
     prob.step(st)
     m = opt.gp_step(pb, ref)
@@ -258,8 +242,8 @@ def test_init_and_one_step_with_eight_layers(form):
     assert rel_l2(st.g_prev.cpu().numpy(), ref.g_prev) <= 1e-4
     for _ in range(3):
         opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
-    ref = _round_state(ref)
-    st = _load_state(prob, ref)
+    ref = round_state(ref)
+    st = load_state(prob, ref)
     v0 = ref.v.copy()
     prob.step(st)
     m = opt.gp_step(pb, ref, dgrad=_oracle_form(form), precond=_oracle_precond(form))
