@@ -2,8 +2,8 @@
 form the benchmark times -- split-bf16 and float32 contractions, compensated and plain
 exponential sums, field-gather and exact-adjoint density gradients -- launched exactly as
 place3d_step launches them (folded contractions, the net schedule and the tile bucketing of that
-size), the wirelength sweep also on the no-locality netlist of that size, and one whole step of the
-benchmark's form from the same state on both sides; and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
+size), the wirelength sweep also on the no-locality netlist of that size, and one whole step of each
+form the benchmark times from the same state on both sides; and at the largest workload (4M cells, 15M pins, grid 2048 x 2048 x 4, clustered start) the
 density map, the split-bf16 spectral solve and the wirelength sweep.  Every output is compared in full against the oracle on the
 same seeded inputs, with the tolerances of the small-case parity tests:
   density map rel L2 <= 1e-6 (at the generated placement and at a clustered one, where bins hold
@@ -155,9 +155,17 @@ def test_wirelength_no_locality_netlist(no_locality, precision):
     _check_wirelength(case, geo, prob, ref, "c4u " + precision)
 
 
-def test_one_step_at_full_size(full):
-    """One step of the benchmark's form (split-bf16 contractions, compensated exp-sums, field
-    gather, Eq. improved-precond) at the 1.2M-cell workload, from the same state on both sides:
+# forms of the full-size step: (problem key or None for a context of its own, oracle density
+# gradient, displacement bar before the float32 floor -- the small workload's one-step bars)
+STEP_FORMS = {"field-bf16x3": ("bf16x3", "field", 5e-5), "field-fp32": ("fp32", "field", 2e-5),
+              "adjoint-bf16x3": (None, "adjoint", 3e-4)}
+
+
+@pytest.mark.parametrize("form", list(STEP_FORMS))
+def test_one_step_at_full_size(full, form):
+    """One step of each form the benchmark times (split-bf16 or float32 contractions, compensated or
+    plain exp-sums, field gather or exact adjoint, Eq. improved-precond) at the 1.2M-cell
+    workload, from the same state on both sides:
     v the clamped start, u and v_prev seeded perturbations of it (half a bin in x and y, 2 % of
     the die depth in z), g_prev zero, a = 2.5 (the momentum term active), lambda the ratio of the
     gradients' L1 norms at v.  The metrics at v, the step size and the new iterate against the
@@ -165,8 +173,10 @@ def test_one_step_at_full_size(full):
     plus twice the floor that rounding the new positions to float32 sets), and the new
     preconditioned gradient within 1e-4."""
     from oracle import optimizer as opt
+    from paper_2403_09070_amd import place3d
     case, probs, geo, rho = full
-    prob = probs["bf16x3"]
+    key, dgrad, bar = STEP_FORMS[form]
+    prob = probs[key] if key else gpu_problem(case, precision=place3d.BF16X3, dgrad=place3d.DGRAD_ADJOINT)
     pb = oracle_problem(case)
     mov = pb.movable
     rng = np.random.default_rng(17)
@@ -179,18 +189,18 @@ def test_one_step_at_full_size(full):
         return opt.clamp(pb, q)
 
     u, v_prev = near(v), near(v)
-    log("[full] oracle evaluation at v (lambda)")
-    wl, _, _, gd = opt.evaluate(pb, v, "field")
+    log(f"[full] {form}: oracle evaluation at v (lambda)")
+    wl, _, _, gd = opt.evaluate(pb, v, dgrad)
     lam = float(np.abs(wl["grad"][:, mov]).sum() / np.abs(gd[:, mov]).sum())
     ref = round_state(opt.GPState(u=u, v=v, v_prev=v_prev, g_prev=np.zeros_like(v), a=2.5, lam=lam))
     st = load_state(prob, ref)
     v0 = ref.v.copy()
     prob.step(st)
-    log("[full] oracle step")
-    m = opt.gp_step(pb, ref, dgrad="field", precond="mixed")
+    log(f"[full] {form}: oracle step")
+    m = opt.gp_step(pb, ref, dgrad=dgrad, precond="mixed")
     s = st.read()
-    for key, rkey in (("hpwl", "hpwl_d2d"), ("wa_bi", "wa_bi"), ("wa_z", "wa_z")):
-        assert abs(s[key] - m[rkey]) <= 1e-5 * abs(m[rkey]), key
+    for name, rkey in (("hpwl", "hpwl_d2d"), ("wa_bi", "wa_bi"), ("wa_z", "wa_z")):
+        assert abs(s[name] - m[rkey]) <= 1e-5 * abs(m[rkey]), name
     assert s["ncut"] == m["ncut"]
     assert abs(s["ovfl_bot"] - m["ovfl_bot"]) <= 1e-6 and abs(s["ovfl_top"] - m["ovfl_top"]) <= 1e-6
     assert abs(s["lam"] - ref.lam) <= 1e-12 * ref.lam
@@ -201,11 +211,13 @@ def test_one_step_at_full_size(full):
     # each, against the move, is a floor the displacement error cannot go below
     floor = float(np.linalg.norm(0.5 * np.spacing(ref.v.astype(np.float32)).astype(np.float64)) /
                   np.linalg.norm(ref.v - v0))
-    log(f"[full] one step: gradient rel_l2={gerr:.3e} step rel={step_err:.3e} displacement rel_l2={disp:.3e} "
+    log(f"[full] {form} one step: gradient rel_l2={gerr:.3e} step rel={step_err:.3e} displacement rel_l2={disp:.3e} "
         f"(float32 floor {floor:.2e}) ovfl {s['ovfl_bot']:.6f}/{s['ovfl_top']:.6f} "
         f"ref {m['ovfl_bot']:.6f}/{m['ovfl_top']:.6f}")
     assert gerr <= 1e-4
-    assert step_err <= 1e-5 and disp <= 5e-5 + 2.0 * floor
+    assert step_err <= 1e-5 and disp <= bar + 2.0 * floor
+    if dgrad == "adjoint":
+        assert abs(s["energy"] - m["energy"]) <= 1e-4 * abs(m["energy"])
 
 
 def test_density_vjp_full(full):
