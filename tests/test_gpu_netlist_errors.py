@@ -1,4 +1,5 @@
-"""place3d_create refuses a malformed netlist with PLACE3D_ERR_NETLIST.
+"""place3d_create refuses a malformed netlist with PLACE3D_ERR_NETLIST (and a filler that is
+also a macro with PLACE3D_ERR_ARG).
 
 The library reads the netlist back once at creation and checks it on the host before any kernel
 uses it: net_start must start at 0, end at n_pins and never decrease; every pin's owner must be
@@ -35,11 +36,20 @@ def _broken(case, what):
         owner = int(p2n[0])
         assert owner < case.meta["n_cells"]                  # a standard cell: not macro, not fixed
         c.kind[owner] = place3d.KIND_FILLER | place3d.KIND_ZFIXED
+    elif what == "filler_also_macro":
+        from paper_2403_09070_amd import place3d
+        pinless = np.setdiff1d(np.arange(case.meta["n_cells"]), p2n)
+        i = int(pinless[0]) if len(pinless) else 0
+        c.kind[i] = place3d.KIND_FILLER | place3d.KIND_MACRO
     return c
 
 
-@pytest.mark.parametrize("what", ["owner_past_end", "owner_negative", "net_start_decreasing", "net_start_short",
-                                  "filler_with_pin"])
+# the status each case must return (the kind rule is an argument error, the others netlist errors)
+EXPECT = {"owner_past_end": "ERR_NETLIST", "owner_negative": "ERR_NETLIST", "net_start_decreasing": "ERR_NETLIST",
+          "net_start_short": "ERR_NETLIST", "filler_with_pin": "ERR_NETLIST", "filler_also_macro": "ERR_ARG"}
+
+
+@pytest.mark.parametrize("what", list(EXPECT))
 def test_malformed_netlist_is_refused_at_create(what):
     need_gpu()
     from paper_2403_09070_amd import place3d
@@ -47,7 +57,7 @@ def test_malformed_netlist_is_refused_at_create(what):
     case = tiny_case(5)
     with pytest.raises(place3d.Place3dError) as e:
         gpu_problem(_broken(case, what))
-    assert place3d.STATUS.get(e.value.code) == "ERR_NETLIST", str(e.value)
+    assert place3d.STATUS.get(e.value.code) == EXPECT[what], str(e.value)
     # the library is left usable: the valid problem creates and evaluates
     import torch
     prob = gpu_problem(case)
