@@ -163,7 +163,8 @@ enum {
 typedef struct place3d_problem {
   int32_t n_inst;          /* instances: movable cells and macros, fixed instances           */
   int32_t n_pins;
-  int32_t n_nets;
+  int32_t n_nets;          /* each count at most 2^28 (PLACE3D_ERR_SIZE beyond): the kernels
+                              index [4][n] arrays with 32-bit integers                       */
   int32_t nx, ny, nz;      /* bin grid; nx, ny in [2, 8192]; nz even, in [2, 16]; and at most
                               40,704 density tiles (32 x 32 bins for nz <= 4; 16 x 16 for
                               nz = 16): e.g. 6400 x 6400 at nz = 4 (else PLACE3D_ERR_SIZE)       */

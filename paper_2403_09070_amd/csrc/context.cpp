@@ -33,6 +33,13 @@ int check_grid_fits(const place3d_problem& p, std::string& why);
 int check_problem(const place3d_problem* p, std::string& why) {
   if (!p) { why = "problem is NULL"; return PLACE3D_ERR_ARG; }
   if (p->n_inst < 1 || p->n_pins < 0 || p->n_nets < 0) { why = "n_inst < 1 or negative pin/net count"; return PLACE3D_ERR_SIZE; }
+  // the kernels index arrays of four rows per instance or pin ([4][n] sizes, offsets and
+  // per-(cell, tile) shares) with 32-bit integers
+  constexpr int32_t kMaxCount = 1 << 28;
+  if (p->n_inst > kMaxCount || p->n_pins > kMaxCount || p->n_nets > kMaxCount) {
+    why = "n_inst, n_pins and n_nets must not exceed 2^28";
+    return PLACE3D_ERR_SIZE;
+  }
   if (p->nx < 2 || p->ny < 2 || p->nx > 8192 || p->ny > 8192) { why = "nx, ny must lie in [2, 8192]"; return PLACE3D_ERR_SIZE; }
   if (p->nz < 2 || p->nz > p3d::kMaxNz || (p->nz & 1)) { why = "nz must be even and in [2, 16]"; return PLACE3D_ERR_SIZE; }
   if (!(p->die_x > 0) || !(p->die_y > 0) || !std::isfinite(p->die_x) || !std::isfinite(p->die_y)) { why = "die extent must be positive"; return PLACE3D_ERR_ARG; }

@@ -46,6 +46,7 @@ def _problem(**kw):
 
 @pytest.mark.parametrize("field,value,code", [
     ("nx", 1, -2), ("ny", 9000, -2), ("nz", 3, -2), ("nz", 18, -2), ("n_inst", 0, -2),
+    ("n_inst", 2**28 + 1, -2), ("n_pins", 2**28 + 1, -2), ("n_nets", 2**28 + 1, -2),
     ("gamma", 0.0, -1), ("die_x", -1.0, -1), ("precision", 7, -1), ("dgrad", 5, -1), ("precond", 9, -1), ("options", 4, -1),
     ("alpha", -1.0, -1), ("size", 0, -1), ("pin_off", 18, -1),
 ])
