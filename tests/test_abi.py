@@ -30,6 +30,22 @@ def test_header_declares_the_hot_path_calls():
         assert n in names
 
 
+@pytest.mark.parametrize("lang,std", [("c", "c99"), ("c++", "c++17")])
+def test_header_compiles_as_plain_c_and_cpp(tmp_path, lang, std):
+    """The boundary is a C ABI: the header must be includable from C99 (and C++) with no warnings."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / ("use_header.c" if lang == "c" else "use_header.cpp")
+    src.write_text('#include "place3d.h"\nint main(void) { place3d_problem p; place3d_state s; (void)p; (void)s; '
+                   'return PLACE3D_OK; }\n')
+    r = subprocess.run([cc, f"-std={std}", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.dirname(HEADER),
+                        "-c", str(src), "-o", str(tmp_path / "use_header.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_every_declared_symbol_is_exported(L):
     for n in declared():
         assert hasattr(L, n), n
